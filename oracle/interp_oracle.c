@@ -1,0 +1,185 @@
+/*
+ * interp_oracle.c -- plain FP64 CPU oracle for the multiple-resolution
+ * velocity transfer of sec. 3.4 (multi-resolution meshes for C and u):
+ * the staggered velocity of a coarse mesh, uniform and periodic in x and y
+ * and stretched between two walls in z, is interpolated to the faces of the
+ * fine uniform mesh on which C lives, with a tensor-product cubic Hermite
+ * interpolant using four source points per direction (64 in 3-D).
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load it; it shares no code with the GPU
+ * library.
+ *
+ * Readings where the paper is silent (listed in the design notes):
+ *   - The Hermite slopes are the chord slopes through the two neighbours,
+ *       m_i = (f_{i+1} - f_{i-1}) / (s_{i+1} - s_{i-1}),
+ *     so the four points are s_{i-1} .. s_{i+2} around the target interval
+ *     [s_i, s_{i+1}] (on a uniform axis this is the Catmull-Rom spline).
+ *   - Beyond a wall the source is continued by reflection: tangential
+ *     components (cell-centred in z) evenly, the wall-normal component
+ *     (on z faces, zero on the walls) oddly.
+ *   - The plain form is used: u, v and w are interpolated directly.  The
+ *     paper's solenoidal variant (interpolating gradients and integrating
+ *     from a reference plane) is not this function.
+ *
+ * Geometry (unit box):
+ *   coarse: ncx x ncy cells of width 1/ncx, 1/ncy; ncz cells between the
+ *           face positions zf[0] = 0 < zf[1] < ... < zf[ncz] = 1.
+ *   fine:   nfx x nfy x nfz cells of width 1/nfx, 1/nfy, 1/nfz.
+ *   u: x faces (periodic, n_x of them), y and z centres
+ *   v: y faces (periodic), x and z centres
+ *   w: z faces including both walls (n_z + 1), x and y centres
+ * Arrays are x-fastest, [z][y][x].
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+enum { AX_PERIODIC = 0, AX_WALL_EVEN = 1, AX_WALL_ODD = 2 };
+
+typedef struct {
+    int64_t n;          /* number of stored source points */
+    const double* s;    /* their coordinates, increasing */
+    double L;           /* period or wall-to-wall length (walls at 0 and L) */
+    int kind;
+} axis_t;
+
+/* Extended source sequence: coordinate of point m and the stored index and
+ * sign that give its value. */
+static double ext_coord(const axis_t* a, int64_t m, int64_t* idx, double* sign)
+{
+    int64_t n = a->n;
+    *sign = 1.0;
+    if (a->kind == AX_PERIODIC) {
+        int64_t q = m / n, r = m % n;
+        if (r < 0) { r += n; q -= 1; }
+        *idx = r;
+        return a->s[r] + (double)q * a->L;
+    }
+    if (a->kind == AX_WALL_EVEN) {
+        if (m < 0) { *idx = -1 - m; return -a->s[-1 - m]; }
+        if (m >= n) { *idx = 2 * n - 1 - m; return 2.0 * a->L - a->s[2 * n - 1 - m]; }
+        *idx = m;
+        return a->s[m];
+    }
+    /* odd reflection about the walls, which are the points 0 and n-1 */
+    if (m < 0) { *idx = -m; *sign = -1.0; return -a->s[-m]; }
+    if (m >= n) { *idx = 2 * n - 2 - m; *sign = -1.0; return 2.0 * a->L - a->s[2 * n - 2 - m]; }
+    *idx = m;
+    return a->s[m];
+}
+
+/* Four source indices and weights (sign of the reflection folded in) that
+ * interpolate the source at coordinate t. */
+void oracle_hermite_stencil(int64_t n, const double* s, double L, int kind, double t,
+                            int64_t idx[4], double wt[4])
+{
+    axis_t a = {n, s, L, kind};
+    int64_t i0, dummy;
+    double sg;
+    /* largest m with s_m <= t */
+    int64_t m = -2;
+    while (ext_coord(&a, m + 1, &dummy, &sg) <= t) ++m;
+    i0 = m;
+    double x[4], sgn[4];
+    int64_t id[4];
+    for (int p = 0; p < 4; ++p) x[p] = ext_coord(&a, i0 - 1 + p, &id[p], &sgn[p]);
+    /* x[1] <= t < x[2] */
+    double D = x[2] - x[1];
+    double tau = (t - x[1]) / D;
+    double h00 = 2 * tau * tau * tau - 3 * tau * tau + 1;
+    double h10 = tau * tau * tau - 2 * tau * tau + tau;
+    double h01 = -2 * tau * tau * tau + 3 * tau * tau;
+    double h11 = tau * tau * tau - tau * tau;
+    /* f(t) = h00 f1 + h10 D m1 + h01 f2 + h11 D m2,
+       m1 = (f2 - f0)/(x2 - x0),  m2 = (f3 - f1)/(x3 - x1) */
+    double g1 = D / (x[2] - x[0]);
+    double g2 = D / (x[3] - x[1]);
+    double w[4];
+    w[0] = -h10 * g1;
+    w[1] = h00 - h11 * g2;
+    w[2] = h01 + h10 * g1;
+    w[3] = h11 * g2;
+    for (int p = 0; p < 4; ++p) {
+        idx[p] = id[p];
+        wt[p] = w[p] * sgn[p];
+    }
+}
+
+/* Interpolate one component: source axes ax[3] (x, y, z), source array src
+ * of shape [ax[2].n][ax[1].n][ax[0].n]; targets t_x[nx], t_y[ny], t_z[nz];
+ * output dst [nz][ny][nx]. */
+static void interp_component(const axis_t ax[3], const double* src,
+                             int64_t nx, const double* tx, int64_t ny, const double* ty,
+                             int64_t nz, const double* tz, double* dst)
+{
+    /* the 1-D stencils of every target coordinate, computed once */
+    int64_t* ix = malloc(sizeof(int64_t) * 4 * nx);
+    int64_t* iy = malloc(sizeof(int64_t) * 4 * ny);
+    int64_t* iz = malloc(sizeof(int64_t) * 4 * nz);
+    double* wx = malloc(sizeof(double) * 4 * nx);
+    double* wy = malloc(sizeof(double) * 4 * ny);
+    double* wz = malloc(sizeof(double) * 4 * nz);
+    for (int64_t i = 0; i < nx; ++i)
+        oracle_hermite_stencil(ax[0].n, ax[0].s, ax[0].L, ax[0].kind, tx[i], ix + 4 * i, wx + 4 * i);
+    for (int64_t j = 0; j < ny; ++j)
+        oracle_hermite_stencil(ax[1].n, ax[1].s, ax[1].L, ax[1].kind, ty[j], iy + 4 * j, wy + 4 * j);
+    for (int64_t k = 0; k < nz; ++k)
+        oracle_hermite_stencil(ax[2].n, ax[2].s, ax[2].L, ax[2].kind, tz[k], iz + 4 * k, wz + 4 * k);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                double acc = 0.0;
+                for (int c = 0; c < 4; ++c)
+                    for (int b = 0; b < 4; ++b)
+                        for (int a = 0; a < 4; ++a)
+                            acc += wz[4 * k + c] * wy[4 * j + b] * wx[4 * i + a]
+                                 * src[(iz[4 * k + c] * ax[1].n + iy[4 * j + b]) * ax[0].n
+                                       + ix[4 * i + a]];
+                dst[(k * ny + j) * nx + i] = acc;
+            }
+    free(ix); free(iy); free(iz); free(wx); free(wy); free(wz);
+}
+
+/* Coarse staggered velocity -> fine staggered velocity (sec. 3.4). */
+int oracle_interp_velocity(const int64_t nc[3], const double* zf, const double* uc,
+                           const double* vc, const double* wc, const int64_t nf[3],
+                           double* uf, double* vf, double* wf)
+{
+    int64_t ncx = nc[0], ncy = nc[1], ncz = nc[2];
+    int64_t nfx = nf[0], nfy = nf[1], nfz = nf[2];
+    double* cxf = malloc(sizeof(double) * ncx);   /* coarse x faces  */
+    double* cxc = malloc(sizeof(double) * ncx);   /* coarse x centres */
+    double* cyf = malloc(sizeof(double) * ncy);
+    double* cyc = malloc(sizeof(double) * ncy);
+    double* czc = malloc(sizeof(double) * ncz);   /* coarse z centres */
+    double* fxf = malloc(sizeof(double) * nfx);
+    double* fxc = malloc(sizeof(double) * nfx);
+    double* fyf = malloc(sizeof(double) * nfy);
+    double* fyc = malloc(sizeof(double) * nfy);
+    double* fzf = malloc(sizeof(double) * (nfz + 1));
+    double* fzc = malloc(sizeof(double) * nfz);
+    if (!cxf || !cxc || !cyf || !cyc || !czc || !fxf || !fxc || !fyf || !fyc || !fzf || !fzc)
+        return -1;
+    for (int64_t i = 0; i < ncx; ++i) { cxf[i] = (double)i / ncx; cxc[i] = (i + 0.5) / ncx; }
+    for (int64_t j = 0; j < ncy; ++j) { cyf[j] = (double)j / ncy; cyc[j] = (j + 0.5) / ncy; }
+    for (int64_t k = 0; k < ncz; ++k) czc[k] = 0.5 * (zf[k] + zf[k + 1]);
+    for (int64_t i = 0; i < nfx; ++i) { fxf[i] = (double)i / nfx; fxc[i] = (i + 0.5) / nfx; }
+    for (int64_t j = 0; j < nfy; ++j) { fyf[j] = (double)j / nfy; fyc[j] = (j + 0.5) / nfy; }
+    for (int64_t k = 0; k <= nfz; ++k) fzf[k] = (double)k / nfz;
+    for (int64_t k = 0; k < nfz; ++k) fzc[k] = (k + 0.5) / nfz;
+
+    axis_t au[3] = {{ncx, cxf, 1.0, AX_PERIODIC}, {ncy, cyc, 1.0, AX_PERIODIC},
+                    {ncz, czc, 1.0, AX_WALL_EVEN}};
+    axis_t av[3] = {{ncx, cxc, 1.0, AX_PERIODIC}, {ncy, cyf, 1.0, AX_PERIODIC},
+                    {ncz, czc, 1.0, AX_WALL_EVEN}};
+    axis_t aw[3] = {{ncx, cxc, 1.0, AX_PERIODIC}, {ncy, cyc, 1.0, AX_PERIODIC},
+                    {ncz + 1, zf, 1.0, AX_WALL_ODD}};
+    interp_component(au, uc, nfx, fxf, nfy, fyc, nfz, fzc, uf);
+    interp_component(av, vc, nfx, fxc, nfy, fyf, nfz, fzc, vf);
+    interp_component(aw, wc, nfx, fxc, nfy, fyc, nfz + 1, fzf, wf);
+    free(cxf); free(cxc); free(cyf); free(cyc); free(czc);
+    free(fxf); free(fxc); free(fyf); free(fyc); free(fzf); free(fzc);
+    return 0;
+}

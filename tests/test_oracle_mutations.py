@@ -1,0 +1,82 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle's C source (on the CPU,
+in a temporary directory), builds it, and runs the pin tests against that
+copy; at least one pin must fail.  The unmodified copy must pass.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE = os.path.join(ROOT, "oracle")
+PINS = ["tests/test_oracle_pins.py", "tests/test_interp_oracle.py"]
+
+# (name, file, original text, planted mistake)
+MUTATIONS = [
+    ("weno-smoothness-coefficient", "ch_oracle.c",
+     "double s0 = 13.0 / 12.0 * (a - 2.0 * b + c)", "double s0 = 12.0 / 12.0 * (a - 2.0 * b + c)"),
+    ("weno-linear-weight", "ch_oracle.c",
+     "double w1 = 0.6 /", "double w1 = 0.5 /"),
+    ("weno-candidate", "ch_oracle.c",
+     "double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;", "double q1 = (-b + 5.0 * c + 2.0 * d) / 6.5;"),
+    ("upwind-side", "ch_oracle.c",
+     "if (U >= 0.0) return oracle_weno5", "if (U <= 0.0) return oracle_weno5"),
+    ("advection-sign", "ch_oracle.c",
+     "E[p] = -adv[p] + lap[p] / Pe", "E[p] = adv[p] + lap[p] / Pe"),
+    ("laplacian-scale", "ch_oracle.c",
+     "s += (mp - 2.0 * mu0 + mm) / (h * h);", "s += (mp - 2.0 * mu0 + mm) / (h);"),
+    ("biharmonic-centre", "ch_oracle.c",
+     "const double row[5] = {1.0, -4.0, 6.0, -4.0, 1.0};\n    double scale = kappa",
+     "const double row[5] = {1.0, -4.0, 5.0, -4.0, 1.0};\n    double scale = kappa"),
+    ("cn-half-factor", "ch_oracle.c",
+     "(2.0 * Pe * h * h * h * h)", "(1.0 * Pe * h * h * h * h)"),
+    ("rk3-constant", "ch_oracle.c",
+     "-17.0 / 60.0", "-15.0 / 60.0"),
+    ("rk3-history", "ch_oracle.c",
+     "RK_RHO[k] * Eold[p])", "RK_RHO[k] * E[p])"),
+    ("noflux-reflection", "ch_oracle.c",
+     "return m < n ? m : p - 1 - m;", "return m < n ? m : p - 2 - m;"),
+    ("periodic-corner", "ch_oracle.c",
+     "s->V[(size_t)c * n + col] += val;", "s->V[(size_t)c * n + col] += 0.5 * val;"),
+    ("mass-volume", "ch_oracle.c",
+     "return h * h * h * pairwise_sum(C, count);", "return h * h * pairwise_sum(C, count);"),
+    ("hermite-slope", "interp_oracle.c",
+     "double g1 = D / (x[2] - x[0]);", "double g1 = D / (x[2] - x[1]);"),
+    ("odd-reflection", "interp_oracle.c",
+     "if (m < 0) { *idx = -m; *sign = -1.0;", "if (m < 0) { *idx = -m; *sign = 1.0;"),
+]
+
+
+def _build_and_run(tmp, edits):
+    srcs = []
+    for name in ("ch_oracle.c", "interp_oracle.c"):
+        text = open(os.path.join(ORACLE, name)).read()
+        for fname, old, new in edits:
+            if fname == name:
+                assert text.count(old) >= 1, old
+                text = text.replace(old, new, 1)
+        path = os.path.join(tmp, name)
+        open(path, "w").write(text)
+        srcs.append(path)
+    so = os.path.join(tmp, "liboracle.so")
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", so]
+                   + srcs + ["-lm"], check=True)
+    env = dict(os.environ, CH_ORACLE_LIB=so, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"]
+                       + PINS, cwd=ROOT, env=env, capture_output=True, text=True)
+    return r.returncode
+
+
+def test_unmodified_copy_passes():
+    with tempfile.TemporaryDirectory() as tmp:
+        assert _build_and_run(tmp, []) == 0
+
+
+@pytest.mark.parametrize("name,fname,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(name, fname, old, new):
+    with tempfile.TemporaryDirectory() as tmp:
+        assert _build_and_run(tmp, [(fname, old, new)]) != 0, name
