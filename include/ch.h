@@ -1,0 +1,217 @@
+/*
+ * ch.h -- C ABI of libch: the Cahn-Hilliard scalar update of the phase-field
+ * method of Liu, Ng, Chong, Lohse & Verzicco (arXiv 2105.01865) on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * One step advances the volume fraction C of eq-ch (sec. 2.1),
+ *
+ *   dC/dt + div(u C) = (1/Pe) [ -Cn^2 lap^2 C + lap psi'(C) ],
+ *
+ * on a uniform cell-centred mesh of spacing h with a prescribed staggered
+ * face velocity (u, v, w), using
+ *   - fifth-order WENO face values for the conservative advection flux
+ *     (sec. 3),
+ *   - the central 7-point Laplacian of psi'(C) (sec. 3),
+ *   - the new biharmonic scheme of sec. 3.1 without mixed derivatives,
+ *     sum_d A_d C with A_d = kappa Cn^2/h^4 (1,-4,6,-4,1)_d (eq-divbi,
+ *     eq-a3d; kappa = 4 as printed for 3-D),
+ *   - a low-storage third-order Runge-Kutta scheme with Crank-Nicolson on
+ *     the biharmonic term in delta form (eq-re), approximately factorised
+ *     (eq-fac) into three pentadiagonal line solves along x, y, z
+ *     (eq-fac-1 .. eq-fac-3).
+ *
+ * RK3 substage k = 1, 2, 3 with gamma = (8/15, 5/12, 3/4), rho = (0, -17/60,
+ * -5/12), alpha = gamma + rho:
+ *   E_k   = -div(u C) + lap psi'(C) / Pe
+ *   rhs   = dt (gamma_k E_k + rho_k E_{k-1}) - alpha_k dt / Pe sum_d A_d C
+ *   (I + alpha_k dt/(2 Pe) A_x)(I + alpha_k dt/(2 Pe) A_y)
+ *       (I + alpha_k dt/(2 Pe) A_z) dC = rhs ;   C += dC
+ *
+ * Memory: every field is x-fastest, C[z][y][x].  Face i along an axis is the
+ * low face of cell i.  A periodic axis of n cells has n faces along it (face
+ * n is face 0); a no-flux axis has n + 1 (the first and last are the walls,
+ * where the normal velocity must be zero).  So u is [nz][ny][fx],
+ * v is [nz][fy][nx], w is [fz][ny][nx] with f = n or n + 1.
+ *
+ * Precision: CH_FP64 stores and computes in double; CH_FP32 stores and
+ * computes C, E and the stencils in float, while the mass is always summed
+ * in double and the line-solve recurrences use double when the solve's
+ * diagonal dominance is weak (solve_fp64 = CH_SOLVE_AUTO) or always
+ * (CH_SOLVE_FP64).
+ *
+ * Streams: all work is enqueued on the state's HIP stream (default: the
+ * null stream); calls return once the work is enqueued, except ch_mass,
+ * ch_get_field and ch_batch_mass, which wait for it.
+ *
+ * Errors: every call returns a ch_status; ch_last_error() gives a
+ * thread-local message for the last failure.  Handles are checked: a call on
+ * a destroyed or foreign handle returns CH_EHANDLE.
+ */
+#ifndef CH_H
+#define CH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CH_OK = 0,
+    CH_EINVAL = -1,        /* invalid argument */
+    CH_ENOMEM = -2,        /* device or host allocation failed */
+    CH_EHIP = -3,          /* a HIP runtime call failed */
+    CH_EUNSUPPORTED = -4,  /* valid request this build does not support */
+    CH_ENONFINITE = -5,    /* NaN or Inf found by a checking call */
+    CH_EHANDLE = -6        /* handle not live (destroyed or never created) */
+} ch_status;
+
+enum { CH_PERIODIC = 0, CH_NOFLUX = 1 };
+enum { CH_FP64 = 0, CH_FP32 = 1 };
+enum { CH_SOLVE_AUTO = 0, CH_SOLVE_FP64 = 1, CH_SOLVE_NATIVE = 2 };
+
+/* Uniform mesh: n_x x n_y x n_z cells of width h (sec. 3: uniform h in all
+ * three directions for C).  Each n is 1 (a degenerate axis: no variation,
+ * no flux, the solve along it is the identity) or at least 8. */
+typedef struct {
+    int64_t nx, ny, nz;
+    double h;
+} ch_grid;
+
+/* psi'(C) = c[0] + c[1] C + c[2] C^2 + c[3] C^3; the double well of eq-ch,
+ * psi = C^2 (C-1)^2 / 4, is {0, 0.5, -1.5, 1}. */
+typedef struct {
+    double c[4];
+} ch_psi;
+
+/* Boundary per axis: CH_PERIODIC, or CH_NOFLUX (even reflection of C across
+ * the wall and zero normal velocity on it; the paper leaves the first and
+ * last operator rows to the boundary condition, after eq-a2d). */
+typedef struct {
+    int x, y, z;
+} ch_bc;
+
+typedef struct {
+    int precision;      /* CH_FP64 (default) or CH_FP32 */
+    double kappa;       /* weight of the per-direction fourth difference; 4 */
+    double weno_eps;    /* WENO regularisation; 1e-6 */
+    int solve_fp64;     /* CH_SOLVE_AUTO (default), CH_SOLVE_FP64, CH_SOLVE_NATIVE */
+    int use_graph;      /* 1 (default): replay each step as one HIP graph */
+    int x_rows;         /* rows per x-pass work-group; 0 = automatic */
+    int seg_len;        /* y/z line segment per work-group; 0 = automatic */
+    int waves_yz;       /* waves per y/z work-group (1..8); 0 = automatic */
+} ch_opts;
+
+typedef struct ch_state ch_state;
+typedef struct ch_batch ch_batch;
+typedef struct ch_interp ch_interp;
+
+/* Fill *opt with the defaults above. */
+void ch_default_opts(ch_opts* opt);
+
+/* Create a single-box state.  Cn, Pe > 0 (eq-ch); psi NULL = double well;
+ * bc NULL = periodic everywhere; opt NULL = defaults.  The state owns C, the
+ * explicit-term history E and two line-solve buffers on the current device.
+ * C starts at zero.  Errors: CH_EINVAL (bad sizes, h, Cn, Pe, kappa, eps),
+ * CH_ENOMEM, CH_EHIP. */
+ch_status ch_create(const ch_grid* g, double Cn, double Pe, const ch_psi* psi,
+                    const ch_bc* bc, const ch_opts* opt, ch_state** out);
+
+/* Use the given HIP stream (hipStream_t; NULL = null stream) for all work. */
+ch_status ch_set_stream(ch_state* s, void* stream);
+
+/* Copy C in / out: nx*ny*nz values in the state's precision, x fastest.
+ * on_device = 1: C is device memory; 0: host memory.  ch_get_field waits for
+ * the copy. */
+ch_status ch_set_field(ch_state* s, const void* C, int on_device);
+ch_status ch_get_field(ch_state* s, void* C, int on_device);
+
+/* Enqueue nsteps RK3 steps with the frozen face velocity (u, v, w): borrowed
+ * device pointers in the state's precision with the shapes given above; the
+ * caller keeps them alive until the stream has passed the work.  dt > 0 and
+ * finite, nsteps >= 0.  Errors: CH_EINVAL, CH_EHIP, CH_EHANDLE. */
+ch_status ch_step(ch_state* s, const void* u, const void* v, const void* w,
+                  double dt, int nsteps);
+
+/* Mass h^3 sum C in double, summed in a fixed order (the quantity behind
+ * the mass-loss measure of sec. 4.3.1).  Waits for the stream. */
+ch_status ch_mass(ch_state* s, double* out);
+
+/* Check the velocity: finite everywhere and zero on no-flux walls.  Waits.
+ * Returns CH_OK, CH_ENONFINITE or CH_EINVAL. */
+ch_status ch_check_velocity(ch_state* s, const void* u, const void* v, const void* w);
+
+/* Free everything the state owns.  NULL is accepted. */
+void ch_destroy(ch_state* s);
+
+/* Thread-local message of the last failed call ("" if none). */
+const char* ch_last_error(void);
+
+/* ---- batched ensemble: independent boxes advanced together -------------
+ * Box b has grid g[b], Cn[b], Pe[b], psi[b] (NULL = double well for all),
+ * bc[b] (NULL = periodic for all); opt applies to all boxes.  Fields are
+ * packed: box b's C starts at element c_off[b] of the packed array, its
+ * u, v, w at u_off[b], v_off[b], w_off[b] of theirs (see
+ * ch_batch_field_offsets).  One step of all boxes is one HIP graph launch. */
+ch_status ch_batch_create(int nbox, const ch_grid* g, const double* Cn, const double* Pe,
+                          const ch_psi* psi, const ch_bc* bc, const ch_opts* opt,
+                          ch_batch** out);
+/* Offsets (elements) of each box in the packed C, u, v, w arrays, and the
+ * four packed lengths in totals[4]; any pointer may be NULL. */
+ch_status ch_batch_field_offsets(const ch_batch* b, int64_t* c_off, int64_t* u_off,
+                                 int64_t* v_off, int64_t* w_off, int64_t totals[4]);
+ch_status ch_batch_set_stream(ch_batch* b, void* stream);
+ch_status ch_batch_set_field(ch_batch* b, const void* C_packed, int on_device);
+ch_status ch_batch_get_field(ch_batch* b, void* C_packed, int on_device);
+ch_status ch_batch_step(ch_batch* b, const void* u_packed, const void* v_packed,
+                        const void* w_packed, double dt, int nsteps);
+/* Per-box mass h_b^3 sum C_b into out[nbox]; waits. */
+ch_status ch_batch_mass(ch_batch* b, double* out);
+void ch_batch_destroy(ch_batch* b);
+
+/* ---- multiple-resolution velocity (sec. 3.4) -----------------------------
+ * The velocity lives on a coarse mesh, ncx x ncy cells uniform and periodic
+ * in x and y, ncz cells between walls at z = 0 and 1 with face positions
+ * zf[0..ncz] (host array, increasing, zf[0] = 0, zf[ncz] = 1); it is
+ * transferred to the faces of the fine uniform mesh of `fine` (periodic x,
+ * y; no-flux z) by tensor-product cubic Hermite interpolation with four
+ * points per direction (slopes: chord through the two neighbours; beyond a
+ * wall the tangential components continue evenly, the normal one oddly).
+ * The 1-D stencils are built once at creation.  Coarse arrays: uc, vc
+ * [ncz][ncy][ncx], wc [ncz+1][ncy][ncx]; fine: u, v [nz][ny][nx],
+ * w [nz+1][ny][nx]; all device memory in the given precision. */
+ch_status ch_interp_create(const ch_grid* fine, int64_t ncx, int64_t ncy, int64_t ncz,
+                           const double* zf, int precision, ch_interp** out);
+ch_status ch_interp_set_stream(ch_interp* ip, void* stream);
+ch_status ch_interp_apply(ch_interp* ip, const void* uc, const void* vc, const void* wc,
+                          void* u, void* v, void* w);
+void ch_interp_destroy(ch_interp* ip);
+
+/* nsteps steps where every step first transfers the coarse velocity to the
+ * fine faces (into buffers the state allocates on first use) and then
+ * advances C by one RK3 step. */
+ch_status ch_step_multires(ch_state* s, ch_interp* ip, const void* uc, const void* vc,
+                           const void* wc, double dt, int nsteps);
+
+/* ---- measurement ---------------------------------------------------------
+ * With profiling on, ch_step / ch_batch_step launch kernels one by one
+ * (no graph) and time each launch with HIP events on the state's stream.
+ * ch_profile_read returns, for kernel class k (0 = x pass: RHS + x solve,
+ * 1 = y solve, 2 = z solve + update, 3 = velocity transfer), the summed
+ * milliseconds and the launch count since profiling was switched on.  It
+ * waits for the stream. */
+ch_status ch_profile_enable(ch_state* s, int on);
+ch_status ch_profile_read(ch_state* s, int kernel, double* total_ms, int64_t* launches);
+ch_status ch_batch_profile_enable(ch_batch* b, int on);
+ch_status ch_batch_profile_read(ch_batch* b, int kernel, double* total_ms, int64_t* launches);
+
+/* Launch configuration the library chose (or was given) for the state:
+ * cfg[0] = x rows per work-group, cfg[1] = y/z segment, cfg[2] = waves per
+ * y/z work-group, cfg[3..5] = warm-up length of the line recurrences in
+ * substages 1..3 for the first box, cfg[6] = 1 if the solves run in double. */
+ch_status ch_get_config(const ch_state* s, int cfg[7]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CH_H */

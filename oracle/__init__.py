@@ -57,6 +57,8 @@ def lib():
         L.oracle_step_explicit25.argtypes = [_I64, _INT, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, _D, ctypes.c_double, _D,
                                              _D, _D, _D, ctypes.c_double, ctypes.c_int]
+        L.oracle_threads.restype = ctypes.c_int
+        L.oracle_threads.argtypes = []
         L.oracle_mass.restype = ctypes.c_double
         L.oracle_mass.argtypes = [ctypes.c_int64, ctypes.c_double, _D]
         L.oracle_hermite_stencil.argtypes = [ctypes.c_int64, _D, ctypes.c_double, ctypes.c_int,
@@ -181,6 +183,11 @@ def step_explicit25(C, u, v, w, h, Cn, Pe, dt, nsteps=1, bc=(0, 0, 0),
     if rc:
         raise RuntimeError("oracle_step_explicit25 failed")
     return C
+
+
+def threads():
+    """Threads the oracle's parallel loops use."""
+    return lib().oracle_threads()
 
 
 def mass(C, h):

@@ -48,6 +48,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_PERIODIC 0
 #define ORC_NOFLUX 1
@@ -572,4 +575,14 @@ static double pairwise_sum(const double* x, int64_t n)
 double oracle_mass(int64_t count, double h, const double* C)
 {
     return h * h * h * pairwise_sum(C, count);
+}
+
+/* Threads the oracle's parallel loops use. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -1,0 +1,423 @@
+"""Python binding of libch (include/ch.h): argument marshalling only.
+
+Every step of the Cahn-Hilliard update runs in the library's HIP kernels;
+this module checks shapes and dtypes on the host, passes raw device
+pointers of torch tensors, and orders the library's stream after torch's
+current stream (and back).  It raises if libch.so is not built -- there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libch.so")
+
+CH_PERIODIC, CH_NOFLUX = 0, 1
+CH_FP64, CH_FP32 = 0, 1
+SOLVE = {"auto": 0, "fp64": 1, "native": 2}
+STATUS = {0: "CH_OK", -1: "CH_EINVAL", -2: "CH_ENOMEM", -3: "CH_EHIP", -4: "CH_EUNSUPPORTED",
+          -5: "CH_ENONFINITE", -6: "CH_EHANDLE"}
+KERNELS = {"x": 0, "y": 1, "z": 2, "interp": 3}
+
+
+class CHError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("h", ctypes.c_double)]
+
+
+class Psi(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double * 4)]
+
+
+class BC(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_int), ("y", ctypes.c_int), ("z", ctypes.c_int)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("kappa", ctypes.c_double),
+                ("weno_eps", ctypes.c_double), ("solve_fp64", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("x_rows", ctypes.c_int),
+                ("seg_len", ctypes.c_int), ("waves_yz", ctypes.c_int)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_PD = ctypes.POINTER(ctypes.c_double)
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+
+# name -> (restype, argtypes); kept in the order of include/ch.h
+SIGNATURES = {
+    "ch_default_opts": (None, [ctypes.POINTER(Opts)]),
+    "ch_create": (_I, [ctypes.POINTER(Grid), _D, _D, ctypes.POINTER(Psi), ctypes.POINTER(BC),
+                       ctypes.POINTER(Opts), ctypes.POINTER(_VP)]),
+    "ch_set_stream": (_I, [_VP, _VP]),
+    "ch_set_field": (_I, [_VP, _VP, _I]),
+    "ch_get_field": (_I, [_VP, _VP, _I]),
+    "ch_step": (_I, [_VP, _VP, _VP, _VP, _D, _I]),
+    "ch_mass": (_I, [_VP, _PD]),
+    "ch_check_velocity": (_I, [_VP, _VP, _VP, _VP]),
+    "ch_destroy": (None, [_VP]),
+    "ch_last_error": (ctypes.c_char_p, []),
+    "ch_batch_create": (_I, [_I, ctypes.POINTER(Grid), _PD, _PD, ctypes.POINTER(Psi),
+                             ctypes.POINTER(BC), ctypes.POINTER(Opts), ctypes.POINTER(_VP)]),
+    "ch_batch_field_offsets": (_I, [_VP, _PI64, _PI64, _PI64, _PI64, _PI64]),
+    "ch_batch_set_stream": (_I, [_VP, _VP]),
+    "ch_batch_set_field": (_I, [_VP, _VP, _I]),
+    "ch_batch_get_field": (_I, [_VP, _VP, _I]),
+    "ch_batch_step": (_I, [_VP, _VP, _VP, _VP, _D, _I]),
+    "ch_batch_mass": (_I, [_VP, _PD]),
+    "ch_batch_destroy": (None, [_VP]),
+    "ch_interp_create": (_I, [ctypes.POINTER(Grid), ctypes.c_int64, ctypes.c_int64,
+                              ctypes.c_int64, _PD, _I, ctypes.POINTER(_VP)]),
+    "ch_interp_set_stream": (_I, [_VP, _VP]),
+    "ch_interp_apply": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "ch_interp_destroy": (None, [_VP]),
+    "ch_step_multires": (_I, [_VP, _VP, _VP, _VP, _VP, _D, _I]),
+    "ch_profile_enable": (_I, [_VP, _I]),
+    "ch_profile_read": (_I, [_VP, _I, _PD, _PI64]),
+    "ch_batch_profile_enable": (_I, [_VP, _I]),
+    "ch_batch_profile_read": (_I, [_VP, _I, _PD, _PI64]),
+    "ch_get_config": (_I, [_VP, ctypes.POINTER(ctypes.c_int)]),
+}
+
+
+def lib():
+    """Load libch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m "
+                               "paper_2105_01865_amd.build` (there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise CHError(status, lib().ch_last_error().decode())
+
+
+def _dtype(precision):
+    return torch.float64 if precision == CH_FP64 else torch.float32
+
+
+def _prec(p):
+    if p in ("fp64", "f64", CH_FP64, torch.float64):
+        return CH_FP64
+    if p in ("fp32", "f32", CH_FP32, torch.float32):
+        return CH_FP32
+    raise ValueError(f"unknown precision {p!r}")
+
+
+def make_opts(precision="fp64", kappa=4.0, weno_eps=1e-6, solve="auto", use_graph=True,
+              x_rows=0, seg_len=0, waves_yz=0):
+    o = Opts()
+    lib().ch_default_opts(ctypes.byref(o))
+    o.precision = _prec(precision)
+    o.kappa = kappa
+    o.weno_eps = weno_eps
+    o.solve_fp64 = SOLVE[solve]
+    o.use_graph = 1 if use_graph else 0
+    o.x_rows, o.seg_len, o.waves_yz = x_rows, seg_len, waves_yz
+    return o
+
+
+def _dev_tensor(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class _StreamMixin:
+    """Orders the library's stream after torch's current stream and back."""
+
+    def _enter(self):
+        if self.stream is not None:
+            self.stream.wait_stream(torch.cuda.current_stream())
+
+    def _leave(self):
+        if self.stream is not None:
+            torch.cuda.current_stream().wait_stream(self.stream)
+
+
+class State(_StreamMixin):
+    """One box: C of shape (nz, ny, nx) on the current device."""
+
+    def __init__(self, shape, h, Cn, Pe, psi=None, bc=(0, 0, 0), stream=None, **opts):
+        nz, ny, nx = shape
+        self.shape = (nz, ny, nx)
+        self.bc = tuple(int(b) for b in bc)
+        self.h = float(h)
+        self.opts = make_opts(**opts)
+        self.dtype = _dtype(self.opts.precision)
+        g = Grid(nx, ny, nz, h)
+        p = Psi((ctypes.c_double * 4)(*psi)) if psi is not None else None
+        b = BC(*self.bc)
+        handle = ctypes.c_void_p()
+        _check(lib().ch_create(ctypes.byref(g), Cn, Pe, ctypes.byref(p) if p else None,
+                               ctypes.byref(b), ctypes.byref(self.opts), ctypes.byref(handle)))
+        self._h = handle
+        self.stream = None
+        self.set_stream(stream)
+
+    # faces per axis
+    def vel_shapes(self):
+        nz, ny, nx = self.shape
+        fx = nx + (self.bc[0] == CH_NOFLUX)
+        fy = ny + (self.bc[1] == CH_NOFLUX)
+        fz = nz + (self.bc[2] == CH_NOFLUX)
+        return (nz, ny, fx), (nz, fy, nx), (fz, ny, nx)
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(lib().ch_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream if stream else 0)))
+
+    def set_field(self, C):
+        if isinstance(C, np.ndarray):
+            C = torch.from_numpy(np.ascontiguousarray(C)).to(device="cuda", dtype=self.dtype)
+        ptr = _dev_tensor(C, self.dtype, self.shape, "C")
+        self._enter()
+        _check(lib().ch_set_field(self._h, ptr, 1))
+        self._leave()
+        torch.cuda.current_stream().synchronize()
+
+    def get_field(self):
+        out = torch.empty(self.shape, dtype=self.dtype, device="cuda")
+        self._enter()
+        _check(lib().ch_get_field(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+        self._leave()
+        return out
+
+    def step(self, u, v, w, dt, nsteps=1):
+        su, sv, sw = self.vel_shapes()
+        pu = _dev_tensor(u, self.dtype, su, "u")
+        pv = _dev_tensor(v, self.dtype, sv, "v")
+        pw = _dev_tensor(w, self.dtype, sw, "w")
+        self._enter()
+        _check(lib().ch_step(self._h, pu, pv, pw, float(dt), int(nsteps)))
+        self._leave()
+
+    def step_multires(self, interp, uc, vc, wc, dt, nsteps=1):
+        self._enter()
+        _check(lib().ch_step_multires(self._h, interp._h, *interp._coarse_ptrs(uc, vc, wc),
+                                      float(dt), int(nsteps)))
+        self._leave()
+
+    def mass(self):
+        out = ctypes.c_double()
+        self._enter()
+        _check(lib().ch_mass(self._h, ctypes.byref(out)))
+        return out.value
+
+    def check_velocity(self, u, v, w):
+        su, sv, sw = self.vel_shapes()
+        self._enter()
+        _check(lib().ch_check_velocity(self._h, _dev_tensor(u, self.dtype, su, "u"),
+                                       _dev_tensor(v, self.dtype, sv, "v"),
+                                       _dev_tensor(w, self.dtype, sw, "w")))
+
+    def profile(self, on=True):
+        _check(lib().ch_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self, kernel):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().ch_profile_read(self._h, KERNELS.get(kernel, kernel), ctypes.byref(ms),
+                                     ctypes.byref(n)))
+        return ms.value, n.value
+
+    def config(self):
+        cfg = (ctypes.c_int * 7)()
+        _check(lib().ch_get_config(self._h, cfg))
+        return dict(x_rows=cfg[0], seg=cfg[1], chains=cfg[2], tw=list(cfg[3:6]),
+                    acc64=bool(cfg[6]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch(_StreamMixin):
+    """Independent boxes advanced together; fields are packed 1-D tensors."""
+
+    def __init__(self, shapes, hs, Cns, Pes, bcs=None, stream=None, **opts):
+        n = len(shapes)
+        self.shapes = [tuple(s) for s in shapes]
+        self.bcs = [tuple(b) for b in (bcs or [(0, 0, 0)] * n)]
+        self.opts = make_opts(**opts)
+        self.dtype = _dtype(self.opts.precision)
+        grids = (Grid * n)(*[Grid(s[2], s[1], s[0], h) for s, h in zip(self.shapes, hs)])
+        cn = (ctypes.c_double * n)(*Cns)
+        pe = (ctypes.c_double * n)(*Pes)
+        bc = (BC * n)(*[BC(*b) for b in self.bcs])
+        handle = ctypes.c_void_p()
+        _check(lib().ch_batch_create(n, grids, cn, pe, None, bc, ctypes.byref(self.opts),
+                                     ctypes.byref(handle)))
+        self._h = handle
+        self.nbox = n
+        offs = [(ctypes.c_int64 * n)() for _ in range(4)]
+        tot = (ctypes.c_int64 * 4)()
+        _check(lib().ch_batch_field_offsets(self._h, *offs, tot))
+        self.c_off, self.u_off, self.v_off, self.w_off = ([int(x) for x in o] for o in offs)
+        self.totals = [int(x) for x in tot]
+        self.stream = None
+        self.set_stream(stream)
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(lib().ch_batch_set_stream(self._h,
+                                         ctypes.c_void_p(stream.cuda_stream if stream else 0)))
+
+    def vel_shapes(self, b):
+        nz, ny, nx = self.shapes[b]
+        bc = self.bcs[b]
+        return ((nz, ny, nx + (bc[0] == 1)), (nz, ny + (bc[1] == 1), nx),
+                (nz + (bc[2] == 1), ny, nx))
+
+    def pack(self, arrays, which):
+        """Pack per-box arrays (numpy or torch) into one device tensor."""
+        tot = self.totals["cuvw".index(which)]
+        out = torch.empty(tot, dtype=self.dtype, device="cuda")
+        offs = {"c": self.c_off, "u": self.u_off, "v": self.v_off, "w": self.w_off}[which]
+        for o, a in zip(offs, arrays):
+            t = torch.as_tensor(np.ascontiguousarray(a) if isinstance(a, np.ndarray) else a)
+            t = t.to(device="cuda", dtype=self.dtype).reshape(-1)
+            out[o:o + t.numel()] = t
+        return out
+
+    def unpack(self, packed):
+        return [packed[o:o + int(np.prod(s))].reshape(s) for o, s in zip(self.c_off, self.shapes)]
+
+    def set_field(self, C_packed):
+        ptr = _dev_tensor(C_packed, self.dtype, (self.totals[0],), "C")
+        self._enter()
+        _check(lib().ch_batch_set_field(self._h, ptr, 1))
+        self._leave()
+        torch.cuda.current_stream().synchronize()
+
+    def get_field(self):
+        out = torch.empty(self.totals[0], dtype=self.dtype, device="cuda")
+        self._enter()
+        _check(lib().ch_batch_get_field(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+        self._leave()
+        return out
+
+    def step(self, u, v, w, dt, nsteps=1):
+        pu = _dev_tensor(u, self.dtype, (self.totals[1],), "u")
+        pv = _dev_tensor(v, self.dtype, (self.totals[2],), "v")
+        pw = _dev_tensor(w, self.dtype, (self.totals[3],), "w")
+        self._enter()
+        _check(lib().ch_batch_step(self._h, pu, pv, pw, float(dt), int(nsteps)))
+        self._leave()
+
+    def mass(self):
+        out = (ctypes.c_double * self.nbox)()
+        self._enter()
+        _check(lib().ch_batch_mass(self._h, out))
+        return [float(x) for x in out]
+
+    def profile(self, on=True):
+        _check(lib().ch_batch_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self, kernel):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().ch_batch_profile_read(self._h, KERNELS.get(kernel, kernel),
+                                           ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ch_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Interp:
+    """Coarse stretched-z velocity -> fine uniform faces (multiple resolution)."""
+
+    def __init__(self, fine_shape, h, coarse_shape, zf, precision="fp64", stream=None):
+        nz, ny, nx = fine_shape
+        ncz, ncy, ncx = coarse_shape
+        self.fine_shape = tuple(fine_shape)
+        self.coarse_shape = tuple(coarse_shape)
+        self.dtype = _dtype(_prec(precision))
+        zf = np.ascontiguousarray(zf, dtype=np.float64)
+        if zf.shape != (ncz + 1,):
+            raise ValueError("zf must have ncz + 1 entries")
+        g = Grid(nx, ny, nz, h)
+        handle = ctypes.c_void_p()
+        _check(lib().ch_interp_create(ctypes.byref(g), ncx, ncy, ncz,
+                                      zf.ctypes.data_as(_PD), _prec(precision),
+                                      ctypes.byref(handle)))
+        self._h = handle
+        self.stream = stream
+        _check(lib().ch_interp_set_stream(self._h,
+                                          ctypes.c_void_p(stream.cuda_stream if stream else 0)))
+
+    def _coarse_ptrs(self, uc, vc, wc):
+        ncz, ncy, ncx = self.coarse_shape
+        return (_dev_tensor(uc, self.dtype, (ncz, ncy, ncx), "uc"),
+                _dev_tensor(vc, self.dtype, (ncz, ncy, ncx), "vc"),
+                _dev_tensor(wc, self.dtype, (ncz + 1, ncy, ncx), "wc"))
+
+    def apply(self, uc, vc, wc):
+        nz, ny, nx = self.fine_shape
+        u = torch.empty((nz, ny, nx), dtype=self.dtype, device="cuda")
+        v = torch.empty((nz, ny, nx), dtype=self.dtype, device="cuda")
+        w = torch.empty((nz + 1, ny, nx), dtype=self.dtype, device="cuda")
+        if self.stream is not None:
+            self.stream.wait_stream(torch.cuda.current_stream())
+        _check(lib().ch_interp_apply(self._h, *self._coarse_ptrs(uc, vc, wc),
+                                     ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                     ctypes.c_void_p(w.data_ptr())))
+        if self.stream is not None:
+            torch.cuda.current_stream().wait_stream(self.stream)
+        return u, v, w
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ch_interp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,327 @@
+// ch_plan.h -- host-side planning of libch, free of any HIP call: the box
+// table (layout of the packed fields, per-box constants), the coefficients
+// of one time step dt (RK3 weights, the factorised line-solve recurrences
+// and their warm-up lengths) and the launch configuration (tasks and LDS
+// per pass).  The library and the CPU harness of the tests share it.
+#pragma once
+
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "../../include/ch.h"
+#include "ch_device.h"
+
+namespace chp {
+
+// Low-storage RK3 constants (gamma_k, rho_k); alpha_k = gamma_k + rho_k.
+constexpr double RK_G[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+constexpr double RK_R[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+
+constexpr size_t LDS_BUDGET = 64 * 1024;   // default per work-group
+constexpr size_t LDS_HARD = 160 * 1024;    // gfx950 LDS per CU
+
+// Factor 1 + r (z - 2 + 1/z)^2 = c (1 + a1/z + a2/z^2)(1 + a1 z + a2 z^2)
+// and choose the warm-up length: the smallest T for which the response of
+// the forward-then-backward recurrences beyond T points stays below tol
+// relative to the data.
+inline bool recurrence(double r, double tol, double* a1, double* a2, double* ic, int* tw)
+{
+    if (!(r > 0.0)) {
+        *a1 = 0.0;
+        *a2 = 0.0;
+        *ic = 1.0;
+        *tw = 0;
+        return true;
+    }
+    const std::complex<double> beta(2.0, 1.0 / std::sqrt(r));
+    const std::complex<double> disc = std::sqrt(beta * beta - 4.0);
+    std::complex<double> z = 0.5 * (beta + disc);
+    if (std::abs(z) >= 1.0) z = 0.5 * (beta - disc);
+    if (!(std::abs(z) < 1.0)) return false;
+    *a1 = -2.0 * z.real();
+    *a2 = std::norm(z);
+    const double c = r / *a2;
+    *ic = 1.0 / c;
+    // impulse response h of 1 / (1 + a1 S^-1 + a2 S^-2)
+    const int NMAX = 1 << 14;
+    std::vector<double> h(NMAX);
+    h[0] = 1.0;
+    h[1] = -*a1;
+    double sum = std::fabs(h[0]) + std::fabs(h[1]);
+    for (int n = 2; n < NMAX; ++n) {
+        h[n] = -*a1 * h[n - 1] - *a2 * h[n - 2];
+        sum += std::fabs(h[n]);
+    }
+    // error <= 2 tail(T) sum / c: the forward truncation carried through the
+    // backward filter, plus the backward truncation
+    double tail = 0.0;
+    int T = NMAX;
+    for (int n = NMAX - 1; n >= 0; --n) {
+        tail += std::fabs(h[n]);
+        if (2.0 * tail * sum / c > tol) {
+            T = n + 1;
+            break;
+        }
+    }
+    if (T >= 4096) return false;
+    *tw = T;
+    return true;
+}
+
+struct Plan {
+    int nbox = 0;
+    int prec = CH_FP64;
+    ch_opts opt{};
+    std::vector<ch_grid> g;
+    std::vector<double> Cn, Pe;
+    std::vector<ch_psi> psi;
+    std::vector<ch_bc> bc;
+    std::vector<chd::BoxDesc> boxes;
+    int64_t tot[4] = {0, 0, 0, 0};   // packed lengths of C (and E, q), u, v, w
+    int nmblk = 0;                   // mass blocks
+    // for the current dt
+    double dt = NAN;
+    bool acc64 = true;
+    int tw_max = 0;
+    int x_rows = 0, lanes = 64, chains = 4, seg_cap = 0;
+    int ntask[3] = {0, 0, 0};
+    size_t lds[3] = {0, 0, 0};
+    int nx_max = 0, seg_max[2] = {0, 0};
+    std::string err;
+
+    ch_status fail(ch_status st, const std::string& m)
+    {
+        err = m;
+        return st;
+    }
+};
+
+inline size_t esize(int prec) { return prec == CH_FP64 ? 8 : 4; }
+
+inline void default_opts(ch_opts* o)
+{
+    *o = ch_opts{};
+    o->precision = CH_FP64;
+    o->kappa = 4.0;
+    o->weno_eps = 1e-6;
+    o->solve_fp64 = CH_SOLVE_AUTO;
+    o->use_graph = 1;
+}
+
+inline ch_status plan_init(Plan& P, int nbox, const ch_grid* g, const double* Cn,
+                           const double* Pe, const ch_psi* psi, const ch_bc* bc,
+                           const ch_opts* opt)
+{
+    if (nbox < 1 || !g || !Cn || !Pe) return P.fail(CH_EINVAL, "null argument");
+    ch_opts o;
+    default_opts(&o);
+    if (opt) o = *opt;
+    if (o.precision != CH_FP64 && o.precision != CH_FP32)
+        return P.fail(CH_EINVAL, "unknown precision");
+    if (!(o.kappa >= 0.0) || !std::isfinite(o.kappa))
+        return P.fail(CH_EINVAL, "kappa must be >= 0 and finite");
+    if (!(o.weno_eps > 0.0) || !std::isfinite(o.weno_eps))
+        return P.fail(CH_EINVAL, "weno_eps must be > 0 and finite");
+    if (o.solve_fp64 < CH_SOLVE_AUTO || o.solve_fp64 > CH_SOLVE_NATIVE)
+        return P.fail(CH_EINVAL, "unknown solve_fp64 mode");
+    if (o.x_rows < 0 || o.x_rows > 64 || o.seg_len < 0 || o.waves_yz < 0 || o.waves_yz > 8)
+        return P.fail(CH_EINVAL, "launch options out of range");
+    if (o.precision == CH_FP64 && o.solve_fp64 == CH_SOLVE_NATIVE) o.solve_fp64 = CH_SOLVE_FP64;
+    P.nbox = nbox;
+    P.prec = o.precision;
+    P.opt = o;
+    P.g.assign(g, g + nbox);
+    P.Cn.assign(Cn, Cn + nbox);
+    P.Pe.assign(Pe, Pe + nbox);
+    const ch_psi dw = {{0.0, 0.5, -1.5, 1.0}};
+    const ch_bc per = {CH_PERIODIC, CH_PERIODIC, CH_PERIODIC};
+    P.psi.assign(nbox, dw);
+    P.bc.assign(nbox, per);
+    if (psi) P.psi.assign(psi, psi + nbox);
+    if (bc) P.bc.assign(bc, bc + nbox);
+    for (int b = 0; b < nbox; ++b) {
+        const int64_t n[3] = {P.g[b].nx, P.g[b].ny, P.g[b].nz};
+        const int bb[3] = {P.bc[b].x, P.bc[b].y, P.bc[b].z};
+        for (int d = 0; d < 3; ++d) {
+            if (!(n[d] == 1 || n[d] >= 8))
+                return P.fail(CH_EINVAL, "box " + std::to_string(b) + ": axis " +
+                                             std::to_string(d) + " has " + std::to_string(n[d]) +
+                                             " cells; need 1 or at least 8");
+            if (n[d] > (1 << 20)) return P.fail(CH_EINVAL, "axis too long");
+            if (bb[d] != CH_PERIODIC && bb[d] != CH_NOFLUX)
+                return P.fail(CH_EINVAL, "unknown boundary condition");
+        }
+        if ((double)n[0] * (double)n[1] >= 2147483647.0)
+            return P.fail(CH_EINVAL, "a plane of the mesh is too large");
+        if (!(P.g[b].h > 0.0) || !std::isfinite(P.g[b].h))
+            return P.fail(CH_EINVAL, "h must be > 0 and finite");
+        if (!(P.Cn[b] > 0.0) || !std::isfinite(P.Cn[b]))
+            return P.fail(CH_EINVAL, "Cn must be > 0 and finite");
+        if (!(P.Pe[b] > 0.0) || !std::isfinite(P.Pe[b]))
+            return P.fail(CH_EINVAL, "Pe must be > 0 and finite");
+        for (int m = 0; m < 4; ++m)
+            if (!std::isfinite(P.psi[b].c[m])) return P.fail(CH_EINVAL, "psi must be finite");
+    }
+    P.boxes.assign(nbox, chd::BoxDesc{});
+    int64_t off[4] = {0, 0, 0, 0};
+    int64_t mblk = 0;
+    for (int b = 0; b < nbox; ++b) {
+        chd::BoxDesc& d = P.boxes[b];
+        const ch_grid& gg = P.g[b];
+        d.n[0] = (int)gg.nx;
+        d.n[1] = (int)gg.ny;
+        d.n[2] = (int)gg.nz;
+        d.bc[0] = P.bc[b].x;
+        d.bc[1] = P.bc[b].y;
+        d.bc[2] = P.bc[b].z;
+        for (int a = 0; a < 3; ++a) d.nf[a] = d.n[a] + (d.bc[a] == CH_NOFLUX ? 1 : 0);
+        const int64_t cells = gg.nx * gg.ny * gg.nz;
+        d.c_off = off[0];
+        d.u_off = off[1];
+        d.v_off = off[2];
+        d.w_off = off[3];
+        off[0] += cells;
+        off[1] += (int64_t)d.nf[0] * gg.ny * gg.nz;
+        off[2] += (int64_t)gg.nx * d.nf[1] * gg.nz;
+        off[3] += (int64_t)gg.nx * gg.ny * d.nf[2];
+        d.inv_h = 1.0 / gg.h;
+        d.inv_h2 = 1.0 / (gg.h * gg.h);
+        d.inv_pe = 1.0 / P.Pe[b];
+        d.eps = o.weno_eps;
+        for (int m = 0; m < 4; ++m) d.psi[m] = P.psi[b].c[m];
+        d.mblk0 = (int)mblk;
+        const int64_t nb = (cells + chd::MASS_BLOCK - 1) / chd::MASS_BLOCK;
+        d.nmblk = (int)nb;
+        mblk += nb;
+        if (mblk > 2000000000LL) return P.fail(CH_EUNSUPPORTED, "batch too large");
+    }
+    for (int m = 0; m < 4; ++m) P.tot[m] = off[m];
+    P.nmblk = (int)mblk;
+    return CH_OK;
+}
+
+// Coefficients, warm-ups and launch configuration for the time step dt.
+inline ch_status plan_dt(Plan& P, double dt)
+{
+    const double tol = P.prec == CH_FP64 ? std::ldexp(1.0, -58) : std::ldexp(1.0, -28);
+    double rmax = 0.0;
+    P.tw_max = 0;
+    for (int b = 0; b < P.nbox; ++b) {
+        chd::BoxDesc& d = P.boxes[b];
+        const double h = P.g[b].h, Cn = P.Cn[b], Pe = P.Pe[b], kap = P.opt.kappa;
+        const double bih = kap * Cn * Cn / (h * h * h * h);
+        for (int k = 0; k < 3; ++k) {
+            const double al = RK_G[k] + RK_R[k];
+            d.gdt[k] = RK_G[k] * dt;
+            d.rdt[k] = RK_R[k] * dt;
+            d.bdt[k] = al * dt / Pe * bih;
+            const double r = 0.5 * al * dt / Pe * bih;
+            rmax = std::max(rmax, r);
+            int tw = 0;
+            if (!recurrence(r, tol, &d.a1[k], &d.a2[k], &d.ic[k], &tw))
+                return P.fail(CH_EUNSUPPORTED, "time step too large for the line solver");
+            d.tw[k] = tw;
+            P.tw_max = std::max(P.tw_max, tw);
+        }
+    }
+    P.acc64 = P.prec == CH_FP64 || P.opt.solve_fp64 == CH_SOLVE_FP64 ||
+              (P.opt.solve_fp64 == CH_SOLVE_AUTO && rmax > 0.25);
+    const size_t sT = esize(P.prec), sA = P.acc64 ? 8 : 4;
+    P.lanes = sT == 8 ? 32 : 64;
+    P.chains = P.opt.waves_yz > 0 ? P.opt.waves_yz : 4;
+    while (P.lanes * P.chains > 512) --P.chains;
+    int nxm = 0, nym = 0, lmax = 0;
+    for (int b = 0; b < P.nbox; ++b) {
+        nxm = std::max(nxm, P.boxes[b].n[0]);
+        nym = std::max(nym, P.boxes[b].n[1]);
+        lmax = std::max({lmax, P.boxes[b].n[1], P.boxes[b].n[2]});
+    }
+    P.nx_max = nxm;
+    // y/z segment: the whole line if it fits in the budget, else the line
+    // split into equal segments that do
+    int seg = P.opt.seg_len > 0 ? P.opt.seg_len
+                                : (int)(LDS_BUDGET / (P.lanes * sA)) - P.tw_max;
+    if (seg < 16) seg = (int)(LDS_HARD / (P.lanes * sA)) - P.tw_max;
+    if (seg < 1) return P.fail(CH_EUNSUPPORTED, "line-solve warm-up too long");
+    if (P.opt.seg_len == 0 && seg < lmax) {
+        const int nseg = (lmax + seg - 1) / seg;
+        seg = (lmax + nseg - 1) / nseg;
+    }
+    seg = std::min(seg, lmax);
+    P.seg_cap = seg;
+    auto x_lds = [&](int R) {
+        const size_t rp = (size_t)R + 1;
+        size_t a = (size_t)(nxm + 2 * P.tw_max) * rp * sT;
+        a = (a + 15) & ~size_t(15);
+        return a + (size_t)(nxm + P.tw_max) * rp * sA;
+    };
+    int R = P.opt.x_rows;
+    if (R == 0) {
+        const int cand[] = {16, 8, 4, 2, 1};
+        for (int c : cand)
+            if (c <= std::max(1, nym) && x_lds(c) <= LDS_BUDGET) {
+                R = c;
+                break;
+            }
+        if (R == 0) R = 1;
+    }
+    if (x_lds(R) > LDS_HARD) return P.fail(CH_EUNSUPPORTED, "x lines too long for LDS");
+    P.x_rows = R;
+    int64_t t0[3] = {0, 0, 0};
+    P.seg_max[0] = P.seg_max[1] = 0;
+    for (int b = 0; b < P.nbox; ++b) {
+        chd::BoxDesc& d = P.boxes[b];
+        const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
+        d.x_rows = std::min(R, ny);
+        d.seg[0] = std::min(seg, ny);
+        d.seg[1] = std::min(seg, nz);
+        P.seg_max[0] = std::max(P.seg_max[0], d.seg[0]);
+        P.seg_max[1] = std::max(P.seg_max[1], d.seg[1]);
+        const int64_t nxb = (nx + P.lanes - 1) / P.lanes;
+        const int64_t tt[3] = {(int64_t)nz * ((ny + d.x_rows - 1) / d.x_rows),
+                               (int64_t)nz * nxb * ((ny + d.seg[0] - 1) / d.seg[0]),
+                               (int64_t)ny * nxb * ((nz + d.seg[1] - 1) / d.seg[1])};
+        for (int p = 0; p < 3; ++p) {
+            if (t0[p] + tt[p] > 2000000000LL)
+                return P.fail(CH_EUNSUPPORTED, "too many work-groups");
+            d.task0[p] = (int)t0[p];
+            d.ntask[p] = (int)tt[p];
+            t0[p] += tt[p];
+        }
+    }
+    for (int p = 0; p < 3; ++p) P.ntask[p] = (int)t0[p];
+    P.lds[0] = x_lds(R);
+    P.lds[1] = (size_t)(P.seg_max[0] + P.tw_max) * P.lanes * sA;
+    P.lds[2] = (size_t)(P.seg_max[1] + P.tw_max) * P.lanes * sA;
+    for (int p = 1; p < 3; ++p)
+        if (P.lds[p] > LDS_HARD) return P.fail(CH_EUNSUPPORTED, "line segment too long for LDS");
+    P.dt = dt;
+    return CH_OK;
+}
+
+inline chd::PassArgs pass_args(const Plan& P, int k)
+{
+    chd::PassArgs pa{};
+    pa.k = k;
+    pa.e_mode = k;       // substage 1 writes E, 2 reads and writes, 3 reads
+    pa.lanes = P.lanes;
+    pa.rp = P.x_rows + 1;
+    pa.tw_max = P.tw_max;
+    pa.nx_max = P.nx_max;
+    pa.kx = 0;
+    return pa;
+}
+
+// byte offset of the forward-recurrence buffer in the x pass's LDS
+inline size_t x_lds_split(const Plan& P)
+{
+    const size_t a = (size_t)(P.nx_max + 2 * P.tw_max) * (P.x_rows + 1) * esize(P.prec);
+    return (a + 15) & ~size_t(15);
+}
+
+}  // namespace chp

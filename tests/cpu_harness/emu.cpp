@@ -1,0 +1,200 @@
+// emu.cpp -- CPU harness for the device code of libch (test infrastructure).
+//
+// Runs the exact phase functions of the HIP kernels (ch_device.h) with the
+// exact launch plan of the library (ch_plan.h) on the CPU: every work-group
+// of every pass, every thread of a phase in turn, a barrier between phases.
+// Built with AddressSanitizer and UBSan, with LDS buffers of exactly the
+// planned size, it checks the kernels' indexing without a GPU.
+//
+// usage: emu PARAMS IN_DIR OUT_DIR
+//   PARAMS: "nbox prec kappa eps solve x_rows seg_len waves dt nsteps" then
+//           per box "nx ny nz h Cn Pe bcx bcy bcz"
+//   IN_DIR/{C,u,v,w}.bin: packed float64 arrays (the library's layout)
+//   OUT_DIR/C.bin: packed float64 result; OUT_DIR/mass.txt: per-box mass;
+//   OUT_DIR/plan.txt: x_rows seg_cap chains tw_max acc64 ntask0..2 lds0..2
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ch.h"
+#include "../../paper_2105_01865_amd/csrc/ch_device.h"
+#include "../../paper_2105_01865_amd/csrc/ch_plan.h"
+
+static std::vector<double> read_bin(const std::string& path, size_t n)
+{
+    std::vector<double> v(n);
+    FILE* f = fopen(path.c_str(), "rb");
+    if (!f || fread(v.data(), sizeof(double), n, f) != n) {
+        fprintf(stderr, "cannot read %s (%zu values)\n", path.c_str(), n);
+        exit(2);
+    }
+    fclose(f);
+    return v;
+}
+
+template <typename T>
+static T* dev_copy(const std::vector<double>& v)
+{
+    // exact-size heap copy: AddressSanitizer flags any access past the end
+    T* p = (T*)malloc(sizeof(T) * (v.size() ? v.size() : 1));
+    for (size_t i = 0; i < v.size(); ++i) p[i] = T(v[i]);
+    return p;
+}
+
+template <typename T, typename A>
+static void run(chp::Plan& P, T* C, T* E, T* qa, T* qb, const T* u, const T* v, const T* w,
+                int nsteps)
+{
+    const chd::BoxDesc* boxes = P.boxes.data();
+    for (int s = 0; s < nsteps; ++s)
+        for (int k = 0; k < 3; ++k) {
+            const chd::PassArgs pa = chp::pass_args(P, k);
+            // pass x
+            for (int task = 0; task < P.ntask[0]; ++task) {
+                unsigned char* lds = (unsigned char*)malloc(P.lds[0]);
+                memset(lds, 0xff, P.lds[0]);
+                T* tb = (T*)lds;
+                A* twb = (A*)(lds + chp::x_lds_split(P));
+                const int b = chd::find_box(boxes, P.nbox, chd::PASS_X, task);
+                const chd::BoxDesc& bd = boxes[b];
+                const chd::XTask t = chd::x_task(bd, pa, task);
+                const int nth = 256;
+                for (int tid = 0; tid < nth; ++tid)
+                    chd::x_phase_rhs<T>(tid, nth, bd, pa, t, C, u, v, w, E, tb);
+                for (int tid = 0; tid < nth; ++tid) chd::x_phase_halo<T>(tid, nth, bd, pa, t, tb);
+                for (int tid = 0; tid < nth; ++tid)
+                    chd::x_phase_fwd<T, A>(tid, nth, bd, pa, t, tb, twb);
+                for (int tid = 0; tid < nth; ++tid)
+                    chd::x_phase_bwd<T, A>(tid, nth, bd, pa, t, tb, twb);
+                for (int tid = 0; tid < nth; ++tid)
+                    chd::x_phase_store<T>(tid, nth, bd, pa, t, tb, qa);
+                free(lds);
+            }
+            // passes y, z
+            for (int pass = 1; pass <= 2; ++pass) {
+                const T* in = pass == 1 ? qa : qb;
+                T* out = pass == 1 ? qb : C;
+                const int nth = P.lanes * P.chains;
+                for (int task = 0; task < P.ntask[pass]; ++task) {
+                    A* wb = (A*)malloc(P.lds[pass]);
+                    memset((void*)wb, 0xff, P.lds[pass]);
+                    const int b = chd::find_box(boxes, P.nbox, pass, task);
+                    const chd::BoxDesc& bd = boxes[b];
+                    const chd::LTask t = chd::l_task(bd, pa, pass, task);
+                    for (int tid = 0; tid < nth; ++tid)
+                        chd::l_phase_fwd<T, A>(tid, nth, bd, pa, t, in, wb);
+                    for (int tid = 0; tid < nth; ++tid)
+                        chd::l_phase_bwd<T, A>(tid, nth, bd, pa, t, wb, out, pass == 2 ? 1 : 0);
+                    free(wb);
+                }
+            }
+        }
+}
+
+template <typename T>
+static std::vector<double> masses(const chp::Plan& P, const T* C)
+{
+    std::vector<double> out(P.nbox);
+    for (int b = 0; b < P.nbox; ++b) {
+        const chd::BoxDesc& bd = P.boxes[b];
+        std::vector<double> partial(bd.nmblk);
+        for (int blk = 0; blk < bd.nmblk; ++blk) {
+            double sh[chd::MASS_THREADS];
+            for (int tid = 0; tid < chd::MASS_THREADS; ++tid)
+                sh[tid] = chd::mass_thread_sum<T>(tid, bd, blk, C);
+            for (int s = chd::MASS_THREADS / 2; s > 0; s >>= 1)
+                for (int tid = 0; tid < s; ++tid) sh[tid] += sh[tid + s];
+            partial[blk] = sh[0];
+        }
+        double sh[chd::MASS_THREADS];
+        for (int tid = 0; tid < chd::MASS_THREADS; ++tid) {
+            double s = 0.0;
+            for (int i = tid; i < bd.nmblk; i += chd::MASS_THREADS) s += partial[i];
+            sh[tid] = s;
+        }
+        for (int s = chd::MASS_THREADS / 2; s > 0; s >>= 1)
+            for (int tid = 0; tid < s; ++tid) sh[tid] += sh[tid + s];
+        const double h = P.g[b].h;
+        out[b] = sh[0] * (h * h * h);
+    }
+    return out;
+}
+
+template <typename T>
+static int go(chp::Plan& P, const std::string& in, const std::string& out, int nsteps)
+{
+    std::vector<double> C0 = read_bin(in + "/C.bin", P.tot[0]);
+    T* C = dev_copy<T>(C0);
+    std::vector<double> zero(P.tot[0], 0.0);
+    T* E = dev_copy<T>(zero);
+    T* qa = dev_copy<T>(zero);
+    T* qb = dev_copy<T>(zero);
+    T* u = dev_copy<T>(read_bin(in + "/u.bin", P.tot[1]));
+    T* v = dev_copy<T>(read_bin(in + "/v.bin", P.tot[2]));
+    T* w = dev_copy<T>(read_bin(in + "/w.bin", P.tot[3]));
+    if (P.prec == CH_FP64) run<T, T>(P, C, E, qa, qb, u, v, w, nsteps);
+    else if (P.acc64) run<T, double>(P, C, E, qa, qb, u, v, w, nsteps);
+    else run<T, float>(P, C, E, qa, qb, u, v, w, nsteps);
+    std::vector<double> res(P.tot[0]);
+    for (int64_t i = 0; i < P.tot[0]; ++i) res[i] = double(C[i]);
+    FILE* f = fopen((out + "/C.bin").c_str(), "wb");
+    fwrite(res.data(), sizeof(double), res.size(), f);
+    fclose(f);
+    std::vector<double> m = masses<T>(P, C);
+    f = fopen((out + "/mass.txt").c_str(), "w");
+    for (double x : m) fprintf(f, "%.17g\n", x);
+    fclose(f);
+    f = fopen((out + "/plan.txt").c_str(), "w");
+    fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu\n", P.x_rows, P.seg_cap, P.chains, P.tw_max,
+            P.acc64 ? 1 : 0, P.ntask[0], P.ntask[1], P.ntask[2], P.lds[0], P.lds[1], P.lds[2]);
+    fclose(f);
+    free(C); free(E); free(qa); free(qb); free(u); free(v); free(w);
+    return 0;
+}
+
+int main(int argc, char** argv)
+{
+    if (argc != 4) {
+        fprintf(stderr, "usage: emu PARAMS IN_DIR OUT_DIR\n");
+        return 2;
+    }
+    FILE* f = fopen(argv[1], "r");
+    if (!f) return 2;
+    int nbox, prec, solve, x_rows, seg, waves, nsteps;
+    double kappa, eps, dt;
+    if (fscanf(f, "%d %d %lf %lf %d %d %d %d %lf %d", &nbox, &prec, &kappa, &eps, &solve,
+               &x_rows, &seg, &waves, &dt, &nsteps) != 10)
+        return 2;
+    std::vector<ch_grid> g(nbox);
+    std::vector<double> Cn(nbox), Pe(nbox);
+    std::vector<ch_bc> bc(nbox);
+    for (int b = 0; b < nbox; ++b) {
+        long long nx, ny, nz;
+        if (fscanf(f, "%lld %lld %lld %lf %lf %lf %d %d %d", &nx, &ny, &nz, &g[b].h, &Cn[b],
+                   &Pe[b], &bc[b].x, &bc[b].y, &bc[b].z) != 9)
+            return 2;
+        g[b].nx = nx;
+        g[b].ny = ny;
+        g[b].nz = nz;
+    }
+    fclose(f);
+    ch_opts o;
+    chp::default_opts(&o);
+    o.precision = prec;
+    o.kappa = kappa;
+    o.weno_eps = eps;
+    o.solve_fp64 = solve;
+    o.x_rows = x_rows;
+    o.seg_len = seg;
+    o.waves_yz = waves;
+    chp::Plan P;
+    if (chp::plan_init(P, nbox, g.data(), Cn.data(), Pe.data(), nullptr, bc.data(), &o) != CH_OK ||
+        chp::plan_dt(P, dt) != CH_OK) {
+        fprintf(stderr, "plan failed: %s\n", P.err.c_str());
+        return 3;
+    }
+    if (prec == CH_FP64) return go<double>(P, argv[2], argv[3], nsteps);
+    return go<float>(P, argv[2], argv[3], nsteps);
+}

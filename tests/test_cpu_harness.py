@@ -1,0 +1,110 @@
+"""The device code of libch, run on the CPU by the harness in
+tests/cpu_harness (AddressSanitizer + UBSan, exact LDS sizes), against the
+FP64 oracle.  This checks the kernels' indexing, halos, segments, the
+chunked line recurrences and the batch layout without a GPU."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_01865_amd import inputs
+from tests.harness_util import run_emu
+
+
+def _box(shape, bc=(0, 0, 0), seed=0, amp=1.0, drops=True):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    h = 1.0 / max(shape)
+    if drops:
+        cen, rad = inputs.place_drops(rng, 3, 2, 4, shape, h, walls_z=bc[2] == 1, gap_cells=1)
+        C = inputs.drop_field(shape, h, h, cen, rad, walls_z=bc[2] == 1)
+        C = C + 0.02 * rng.normal(size=shape)
+    else:
+        C = 0.5 + 0.3 * rng.normal(size=shape)
+    if bc == (0, 0, 0):
+        Ax, Ay, Az = (rng.normal(size=shape) for _ in range(3))
+        u, v, w = inputs.curl_velocity(Ax, Ay, Az, h)
+    elif bc == (0, 0, 1):
+        zf = np.arange(nz + 1) / nz
+        u, v, w = inputs.coarse_wall_velocity(rng, shape, zf, kmax=3, nmodes_z=3)
+    else:
+        # walls in x and z: a stream function on the x-z cell corners that
+        # vanishes on the walls; v depends on x and z only
+        assert bc == (1, 0, 1)
+        xf = np.arange(nx + 1) / nx
+        zf = np.arange(nz + 1) / nz
+        psi = sum(rng.normal() * np.outer(np.sin(m * np.pi * zf), np.sin(q * np.pi * xf))
+                  for m in (1, 2) for q in (1, 3))                       # (nz+1, nx+1)
+        u = np.repeat(((psi[1:, :] - psi[:-1, :]) / h)[:, None, :], ny, axis=1)
+        w = np.repeat((-(psi[:, 1:] - psi[:, :-1]) / h)[:, None, :], ny, axis=1)
+        v = np.repeat(rng.normal(size=(nz, 1, nx)), ny, axis=1)
+    s = amp / max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max())
+    return dict(C=C, u=u * s, v=v * s, w=w * s, h=h, Cn=h, Pe=0.9 / h, bc=bc)
+
+
+def _oracle(b, dt, nsteps, kappa=4.0):
+    return oracle.step(b["C"], b["u"], b["v"], b["w"], b["h"], b["Cn"], b["Pe"], dt, nsteps,
+                       bc=b["bc"], kappa=kappa)
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+def test_config1_fp64_matches_oracle():
+    wl = inputs.make_workload(1)
+    b = dict(C=wl.C, u=wl.u, v=wl.v, w=wl.w, h=wl.h, Cn=wl.Cn, Pe=wl.Pe, bc=(0, 0, 0))
+    (C1,), (m,), plan = run_emu([b], wl.dt, 2)
+    ref = _oracle(b, wl.dt, 2)
+    assert _rel(C1, ref) < 1e-12
+    assert _rel(C1 - wl.C, ref - wl.C) < 1e-10      # the increment itself
+    assert abs(m - oracle.mass(ref, wl.h)) < 1e-13 * abs(m)
+
+
+@pytest.mark.parametrize("shape,bc", [((20, 12, 16), (0, 0, 0)), ((16, 9, 24), (0, 0, 1)),
+                                      ((12, 16, 8), (1, 0, 1)), ((1, 24, 16), (0, 0, 0))])
+def test_fp64_matches_oracle_ragged_and_walls(shape, bc):
+    b = _box(shape, bc=bc, seed=1, amp=2.0)
+    dt = 2e-4
+    # odd row counts and short segments force ragged tiles and segmented lines
+    out, masses, plan = run_emu([b], dt, 2, x_rows=3, seg=5, waves=3)
+    ref = _oracle(b, dt, 2)
+    assert _rel(out[0], ref) < 1e-12
+    assert plan["ntask"][1] > 0
+
+
+def test_fp64_large_dt_needs_long_warmup():
+    b = _box((16, 16, 16), seed=2, amp=0.5, drops=False)
+    dt = 0.05          # r >> 1: long recurrence warm-up, wrapping the line
+    out, _, plan = run_emu([b], dt, 1)
+    assert plan["tw_max"] > 16
+    ref = _oracle(b, dt, 1)
+    assert _rel(out[0], ref) < 1e-12
+
+
+def test_kappa3_and_default_plan():
+    b = _box((24, 24, 24), seed=3)
+    out, _, plan = run_emu([b], 1e-4, 1, kappa=3.0)
+    ref = _oracle(b, 1e-4, 1, kappa=3.0)
+    assert _rel(out[0], ref) < 1e-12
+
+
+@pytest.mark.parametrize("solve", [0, 1, 2])
+def test_fp32_close_to_fp64_oracle(solve):
+    b = _box((16, 16, 16), seed=4, amp=1.0)
+    out, _, plan = run_emu([b], 2e-4, 3, prec=1, solve=solve)
+    ref = _oracle(b, 2e-4, 3)
+    assert plan["acc64"] == (1 if solve == 1 else 0)
+    assert _rel(out[0], ref) < 2e-6
+
+
+def test_batch_equals_single_boxes_bitwise():
+    boxes = [_box((16, 16, 16), seed=5), _box((8, 12, 24), seed=6), _box((24, 8, 8), seed=7)]
+    dt = 3e-4
+    batch, bm, _ = run_emu(boxes, dt, 2)
+    for b, got, m in zip(boxes, batch, bm):
+        (single,), (sm,), _ = run_emu([b], dt, 2)
+        assert np.array_equal(got, single)
+        assert m == sm
+        assert _rel(got, _oracle(b, dt, 2)) < 1e-12
