@@ -100,6 +100,7 @@ typedef struct {
     int x_rows;         /* rows per x-pass work-group; 0 = automatic */
     int seg_len;        /* y/z line segment per work-group; 0 = automatic */
     int waves_yz;       /* waves per y/z work-group (1..8); 0 = automatic */
+    int z_chunk;        /* planes one x-pass work-group marches over; 0 = automatic */
 } ch_opts;
 
 typedef struct ch_state ch_state;
@@ -205,11 +206,13 @@ ch_status ch_profile_read(ch_state* s, int kernel, double* total_ms, int64_t* la
 ch_status ch_batch_profile_enable(ch_batch* b, int on);
 ch_status ch_batch_profile_read(ch_batch* b, int kernel, double* total_ms, int64_t* launches);
 
-/* Launch configuration the library chose (or was given) for the state:
- * cfg[0] = x rows per work-group, cfg[1] = y/z segment, cfg[2] = waves per
- * y/z work-group, cfg[3..5] = warm-up length of the line recurrences in
- * substages 1..3 for the first box, cfg[6] = 1 if the solves run in double. */
-ch_status ch_get_config(const ch_state* s, int cfg[7]);
+/* Launch configuration the library chose (or was given) for the state at
+ * its last time step: cfg[0] = x rows per x-pass work-group, cfg[1] = y/z
+ * line segment, cfg[2] = threads per y/z work-group, cfg[3..5] = warm-up
+ * length of the line recurrences in substages 1..3 (first box), cfg[6] = 1
+ * if the solves run in double, cfg[7] = planes an x-pass work-group marches
+ * over. */
+ch_status ch_get_config(const ch_state* s, int cfg[8]);
 
 #ifdef __cplusplus
 }

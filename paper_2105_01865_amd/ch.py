@@ -48,7 +48,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("kappa", ctypes.c_double),
                 ("weno_eps", ctypes.c_double), ("solve_fp64", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("x_rows", ctypes.c_int),
-                ("seg_len", ctypes.c_int), ("waves_yz", ctypes.c_int)]
+                ("seg_len", ctypes.c_int), ("waves_yz", ctypes.c_int),
+                ("z_chunk", ctypes.c_int)]
 
 
 _lib = None
@@ -128,7 +129,7 @@ def _prec(p):
 
 
 def make_opts(precision="fp64", kappa=4.0, weno_eps=1e-6, solve="auto", use_graph=True,
-              x_rows=0, seg_len=0, waves_yz=0):
+              x_rows=0, seg_len=0, waves_yz=0, z_chunk=0):
     o = Opts()
     lib().ch_default_opts(ctypes.byref(o))
     o.precision = _prec(precision)
@@ -136,7 +137,7 @@ def make_opts(precision="fp64", kappa=4.0, weno_eps=1e-6, solve="auto", use_grap
     o.weno_eps = weno_eps
     o.solve_fp64 = SOLVE[solve]
     o.use_graph = 1 if use_graph else 0
-    o.x_rows, o.seg_len, o.waves_yz = x_rows, seg_len, waves_yz
+    o.x_rows, o.seg_len, o.waves_yz, o.z_chunk = x_rows, seg_len, waves_yz, z_chunk
     return o
 
 
@@ -251,10 +252,10 @@ class State(_StreamMixin):
         return ms.value, n.value
 
     def config(self):
-        cfg = (ctypes.c_int * 7)()
+        cfg = (ctypes.c_int * 8)()
         _check(lib().ch_get_config(self._h, cfg))
-        return dict(x_rows=cfg[0], seg=cfg[1], chains=cfg[2], tw=list(cfg[3:6]),
-                    acc64=bool(cfg[6]))
+        return dict(x_rows=cfg[0], seg=cfg[1], yz_threads=cfg[2], tw=list(cfg[3:6]),
+                    acc64=bool(cfg[6]), z_chunk=cfg[7])
 
     def close(self):
         if getattr(self, "_h", None):

@@ -46,6 +46,7 @@ struct BoxDesc {
     int32_t bc[3];      // 0 periodic, 1 no-flux
     int32_t nf[3];      // faces stored along x (u), y (v), z (w)
     int32_t x_rows;     // rows of one x-pass task
+    int32_t zc;         // planes one x-pass task marches over
     int64_t c_off;      // first element of this box in C, E, q
     int64_t u_off, v_off, w_off;
     double inv_h, inv_h2, inv_pe, eps;
@@ -67,11 +68,12 @@ struct BoxDesc {
 struct PassArgs {
     int32_t k;          // substage 0, 1, 2
     int32_t e_mode;     // x pass: 0 write E, 1 read old E and write E, 2 read old E
-    int32_t lanes;      // y/z pass: x columns per task (32 or 64)
-    int32_t rp;         // x pass: LDS row pitch (max rows + 1)
+    int32_t lanes;      // y/z pass: x columns per task
+    int32_t rmax;       // x pass: rows per task (LDS layout)
     int32_t tw_max;     // largest warm-up over boxes (LDS layout)
-    int32_t nx_max;     // largest line length of this pass over boxes (LDS layout)
-    int32_t kx;         // x pass: chunk length (0 = derive)
+    int32_t nx_max;     // largest x extent over boxes (LDS layout)
+    int32_t seg_max;    // y/z pass: longest segment over boxes (LDS layout)
+    int32_t kmin;       // shortest chunk of the chunked line recurrences
 };
 
 // Index of a cell that may lie outside [0, n): periodic wrap, or even
@@ -128,82 +130,6 @@ CH_HD T d4(T m2, T m1, T c0, T p1, T p2)
     return ((d - c) - (c - b)) - ((c - b) - (b - a));
 }
 
-// The explicit terms of cell (i, j, kz) of box bd.  Returns
-//   E = -div(u C) + lap psi'(C) / Pe          (through *e_out)
-//   B = sum_d (1,-4,6,-4,1)_d C              (return value, unscaled)
-template <typename T>
-CH_HD T cell_terms(const BoxDesc& bd, const T* __restrict__ C, const T* __restrict__ U,
-                   const T* __restrict__ V, const T* __restrict__ W, int i, int j, int kz,
-                   T* e_out)
-{
-    const int nx = bd.n[0], ny = bd.n[1], nz = bd.n[2];
-    const int64_t plane = (int64_t)nx * ny;
-    const T* Cb = C + bd.c_off;
-    // C along each axis at offsets -3..3
-    T cx[7], cy[7], cz[7];
-    const int64_t rowz = (int64_t)kz * plane;
-    const int64_t rowy = (int64_t)j * nx;
-    for (int m = -3; m <= 3; ++m) {
-        cx[m + 3] = Cb[rowz + rowy + map_idx(i + m, nx, bd.bc[0])];
-        cy[m + 3] = Cb[rowz + (int64_t)map_idx(j + m, ny, bd.bc[1]) * nx + i];
-        cz[m + 3] = Cb[(int64_t)map_idx(kz + m, nz, bd.bc[2]) * plane + rowy + i];
-    }
-    const T eps = T(bd.eps);
-    // face velocities: low face = index of the cell, high face = next index
-    // (wrapping to face 0 on a periodic axis)
-    const int fx = bd.nf[0], fy = bd.nf[1];
-    const int ih = (i + 1 == nx && bd.bc[0] == 0) ? 0 : i + 1;
-    const int jh = (j + 1 == ny && bd.bc[1] == 0) ? 0 : j + 1;
-    const int kh = (kz + 1 == nz && bd.bc[2] == 0) ? 0 : kz + 1;
-    const T* Ub = U + bd.u_off;
-    const T* Vb = V + bd.v_off;
-    const T* Wb = W + bd.w_off;
-    const int64_t ur = ((int64_t)kz * ny + j) * fx;
-    const T ulo = Ub[ur + i], uhi = Ub[ur + ih];
-    const int64_t vr = (int64_t)kz * fy * nx;
-    const T vlo = Vb[vr + (int64_t)j * nx + i], vhi = Vb[vr + (int64_t)jh * nx + i];
-    const T wlo = Wb[(int64_t)kz * plane + rowy + i], whi = Wb[(int64_t)kh * plane + rowy + i];
-
-    // upwinded WENO face values: the left-biased stencil when the face
-    // velocity is >= 0, the mirrored one otherwise
-    T adv = T(0);
-    {
-        const T* c = cx;
-        const bool pl = ulo >= T(0), ph = uhi >= T(0);
-        const T flo = weno5<T>(pl ? c[0] : c[5], pl ? c[1] : c[4], pl ? c[2] : c[3],
-                               pl ? c[3] : c[2], pl ? c[4] : c[1], eps);
-        const T fhi = weno5<T>(ph ? c[1] : c[6], ph ? c[2] : c[5], ph ? c[3] : c[4],
-                               ph ? c[4] : c[3], ph ? c[5] : c[2], eps);
-        adv += uhi * fhi - ulo * flo;
-    }
-    {
-        const T* c = cy;
-        const bool pl = vlo >= T(0), ph = vhi >= T(0);
-        const T flo = weno5<T>(pl ? c[0] : c[5], pl ? c[1] : c[4], pl ? c[2] : c[3],
-                               pl ? c[3] : c[2], pl ? c[4] : c[1], eps);
-        const T fhi = weno5<T>(ph ? c[1] : c[6], ph ? c[2] : c[5], ph ? c[3] : c[4],
-                               ph ? c[4] : c[3], ph ? c[5] : c[2], eps);
-        adv += vhi * fhi - vlo * flo;
-    }
-    {
-        const T* c = cz;
-        const bool pl = wlo >= T(0), ph = whi >= T(0);
-        const T flo = weno5<T>(pl ? c[0] : c[5], pl ? c[1] : c[4], pl ? c[2] : c[3],
-                               pl ? c[3] : c[2], pl ? c[4] : c[1], eps);
-        const T fhi = weno5<T>(ph ? c[1] : c[6], ph ? c[2] : c[5], ph ? c[3] : c[4],
-                               ph ? c[4] : c[3], ph ? c[5] : c[2], eps);
-        adv += whi * fhi - wlo * flo;
-    }
-    // Laplacian of the bulk potential
-    const T mu0 = psi_prime<T>(bd.psi, cx[3]);
-    const T lap = (psi_prime<T>(bd.psi, cx[4]) - mu0) - (mu0 - psi_prime<T>(bd.psi, cx[2]))
-                + (psi_prime<T>(bd.psi, cy[4]) - mu0) - (mu0 - psi_prime<T>(bd.psi, cy[2]))
-                + (psi_prime<T>(bd.psi, cz[4]) - mu0) - (mu0 - psi_prime<T>(bd.psi, cz[2]));
-    *e_out = -adv * T(bd.inv_h) + lap * T(bd.inv_h2) * T(bd.inv_pe);
-    return d4<T>(cx[1], cx[2], cx[3], cx[4], cx[5]) + d4<T>(cy[1], cy[2], cy[3], cy[4], cy[5])
-         + d4<T>(cz[1], cz[2], cz[3], cz[4], cz[5]);
-}
-
 // Box of a global task index (boxes sorted by task0 of the pass).
 CH_HD int find_box(const BoxDesc* boxes, int nbox, int pass, int task)
 {
@@ -217,145 +143,418 @@ CH_HD int find_box(const BoxDesc* boxes, int nbox, int pass, int task)
 }
 
 // ---------------------------------------------------------------------------
-// Pass X: explicit terms, RHS and the x-line solve of eq-fac-1, for a task of
-// `rows` complete x-lines (y0 .. y0+rows-1 at plane z).
-// LDS: tb = (nx_max + 2 tw_max) x rp elements holding the RHS with halos,
-// tw = (nx_max + tw_max) x rp elements holding the forward recurrence.
-// Element of line position p (-tw <= p < nx + tw) and row r: tb[(p + tw) rp + r].
+// Execution of a work-group program.  A pass is written once as a sequence
+// of phases; `ex.phase(f)` runs f(tid) for this thread and then waits at a
+// work-group barrier on the GPU, and runs f for every thread in turn on the
+// CPU.  Per-thread state that lives across phases is kept in `S* st` and
+// addressed as st[ex.slot(tid)]: one local object on the GPU (registers),
+// one per thread on the CPU.
 // ---------------------------------------------------------------------------
-struct XTask {
-    int z, y0, rows, nx, tw, kx;
+#if defined(__HIPCC__)
+struct GpuExec {
+    int tid, nth;
+    template <class F>
+    __device__ __forceinline__ void phase(F&& f)
+    {
+        f(tid);
+        __syncthreads();
+    }
+    __device__ __forceinline__ int slot(int) const { return 0; }
+};
+#endif
+
+struct CpuExec {
+    int nth;
+    template <class F>
+    void phase(F&& f)
+    {
+        for (int t = 0; t < nth; ++t) f(t);
+    }
+    int slot(int t) const { return t; }
 };
 
-CH_HD XTask x_task(const BoxDesc& bd, const PassArgs& pa, int task)
-{
-    XTask t;
-    const int local = task - bd.task0[PASS_X];
-    const int R = bd.x_rows;
-    const int nyb = (bd.n[1] + R - 1) / R;
-    t.z = local / nyb;
-    t.y0 = (local % nyb) * R;
-    t.rows = bd.n[1] - t.y0 < R ? bd.n[1] - t.y0 : R;
-    t.nx = bd.n[0];
-    t.tw = bd.tw[pa.k];
-    t.kx = pa.kx;
-    return t;
-}
-
+// upwinded WENO value on a face from the six values c[0..5] of cells
+// f-3 .. f+2 around the face between c[2] and c[3]
 template <typename T>
-CH_HD void x_phase_rhs(int tid, int nth, const BoxDesc& bd, const PassArgs& pa, const XTask& t,
-                       const T* __restrict__ C, const T* __restrict__ U, const T* __restrict__ V,
-                       const T* __restrict__ W, T* __restrict__ E, T* tb)
+CH_HD T face_weno(T vel, T c0, T c1, T c2, T c3, T c4, T c5, T eps)
 {
-    const int nx = t.nx, k = pa.k, rp = pa.rp;
-    const int64_t plane = (int64_t)bd.n[0] * bd.n[1];
-    const T gdt = T(bd.gdt[k]), rdt = T(bd.rdt[k]), bdt = T(bd.bdt[k]);
-    for (int item = tid; item < t.rows * nx; item += nth) {
-        const int r = item / nx, i = item - r * nx;
-        const int j = t.y0 + r;
-        T e;
-        const T b4 = cell_terms<T>(bd, C, U, V, W, i, j, t.z, &e);
-        const int64_t at = bd.c_off + (int64_t)t.z * plane + (int64_t)j * nx + i;
-        T rhs = gdt * e - bdt * b4;
-        if (pa.e_mode != 0) rhs += rdt * E[at];
-        if (pa.e_mode != 2) E[at] = e;
-        tb[(i + t.tw) * rp + r] = rhs;
-    }
+    const bool p = vel >= T(0);
+    return weno5<T>(p ? c0 : c5, p ? c1 : c4, p ? c2 : c3, p ? c3 : c2, p ? c4 : c1, eps);
 }
 
-template <typename T>
-CH_HD void x_phase_halo(int tid, int nth, const BoxDesc& bd, const PassArgs& pa, const XTask& t,
-                        T* tb)
+// ---------------------------------------------------------------------------
+// In-place chunked line solve of (I + r D4) y = b on an LDS tile.
+// Element (p, l) of line l at position p (-tw <= p < n + tw) sits at
+// tile[(p + tw) * pitch + l]; the halos hold the periodic or reflected
+// continuation of b.  Thread tid works on line l = tid % nl, chunk
+// c = tid / nl of length K.  Four phases, each followed by a barrier:
+//   f1: forward warm-up over [c0 - tw, c0) (reads b)      -> state
+//   f2: forward over the chunk, b -> w in place; the last chunk runs on to
+//       n + tw so that every backward warm-up finds its w values
+//   b1: backward warm-up over [e, e + tw) (reads w)       -> state
+//   b2: backward over the chunk, w -> y in place
+// ---------------------------------------------------------------------------
+template <typename A>
+struct LineState {
+    A s1, s2;
+};
+
+struct Chunk {
+    int l, c0, fend, bend;
+    bool live;
+};
+
+CH_HD Chunk line_chunk(int tid, int nth, int nl, int n, int tw, int kmin)
 {
-    const int nx = t.nx, tw = t.tw, rp = pa.rp;
-    const int span = 2 * tw;
-    for (int item = tid; item < t.rows * span; item += nth) {
-        const int r = item / span, m = item - r * span;
-        const int p = m < tw ? m - tw : nx + (m - tw);
-        const int s = map_idx(p, nx, bd.bc[0]);
-        tb[(p + tw) * rp + r] = tb[(s + tw) * rp + r];
-    }
+    Chunk ch;
+    const int nchmax = nth / nl;
+    ch.l = tid % nl;
+    const int c = tid / nl;
+    int K = (n + nchmax - 1) / nchmax;
+    if (K < kmin) K = kmin;
+    if (K < 1) K = 1;
+    ch.c0 = c * K;
+    ch.live = c < nchmax && ch.c0 < n;
+    const bool last = ch.c0 + K >= n;
+    ch.fend = last ? n + tw : ch.c0 + K;
+    ch.bend = ch.c0 + K < n ? ch.c0 + K : n;
+    return ch;
 }
 
-// chunk length of the x solve: enough chunks to give every thread one
-CH_HD int x_chunk(const XTask& t, int nth)
+template <typename A>
+CH_HD void line_f1(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2, A ic,
+                   LineState<A>& st)
 {
-    if (t.kx > 0) return t.kx;
-    const int per = nth / (t.rows > 0 ? t.rows : 1);
-    const int len = t.nx + t.tw;
-    int kx = (len + per - 1) / (per > 0 ? per : 1);
-    return kx < 1 ? 1 : kx;
-}
-
-template <typename T, typename A>
-CH_HD void x_phase_fwd(int tid, int nth, const BoxDesc& bd, const PassArgs& pa, const XTask& t,
-                       const T* tb, A* twb)
-{
-    const int nx = t.nx, tw = t.tw, rp = pa.rp, k = pa.k;
-    const int kx = x_chunk(t, nth);
-    const int len = nx + tw;
-    const int nch = (len + kx - 1) / kx;
-    const A a1 = A(bd.a1[k]), a2 = A(bd.a2[k]), ic = A(bd.ic[k]);
-    for (int item = tid; item < t.rows * nch; item += nth) {
-        const int r = item % t.rows, c = item / t.rows;
-        const int c0 = c * kx;
-        const int c1 = c0 + kx < len ? c0 + kx : len;
-        A w1 = A(0), w2 = A(0);
-        for (int p = c0 - tw; p < c1; ++p) {
-            const A w = A(tb[(p + tw) * rp + r]) * ic - a1 * w1 - a2 * w2;
-            if (p >= c0) twb[p * rp + r] = w;
+    A w1 = A(0), w2 = A(0);
+    if (ch.live) {
+        for (int p = ch.c0 - tw; p < ch.c0; ++p) {
+            const A w = tile[(p + tw) * pitch + ch.l] * ic - a1 * w1 - a2 * w2;
             w2 = w1;
             w1 = w;
         }
     }
+    st.s1 = w1;
+    st.s2 = w2;
 }
 
-template <typename T, typename A>
-CH_HD void x_phase_bwd(int tid, int nth, const BoxDesc& bd, const PassArgs& pa, const XTask& t,
-                       T* tb, const A* twb)
+template <typename A>
+CH_HD void line_f2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2, A ic,
+                   const LineState<A>& st)
 {
-    const int nx = t.nx, tw = t.tw, rp = pa.rp, k = pa.k;
-    const int kx = x_chunk(t, nth);
-    const int nch = (nx + kx - 1) / kx;
-    const A a1 = A(bd.a1[k]), a2 = A(bd.a2[k]);
-    for (int item = tid; item < t.rows * nch; item += nth) {
-        const int r = item % t.rows, c = item / t.rows;
-        const int c0 = c * kx;
-        const int e = c0 + kx < nx ? c0 + kx : nx;
-        A y1 = A(0), y2 = A(0);
-        for (int p = e + tw - 1; p >= c0; --p) {
-            const A y = twb[p * rp + r] - a1 * y1 - a2 * y2;
-            if (p < e) tb[(p + tw) * rp + r] = T(y);
+    if (!ch.live) return;
+    A w1 = st.s1, w2 = st.s2;
+    for (int p = ch.c0; p < ch.fend; ++p) {
+        A* at = tile + (p + tw) * pitch + ch.l;
+        const A w = *at * ic - a1 * w1 - a2 * w2;
+        *at = w;
+        w2 = w1;
+        w1 = w;
+    }
+}
+
+template <typename A>
+CH_HD void line_b1(const Chunk& ch, const A* tile, int pitch, int tw, A a1, A a2,
+                   LineState<A>& st)
+{
+    A y1 = A(0), y2 = A(0);
+    if (ch.live) {
+        for (int p = ch.bend + tw - 1; p >= ch.bend; --p) {
+            const A y = tile[(p + tw) * pitch + ch.l] - a1 * y1 - a2 * y2;
             y2 = y1;
             y1 = y;
         }
     }
+    st.s1 = y1;
+    st.s2 = y2;
 }
 
-template <typename T>
-CH_HD void x_phase_store(int tid, int nth, const BoxDesc& bd, const PassArgs& pa, const XTask& t,
-                         const T* tb, T* __restrict__ Q)
+template <typename A>
+CH_HD void line_b2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2,
+                   const LineState<A>& st)
 {
-    const int nx = t.nx, rp = pa.rp;
-    const int64_t plane = (int64_t)bd.n[0] * bd.n[1];
-    for (int item = tid; item < t.rows * nx; item += nth) {
-        const int r = item / nx, i = item - r * nx;
-        Q[bd.c_off + (int64_t)t.z * plane + (int64_t)(t.y0 + r) * nx + i] =
-            tb[(i + t.tw) * rp + r];
+    if (!ch.live) return;
+    A y1 = st.s1, y2 = st.s2;
+    for (int p = ch.bend - 1; p >= ch.c0; --p) {
+        A* at = tile + (p + tw) * pitch + ch.l;
+        const A y = *at - a1 * y1 - a2 * y2;
+        *at = y;
+        y2 = y1;
+        y1 = y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass X: explicit terms, RHS and the x-line solve of eq-fac-1 for a task of
+// `rows` complete x-lines (y0 .. y0+rows-1) marching over the planes
+// z0 .. z0+nzc-1.  Thread tid owns the cells item = tid + nth m (m < MI) of
+// the rows x nx plane tile for the whole march, and keeps for each the
+// column of C at z-3 .. z+3 and the flux through its low z face in
+// registers, so that each z face flux is computed once.  x and y face
+// fluxes are computed once per face and exchanged through LDS.
+//
+// LDS (launch-wide pitches; all sizes from the largest box):
+//   pb: (rmax + 6) x (nx_max + 6) T  C of the plane, rows y0-3 .. y0+rows+2,
+//                                    columns -3 .. nx+2
+//   fx: rmax x (nx_max + 1) T        flux through x face f of each row
+//   fy: (rmax + 1) x nx_max T        flux through y face y0 + r
+//   tb: (nx_max + 2 tw_max) x (rmax + 1) A   RHS -> solve tile
+// ---------------------------------------------------------------------------
+struct XLayout {
+    size_t pb, fx, fy, tb, total;  // byte offsets and total size
+    int pbp, fxp, fyp, tbp;        // pitches (elements)
+};
+
+CH_HD size_t al16(size_t b) { return (b + 15) & ~size_t(15); }
+
+CH_HD XLayout x_layout(int nx_max, int rmax, int tw_max, int sT, int sA)
+{
+    XLayout L;
+    L.pbp = nx_max + 6;
+    L.fxp = nx_max + 1;
+    L.fyp = nx_max;
+    L.tbp = rmax + 1;
+    L.pb = 0;
+    L.fx = al16(L.pb + (size_t)(rmax + 6) * L.pbp * sT);
+    L.fy = al16(L.fx + (size_t)rmax * L.fxp * sT);
+    L.tb = al16(L.fy + (size_t)(rmax + 1) * L.fyp * sT);
+    L.total = al16(L.tb + (size_t)(nx_max + 2 * tw_max) * L.tbp * sA);
+    return L;
+}
+
+struct XZTask {
+    int z0, nzc, y0, rows;
+};
+
+CH_HD XZTask xz_task(const BoxDesc& bd, int task)
+{
+    XZTask t;
+    const int local = task - bd.task0[PASS_X];
+    const int R = bd.x_rows;
+    const int nyb = (bd.n[1] + R - 1) / R;
+    const int zc = local / nyb;
+    const int yb = local - zc * nyb;
+    t.y0 = yb * R;
+    t.rows = bd.n[1] - t.y0 < R ? bd.n[1] - t.y0 : R;
+    t.z0 = zc * bd.zc;
+    t.nzc = bd.n[2] - t.z0 < bd.zc ? bd.n[2] - t.z0 : bd.zc;
+    return t;
+}
+
+template <typename T, typename A, int MI>
+struct XState {
+    T cz[MI][7];     // C at z-3 .. z+3 of each owned cell
+    T fzl[MI];       // flux through the low z face of the current plane
+    T pz[MI];        // z flux difference of the current plane
+    T plap[MI];      // sum of second differences of psi'(C)
+    T pb4[MI];       // sum of fourth differences of C
+    int rx[MI];      // (row << 16) | x of each owned cell, -1 if none
+    LineState<A> ls;
+};
+
+template <typename T, typename A, int MI, class X>
+CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const PassArgs& pa,
+                          int task, const T* __restrict__ C, const T* __restrict__ U,
+                          const T* __restrict__ V, const T* __restrict__ W, T* __restrict__ E,
+                          T* __restrict__ Q, unsigned char* smem)
+{
+    const XZTask t = xz_task(bd, task);
+    const int nx = bd.n[0], ny = bd.n[1], nz = bd.n[2];
+    const int fx = bd.nf[0], fy = bd.nf[1];
+    const int k = pa.k, tw = bd.tw[k];
+    const int nth = ex.nth;
+    const XLayout L = x_layout(pa.nx_max, pa.rmax, pa.tw_max, (int)sizeof(T), (int)sizeof(A));
+    T* pb = reinterpret_cast<T*>(smem + L.pb);
+    T* fxb = reinterpret_cast<T*>(smem + L.fx);
+    T* fyb = reinterpret_cast<T*>(smem + L.fy);
+    A* tb = reinterpret_cast<A*>(smem + L.tb);
+    const int64_t plane = (int64_t)nx * ny;
+    const T* Cb = C + bd.c_off;
+    const T* Ub = U + bd.u_off;
+    const T* Vb = V + bd.v_off;
+    const T* Wb = W + bd.w_off;
+    T* Eb = E + bd.c_off;
+    T* Qb = Q + bd.c_off;
+    const T eps = T(bd.eps);
+    const T gdt = T(bd.gdt[k]), rdt = T(bd.rdt[k]), bdt = T(bd.bdt[k]);
+    const T inv_h = T(bd.inv_h), lap_s = T(bd.inv_h2 * bd.inv_pe);
+    const A a1 = A(bd.a1[k]), a2 = A(bd.a2[k]), ic = A(bd.ic[k]);
+    const int rows = t.rows;
+    const int ncell = rows * nx;
+
+    // owned cells
+    ex.phase([&](int tid) {
+        XState<T, A, MI>& s = st[ex.slot(tid)];
+#pragma unroll
+        for (int m = 0; m < MI; ++m) {
+            const int item = tid + nth * m;
+            s.rx[m] = item < ncell ? ((item / nx) << 16) | (item % nx) : -1;
+        }
+    });
+
+    for (int zs = 0; zs < t.nzc; ++zs) {
+        const int z = t.z0 + zs;
+        // ---- load: C columns (queue), the plane tile with its halos
+        ex.phase([&](int tid) {
+            XState<T, A, MI>& s = st[ex.slot(tid)];
+    #pragma unroll
+        for (int m = 0; m < MI; ++m) {
+                if (s.rx[m] < 0) continue;
+                const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
+                const int64_t col = (int64_t)(t.y0 + r) * nx + x;
+                if (zs == 0) {
+#pragma unroll
+                    for (int q = 0; q < 7; ++q)
+                        s.cz[m][q] = Cb[(int64_t)map_idx(z - 3 + q, nz, bd.bc[2]) * plane + col];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) s.cz[m][q] = s.cz[m][q + 1];
+                    s.cz[m][6] = Cb[(int64_t)map_idx(z + 3, nz, bd.bc[2]) * plane + col];
+                }
+                pb[(r + 3) * L.pbp + x + 3] = s.cz[m][3];
+            }
+            const int64_t zp = (int64_t)z * plane;
+            // rows y0-3 .. y0-1 and y0+rows .. y0+rows+2
+            for (int hr = 0; hr < 6; ++hr) {
+                const int prow = hr < 3 ? hr : rows + hr;
+                const int gy = map_idx(t.y0 - 3 + prow, ny, bd.bc[1]);
+                for (int x = tid; x < nx; x += nth)
+                    pb[prow * L.pbp + x + 3] = Cb[zp + (int64_t)gy * nx + x];
+            }
+            // columns -3..-1 and nx..nx+2 of every tile row
+            for (int j = tid; j < 6 * (rows + 6); j += nth) {
+                const int prow = j / 6, q = j - prow * 6;
+                const int xc = q < 3 ? q - 3 : nx + q - 3;
+                const int gy = map_idx(t.y0 - 3 + prow, ny, bd.bc[1]);
+                pb[prow * L.pbp + xc + 3] = Cb[zp + (int64_t)gy * nx + map_idx(xc, nx, bd.bc[0])];
+            }
+        });
+        // ---- faces, Laplacian of psi'(C), fourth differences
+        ex.phase([&](int tid) {
+            XState<T, A, MI>& s = st[ex.slot(tid)];
+    #pragma unroll
+        for (int m = 0; m < MI; ++m) {
+                if (s.rx[m] < 0) continue;
+                const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
+                const int y = t.y0 + r;
+                const T* row = pb + (r + 3) * L.pbp + x + 3;   // row[o] = C(x + o)
+                const T* colm = pb + r * L.pbp + x + 3;        // colm[o * pbp] = C(y - 3 + o)
+                // x: the low face of the cell, and face nx for the last cell
+                const int64_t ur = ((int64_t)z * ny + y) * fx;
+                {
+                    const T ul = Ub[ur + x];
+                    fxb[r * L.fxp + x] =
+                        ul * face_weno<T>(ul, row[-3], row[-2], row[-1], row[0], row[1], row[2], eps);
+                    if (x == nx - 1) {
+                        const T uh = Ub[ur + (bd.bc[0] == 0 ? 0 : nx)];
+                        fxb[r * L.fxp + nx] = uh * face_weno<T>(uh, row[-2], row[-1], row[0],
+                                                                 row[1], row[2], row[3], eps);
+                    }
+                }
+                // y: the low face, and the top face for the last row
+                const int p = L.pbp;
+                {
+                    const T vl = Vb[((int64_t)z * fy + y) * nx + x];
+                    fyb[r * L.fyp + x] = vl * face_weno<T>(vl, colm[0], colm[p], colm[2 * p],
+                                                           colm[3 * p], colm[4 * p], colm[5 * p], eps);
+                    if (r == rows - 1) {
+                        const int yh = (y + 1 == ny && bd.bc[1] == 0) ? 0 : y + 1;
+                        const T vh = Vb[((int64_t)z * fy + yh) * nx + x];
+                        fyb[(r + 1) * L.fyp + x] =
+                            vh * face_weno<T>(vh, colm[p], colm[2 * p], colm[3 * p], colm[4 * p],
+                                              colm[5 * p], colm[6 * p], eps);
+                    }
+                }
+                // z: the high face (the low one carries over from the plane below)
+                const T* c = s.cz[m];
+                {
+                    const int64_t wc = (int64_t)y * nx + x;
+                    if (zs == 0) {
+                        const T wl = Wb[(int64_t)z * plane + wc];
+                        s.fzl[m] = wl * face_weno<T>(wl, c[0], c[1], c[2], c[3], c[4], c[5], eps);
+                    }
+                    const int zh = (z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1;
+                    const T wh = Wb[(int64_t)zh * plane + wc];
+                    const T fzh = wh * face_weno<T>(wh, c[1], c[2], c[3], c[4], c[5], c[6], eps);
+                    s.pz[m] = fzh - s.fzl[m];
+                    s.fzl[m] = fzh;
+                }
+                const T mu0 = psi_prime<T>(bd.psi, c[3]);
+                s.plap[m] = (psi_prime<T>(bd.psi, row[1]) - mu0) - (mu0 - psi_prime<T>(bd.psi, row[-1]))
+                          + (psi_prime<T>(bd.psi, colm[4 * p]) - mu0)
+                          - (mu0 - psi_prime<T>(bd.psi, colm[2 * p]))
+                          + (psi_prime<T>(bd.psi, c[4]) - mu0) - (mu0 - psi_prime<T>(bd.psi, c[2]));
+                s.pb4[m] = d4<T>(row[-2], row[-1], row[0], row[1], row[2])
+                         + d4<T>(colm[p], colm[2 * p], colm[3 * p], colm[4 * p], colm[5 * p])
+                         + d4<T>(c[1], c[2], c[3], c[4], c[5]);
+            }
+        });
+        // ---- RHS into the solve tile
+        ex.phase([&](int tid) {
+            XState<T, A, MI>& s = st[ex.slot(tid)];
+    #pragma unroll
+        for (int m = 0; m < MI; ++m) {
+                if (s.rx[m] < 0) continue;
+                const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
+                const T adv = (fxb[r * L.fxp + x + 1] - fxb[r * L.fxp + x])
+                            + (fyb[(r + 1) * L.fyp + x] - fyb[r * L.fyp + x]) + s.pz[m];
+                const T e = -adv * inv_h + s.plap[m] * lap_s;
+                const int64_t at = (int64_t)z * plane + (int64_t)(t.y0 + r) * nx + x;
+                T rhs = gdt * e - bdt * s.pb4[m];
+                if (pa.e_mode != 0) rhs += rdt * Eb[at];
+                if (pa.e_mode != 2) Eb[at] = e;
+                tb[(x + tw) * L.tbp + r] = A(rhs);
+            }
+        });
+        // ---- halo of the solve tile
+        ex.phase([&](int tid) {
+            const int span = 2 * tw;
+            for (int j = tid; j < rows * span; j += nth) {
+                const int r = j / span, q = j - r * span;
+                const int pp = q < tw ? q - tw : nx + q - tw;
+                tb[(pp + tw) * L.tbp + r] = tb[(map_idx(pp, nx, bd.bc[0]) + tw) * L.tbp + r];
+            }
+        });
+        // ---- x solve
+        ex.phase([&](int tid) {
+            const Chunk ch = line_chunk(tid, nth, rows, nx, tw, pa.kmin);
+            line_f1<A>(ch, tb, L.tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+        });
+        ex.phase([&](int tid) {
+            const Chunk ch = line_chunk(tid, nth, rows, nx, tw, pa.kmin);
+            line_f2<A>(ch, tb, L.tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+        });
+        ex.phase([&](int tid) {
+            const Chunk ch = line_chunk(tid, nth, rows, nx, tw, pa.kmin);
+            line_b1<A>(ch, tb, L.tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+        });
+        ex.phase([&](int tid) {
+            const Chunk ch = line_chunk(tid, nth, rows, nx, tw, pa.kmin);
+            line_b2<A>(ch, tb, L.tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+        });
+        // ---- store q
+        ex.phase([&](int tid) {
+            XState<T, A, MI>& s = st[ex.slot(tid)];
+    #pragma unroll
+        for (int m = 0; m < MI; ++m) {
+                if (s.rx[m] < 0) continue;
+                const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
+                Qb[(int64_t)z * plane + (int64_t)(t.y0 + r) * nx + x] = T(tb[(x + tw) * L.tbp + r]);
+            }
+        });
     }
 }
 
 // ---------------------------------------------------------------------------
 // Passes Y and Z: line solves of eq-fac-2 (q1 -> q2) and eq-fac-3
 // (q2 -> dC, C += dC) for a task of `lanes` adjacent x columns and one
-// segment [s0, s0 + len) of the line.  Lane l holds column x0 + l.  The
-// forward recurrence reads q straight from global memory (coalesced across
-// lanes) and keeps its values in LDS, wb[p * lanes + l] for 0 <= p < len + tw;
-// the backward recurrence writes the result.
+// segment [s0, s0 + len) of the line.  The segment and a warm-up halo of tw
+// positions on each side are staged in LDS (coalesced rows of lanes
+// elements), solved in place, and written back.
+// LDS: (seg_max + 2 tw_max) x lanes A.
 // ---------------------------------------------------------------------------
 struct LTask {
     int plane;      // z (pass Y) or y (pass Z)
-    int x0, s0, len, n, tw, bc;
+    int x0, s0, len, n, bc;
     int64_t stride; // elements between consecutive line positions
     int64_t base;   // element of (x0, position 0) of this line family
 };
@@ -363,23 +562,21 @@ struct LTask {
 CH_HD LTask l_task(const BoxDesc& bd, const PassArgs& pa, int pass, int task)
 {
     LTask t;
-    const int L = pa.lanes;
+    const int Lw = pa.lanes;
     const int nx = bd.n[0], ny = bd.n[1];
-    const int axis = pass;                       // 1 = y, 2 = z
-    const int n = bd.n[axis];
-    const int S = bd.seg[axis - 1];
-    const int nxb = (nx + L - 1) / L;
+    const int n = bd.n[pass];
+    const int S = bd.seg[pass - 1];
+    const int nxb = (nx + Lw - 1) / Lw;
     const int nseg = (n + S - 1) / S;
     const int local = task - bd.task0[pass];
     t.plane = local / (nxb * nseg);
     const int rem = local - t.plane * (nxb * nseg);
     const int seg = rem / nxb;
-    t.x0 = (rem - seg * nxb) * L;
+    t.x0 = (rem - seg * nxb) * Lw;
     t.s0 = seg * S;
     t.len = n - t.s0 < S ? n - t.s0 : S;
     t.n = n;
-    t.tw = bd.tw[pa.k];
-    t.bc = bd.bc[axis];
+    t.bc = bd.bc[pass];
     const int64_t plane = (int64_t)nx * ny;
     if (pass == PASS_Y) {
         t.stride = nx;
@@ -391,54 +588,50 @@ CH_HD LTask l_task(const BoxDesc& bd, const PassArgs& pa, int pass, int task)
     return t;
 }
 
-template <typename T, typename A>
-CH_HD void l_phase_fwd(int tid, int nth, const BoxDesc& bd, const PassArgs& pa, const LTask& t,
-                       const T* __restrict__ Qin, A* wb)
+template <typename T, typename A, class X>
+CH_HD void pass_line_program(X& ex, LineState<A>* st, const BoxDesc& bd, const PassArgs& pa,
+                             int pass, int task, const T* __restrict__ Qin,
+                             T* __restrict__ Qout, unsigned char* smem)
 {
-    const int L = pa.lanes, k = pa.k;
-    const int lane = tid % L, wv = tid / L, nw = nth / L;
-    const int total = t.len + t.tw;
-    const int kf = (total + nw - 1) / nw;
-    const int c0 = wv * kf;
-    const int c1 = c0 + kf < total ? c0 + kf : total;
-    if (c0 >= c1) return;
-    const bool live = t.x0 + lane < bd.n[0];
+    const LTask t = l_task(bd, pa, pass, task);
+    const int Lw = pa.lanes, nth = ex.nth, k = pa.k, tw = bd.tw[k];
+    const int nlive = bd.n[0] - t.x0 < Lw ? bd.n[0] - t.x0 : Lw;
     const A a1 = A(bd.a1[k]), a2 = A(bd.a2[k]), ic = A(bd.ic[k]);
-    A w1 = A(0), w2 = A(0);
-    for (int p = c0 - t.tw; p < c1; ++p) {
-        const int g = map_idx(t.s0 + p, t.n, t.bc);
-        const A b = live ? A(Qin[t.base + (int64_t)g * t.stride + lane]) : A(0);
-        const A w = b * ic - a1 * w1 - a2 * w2;
-        if (p >= c0) wb[p * L + lane] = w;
-        w2 = w1;
-        w1 = w;
-    }
-}
-
-// mode 0: Qout = y (pass Y); mode 1: Qout += y (pass Z, Qout = C)
-template <typename T, typename A>
-CH_HD void l_phase_bwd(int tid, int nth, const BoxDesc& bd, const PassArgs& pa, const LTask& t,
-                       const A* wb, T* __restrict__ Qout, int mode)
-{
-    const int L = pa.lanes, k = pa.k;
-    const int lane = tid % L, wv = tid / L, nw = nth / L;
-    const int kb = (t.len + nw - 1) / nw;
-    const int c0 = wv * kb;
-    const int e = c0 + kb < t.len ? c0 + kb : t.len;
-    if (c0 >= e) return;
-    const bool live = t.x0 + lane < bd.n[0];
-    const A a1 = A(bd.a1[k]), a2 = A(bd.a2[k]);
-    A y1 = A(0), y2 = A(0);
-    for (int p = e + t.tw - 1; p >= c0; --p) {
-        const A y = wb[p * L + lane] - a1 * y1 - a2 * y2;
-        if (p < e && live) {
-            T* dst = Qout + t.base + (int64_t)(t.s0 + p) * t.stride + lane;
-            if (mode == 0) *dst = T(y);
-            else *dst = T(A(*dst) + y);
+    A* tile = reinterpret_cast<A*>(smem);
+    const int npos = t.len + 2 * tw;
+    ex.phase([&](int tid) {
+        const int l = tid % Lw;
+        for (int q = tid / Lw; q < npos; q += nth / Lw) {
+            const int g = map_idx(t.s0 + q - tw, t.n, t.bc);
+            tile[q * Lw + l] = l < nlive ? A(Qin[t.base + (int64_t)g * t.stride + l]) : A(0);
         }
-        y2 = y1;
-        y1 = y;
-    }
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nth, Lw, t.len, tw, pa.kmin);
+        line_f1<A>(ch, tile, Lw, tw, a1, a2, ic, st[ex.slot(tid)]);
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nth, Lw, t.len, tw, pa.kmin);
+        line_f2<A>(ch, tile, Lw, tw, a1, a2, ic, st[ex.slot(tid)]);
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nth, Lw, t.len, tw, pa.kmin);
+        line_b1<A>(ch, tile, Lw, tw, a1, a2, st[ex.slot(tid)]);
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nth, Lw, t.len, tw, pa.kmin);
+        line_b2<A>(ch, tile, Lw, tw, a1, a2, st[ex.slot(tid)]);
+    });
+    ex.phase([&](int tid) {
+        const int l = tid % Lw;
+        if (l >= nlive) return;
+        for (int q = tid / Lw; q < t.len; q += nth / Lw) {
+            T* dst = Qout + t.base + (int64_t)(t.s0 + q) * t.stride + l;
+            const A y = tile[(q + tw) * Lw + l];
+            if (pass == PASS_Z) *dst = T(A(*dst) + y);
+            else *dst = T(y);
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------

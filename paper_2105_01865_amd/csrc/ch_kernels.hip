@@ -27,10 +27,8 @@ __device__ __forceinline__ int xcd_task(int wg, int nwg)
     return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + l;
 }
 
-__device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
-
-template <typename T, typename A>
-__global__ void __launch_bounds__(256)
+template <typename T, typename A, int MI>
+__global__ void __launch_bounds__(1024)
 k_pass_x(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
          const T* __restrict__ C, const T* __restrict__ U, const T* __restrict__ V,
          const T* __restrict__ W, T* __restrict__ E, T* __restrict__ Q)
@@ -38,21 +36,9 @@ k_pass_x(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
     extern __shared__ __align__(16) unsigned char smem[];
     const int task = xcd_task(blockIdx.x, gridDim.x);
     const int b = chd::find_box(boxes, nbox, chd::PASS_X, task);
-    const chd::BoxDesc& bd = boxes[b];
-    const chd::XTask t = chd::x_task(bd, pa, task);
-    T* tb = reinterpret_cast<T*>(smem);
-    A* twb = reinterpret_cast<A*>(
-        smem + align16(size_t(pa.nx_max + 2 * pa.tw_max) * pa.rp * sizeof(T)));
-    const int tid = threadIdx.x, nth = blockDim.x;
-    chd::x_phase_rhs<T>(tid, nth, bd, pa, t, C, U, V, W, E, tb);
-    __syncthreads();
-    chd::x_phase_halo<T>(tid, nth, bd, pa, t, tb);
-    __syncthreads();
-    chd::x_phase_fwd<T, A>(tid, nth, bd, pa, t, tb, twb);
-    __syncthreads();
-    chd::x_phase_bwd<T, A>(tid, nth, bd, pa, t, tb, twb);
-    __syncthreads();
-    chd::x_phase_store<T>(tid, nth, bd, pa, t, tb, Q);
+    chd::GpuExec ex{(int)threadIdx.x, (int)blockDim.x};
+    chd::XState<T, A, MI> st;
+    chd::pass_x_program<T, A, MI>(ex, &st, boxes[b], pa, task, C, U, V, W, E, Q, smem);
 }
 
 template <typename T, typename A, int PASS>
@@ -63,13 +49,9 @@ k_pass_line(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
     extern __shared__ __align__(16) unsigned char smem[];
     const int task = xcd_task(blockIdx.x, gridDim.x);
     const int b = chd::find_box(boxes, nbox, PASS, task);
-    const chd::BoxDesc& bd = boxes[b];
-    const chd::LTask t = chd::l_task(bd, pa, PASS, task);
-    A* wb = reinterpret_cast<A*>(smem);
-    const int tid = threadIdx.x, nth = blockDim.x;
-    chd::l_phase_fwd<T, A>(tid, nth, bd, pa, t, Qin, wb);
-    __syncthreads();
-    chd::l_phase_bwd<T, A>(tid, nth, bd, pa, t, wb, Qout, PASS == chd::PASS_Z ? 1 : 0);
+    chd::GpuExec ex{(int)threadIdx.x, (int)blockDim.x};
+    chd::LineState<A> st;
+    chd::pass_line_program<T, A>(ex, &st, boxes[b], pa, PASS, task, Qin, Qout, smem);
 }
 
 // Mass, stage 1: one fixed block of C per work-group, summed in double in a
@@ -201,19 +183,29 @@ k_interp(const T* __restrict__ src, int64_t sx, int64_t sy, int64_t tnx, int64_t
 // ---------------------------------------------------------------------------
 // host-side launchers (declared in ch_kernels.h)
 // ---------------------------------------------------------------------------
-template <typename T, typename A>
-hipError_t launch_pass_x(int nwg, size_t lds, hipStream_t st, const chd::BoxDesc* boxes,
-                         int nbox, const chd::PassArgs& pa, const void* C, const void* U,
-                         const void* V, const void* W, void* E, void* Q)
+template <typename T, typename A, int MI>
+static hipError_t launch_x(int nwg, int nth, size_t lds, hipStream_t st, const chd::BoxDesc* boxes,
+                           int nbox, const chd::PassArgs& pa, const void* C, const void* U,
+                           const void* V, const void* W, void* E, void* Q)
 {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)&k_pass_x<T, A>,
+        hipError_t e = hipFuncSetAttribute((const void*)&k_pass_x<T, A, MI>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_pass_x<T, A>), dim3(nwg), dim3(256), lds, st, boxes, nbox, pa,
+    hipLaunchKernelGGL((k_pass_x<T, A, MI>), dim3(nwg), dim3(nth), lds, st, boxes, nbox, pa,
                        (const T*)C, (const T*)U, (const T*)V, (const T*)W, (T*)E, (T*)Q);
     return hipGetLastError();
+}
+
+template <typename T, typename A>
+hipError_t launch_pass_x(int mi, int nwg, int nth, size_t lds, hipStream_t st,
+                         const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
+                         const void* C, const void* U, const void* V, const void* W, void* E,
+                         void* Q)
+{
+    if (mi == 1) return launch_x<T, A, 1>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    return launch_x<T, A, 2>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
 }
 
 template <typename T, typename A>
@@ -274,7 +266,8 @@ hipError_t launch_interp(hipStream_t st, const void* src, int64_t sx, int64_t sy
 }
 
 #define CH_INSTANTIATE(T, A)                                                                    \
-    template hipError_t launch_pass_x<T, A>(int, size_t, hipStream_t, const chd::BoxDesc*, int, \
+    template hipError_t launch_pass_x<T, A>(int, int, int, size_t, hipStream_t,                 \
+                                            const chd::BoxDesc*, int,                           \
                                             const chd::PassArgs&, const void*, const void*,     \
                                             const void*, const void*, void*, void*);            \
     template hipError_t launch_pass_line<T, A>(int, int, int, size_t, hipStream_t,              \

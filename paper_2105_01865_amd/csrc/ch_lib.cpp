@@ -171,7 +171,7 @@ hipEvent_t take_event(Engine& e)
 template <typename T, typename A>
 hipError_t enqueue_substage(Engine& e, int k, const void* u, const void* v, const void* w)
 {
-    const chd::PassArgs pa = chp::pass_args(e.P, k);
+    
     for (int p = 0; p < 3; ++p) {
         hipEvent_t a = nullptr, b = nullptr;
         if (e.prof) {
@@ -180,15 +180,17 @@ hipError_t enqueue_substage(Engine& e, int k, const void* u, const void* v, cons
             if (a) (void)hipEventRecord(a, e.stream);
         }
         hipError_t err;
+        const chd::PassArgs pa = chp::pass_args(e.P, k, p);
         if (p == 0)
-            err = chk::launch_pass_x<T, A>(e.P.ntask[0], e.P.lds[0], e.stream, e.d_boxes, e.P.nbox, pa,
+            err = chk::launch_pass_x<T, A>(e.P.mi, e.P.ntask[0], e.P.x_threads, e.P.lds[0],
+                                           e.stream, e.d_boxes, e.P.nbox, pa,
                                            e.C, u, v, w, e.E, e.qa);
         else if (p == 1)
-            err = chk::launch_pass_line<T, A>(chd::PASS_Y, e.P.ntask[1], e.P.lanes * e.P.chains,
+            err = chk::launch_pass_line<T, A>(chd::PASS_Y, e.P.ntask[1], e.P.yz_threads,
                                               e.P.lds[1], e.stream, e.d_boxes, e.P.nbox, pa, e.qa,
                                               e.qb);
         else
-            err = chk::launch_pass_line<T, A>(chd::PASS_Z, e.P.ntask[2], e.P.lanes * e.P.chains,
+            err = chk::launch_pass_line<T, A>(chd::PASS_Z, e.P.ntask[2], e.P.yz_threads,
                                               e.P.lds[2], e.stream, e.d_boxes, e.P.nbox, pa, e.qb,
                                               e.C);
         if (e.prof && a && b) {
@@ -573,16 +575,17 @@ ch_status ch_profile_read(ch_state* s, int kernel, double* total_ms, int64_t* la
     return profile_read(s->e, kernel, total_ms, launches);
 }
 
-ch_status ch_get_config(const ch_state* s, int cfg[7])
+ch_status ch_get_config(const ch_state* s, int cfg[8])
 {
     CHECK_STATE(s);
     if (!cfg) return fail(CH_EINVAL, "null output");
-    const Engine& e = s->e;
-    cfg[0] = e.P.x_rows;
-    cfg[1] = e.P.seg_cap;
-    cfg[2] = e.P.chains;
-    for (int k = 0; k < 3; ++k) cfg[3 + k] = e.P.boxes[0].tw[k];
-    cfg[6] = e.P.acc64 ? 1 : 0;
+    const chp::Plan& P = s->e.P;
+    cfg[0] = P.x_rows;
+    cfg[1] = P.seg_cap;
+    cfg[2] = P.yz_threads;
+    for (int k = 0; k < 3; ++k) cfg[3 + k] = P.boxes[0].tw[k];
+    cfg[6] = P.acc64 ? 1 : 0;
+    cfg[7] = P.zc;
     return CH_OK;
 }
 

@@ -24,6 +24,10 @@ constexpr double RK_R[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 
 constexpr size_t LDS_BUDGET = 64 * 1024;   // default per work-group
 constexpr size_t LDS_HARD = 160 * 1024;    // gfx950 LDS per CU
+constexpr int X_MAX_THREADS = 1024;        // largest x-pass work-group
+
+// cells of an x-pass plane tile per thread: one, two for very long x lines
+inline int x_items(int nx) { return nx > X_MAX_THREADS ? 2 : 1; }
 
 // Factor 1 + r (z - 2 + 1/z)^2 = c (1 + a1/z + a2/z^2)(1 + a1 z + a2 z^2)
 // and choose the warm-up length: the smallest T for which the response of
@@ -88,7 +92,8 @@ struct Plan {
     double dt = NAN;
     bool acc64 = true;
     int tw_max = 0;
-    int x_rows = 0, lanes = 64, chains = 4, seg_cap = 0;
+    int x_rows = 0, x_threads = 256, zc = 1, mi = 1, lanes = 32, yz_threads = 256, seg_cap = 0;
+    int kmin = 1;
     int ntask[3] = {0, 0, 0};
     size_t lds[3] = {0, 0, 0};
     int nx_max = 0, seg_max[2] = {0, 0};
@@ -129,7 +134,8 @@ inline ch_status plan_init(Plan& P, int nbox, const ch_grid* g, const double* Cn
         return P.fail(CH_EINVAL, "weno_eps must be > 0 and finite");
     if (o.solve_fp64 < CH_SOLVE_AUTO || o.solve_fp64 > CH_SOLVE_NATIVE)
         return P.fail(CH_EINVAL, "unknown solve_fp64 mode");
-    if (o.x_rows < 0 || o.x_rows > 64 || o.seg_len < 0 || o.waves_yz < 0 || o.waves_yz > 8)
+    if (o.x_rows < 0 || o.x_rows > 64 || o.seg_len < 0 || o.waves_yz < 0 || o.waves_yz > 8 ||
+        o.z_chunk < 0)
         return P.fail(CH_EINVAL, "launch options out of range");
     if (o.precision == CH_FP64 && o.solve_fp64 == CH_SOLVE_NATIVE) o.solve_fp64 = CH_SOLVE_FP64;
     P.nbox = nbox;
@@ -232,21 +238,51 @@ inline ch_status plan_dt(Plan& P, double dt)
     P.acc64 = P.prec == CH_FP64 || P.opt.solve_fp64 == CH_SOLVE_FP64 ||
               (P.opt.solve_fp64 == CH_SOLVE_AUTO && rmax > 0.25);
     const size_t sT = esize(P.prec), sA = P.acc64 ? 8 : 4;
-    P.lanes = sT == 8 ? 32 : 64;
-    P.chains = P.opt.waves_yz > 0 ? P.opt.waves_yz : 4;
-    while (P.lanes * P.chains > 512) --P.chains;
     int nxm = 0, nym = 0, lmax = 0;
+    int64_t cells = 0;
     for (int b = 0; b < P.nbox; ++b) {
         nxm = std::max(nxm, P.boxes[b].n[0]);
         nym = std::max(nym, P.boxes[b].n[1]);
         lmax = std::max({lmax, P.boxes[b].n[1], P.boxes[b].n[2]});
+        cells += (int64_t)P.boxes[b].n[0] * P.boxes[b].n[1] * P.boxes[b].n[2];
     }
     P.nx_max = nxm;
-    // y/z segment: the whole line if it fits in the budget, else the line
-    // split into equal segments that do
+    P.mi = x_items(nxm);
+    const int xcap = X_MAX_THREADS * P.mi;
+    if (nxm > xcap) return P.fail(CH_EUNSUPPORTED, "x extent too large");
+    P.kmin = std::max(1, P.tw_max);
+    // ---- x pass: rows per task and planes per task
+    int R = P.opt.x_rows;
+    if (R == 0) {
+        const int cand[] = {16, 12, 8, 6, 4, 3, 2, 1};
+        for (int c : cand)
+            if (c <= std::max(1, nym) && c * nxm <= xcap &&
+                chd::x_layout(nxm, c, P.tw_max, (int)sT, (int)sA).total <= LDS_BUDGET) {
+                R = c;
+                break;
+            }
+        if (R == 0) R = 1;
+    }
+    if (R * nxm > xcap) return P.fail(CH_EINVAL, "x_rows too large for the x extent");
+    if (chd::x_layout(nxm, R, P.tw_max, (int)sT, (int)sA).total > LDS_HARD)
+        return P.fail(CH_EUNSUPPORTED, "x lines too long for LDS");
+    P.x_rows = R;
+    P.x_threads = ((R * nxm + P.mi - 1) / P.mi + 63) / 64 * 64;
+    int zc = P.opt.z_chunk;
+    if (zc == 0) {
+        // enough tasks to fill the chip a few times over, marching as far as
+        // that allows (each task reloads 6 planes to start its march)
+        const int64_t rows_total = cells / std::max(1, nxm);
+        const int64_t want = 2048;
+        zc = (int)std::max<int64_t>(1, std::min<int64_t>(32, rows_total / R / want));
+    }
+    P.zc = zc;
+    // ---- y/z passes: lanes of 128 bytes, whole lines when they fit
+    P.lanes = (int)(128 / sA);
+    P.yz_threads = 64 * (P.opt.waves_yz > 0 ? P.opt.waves_yz : 4);
     int seg = P.opt.seg_len > 0 ? P.opt.seg_len
-                                : (int)(LDS_BUDGET / (P.lanes * sA)) - P.tw_max;
-    if (seg < 16) seg = (int)(LDS_HARD / (P.lanes * sA)) - P.tw_max;
+                                : (int)(LDS_BUDGET / (P.lanes * sA)) - 2 * P.tw_max;
+    if (seg < 16) seg = (int)(LDS_HARD / (P.lanes * sA)) - 2 * P.tw_max;
     if (seg < 1) return P.fail(CH_EUNSUPPORTED, "line-solve warm-up too long");
     if (P.opt.seg_len == 0 && seg < lmax) {
         const int nseg = (lmax + seg - 1) / seg;
@@ -254,36 +290,19 @@ inline ch_status plan_dt(Plan& P, double dt)
     }
     seg = std::min(seg, lmax);
     P.seg_cap = seg;
-    auto x_lds = [&](int R) {
-        const size_t rp = (size_t)R + 1;
-        size_t a = (size_t)(nxm + 2 * P.tw_max) * rp * sT;
-        a = (a + 15) & ~size_t(15);
-        return a + (size_t)(nxm + P.tw_max) * rp * sA;
-    };
-    int R = P.opt.x_rows;
-    if (R == 0) {
-        const int cand[] = {16, 8, 4, 2, 1};
-        for (int c : cand)
-            if (c <= std::max(1, nym) && x_lds(c) <= LDS_BUDGET) {
-                R = c;
-                break;
-            }
-        if (R == 0) R = 1;
-    }
-    if (x_lds(R) > LDS_HARD) return P.fail(CH_EUNSUPPORTED, "x lines too long for LDS");
-    P.x_rows = R;
     int64_t t0[3] = {0, 0, 0};
     P.seg_max[0] = P.seg_max[1] = 0;
     for (int b = 0; b < P.nbox; ++b) {
         chd::BoxDesc& d = P.boxes[b];
         const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
         d.x_rows = std::min(R, ny);
+        d.zc = std::min(zc, nz);
         d.seg[0] = std::min(seg, ny);
         d.seg[1] = std::min(seg, nz);
         P.seg_max[0] = std::max(P.seg_max[0], d.seg[0]);
         P.seg_max[1] = std::max(P.seg_max[1], d.seg[1]);
         const int64_t nxb = (nx + P.lanes - 1) / P.lanes;
-        const int64_t tt[3] = {(int64_t)nz * ((ny + d.x_rows - 1) / d.x_rows),
+        const int64_t tt[3] = {(int64_t)((nz + d.zc - 1) / d.zc) * ((ny + d.x_rows - 1) / d.x_rows),
                                (int64_t)nz * nxb * ((ny + d.seg[0] - 1) / d.seg[0]),
                                (int64_t)ny * nxb * ((nz + d.seg[1] - 1) / d.seg[1])};
         for (int p = 0; p < 3; ++p) {
@@ -295,33 +314,27 @@ inline ch_status plan_dt(Plan& P, double dt)
         }
     }
     for (int p = 0; p < 3; ++p) P.ntask[p] = (int)t0[p];
-    P.lds[0] = x_lds(R);
-    P.lds[1] = (size_t)(P.seg_max[0] + P.tw_max) * P.lanes * sA;
-    P.lds[2] = (size_t)(P.seg_max[1] + P.tw_max) * P.lanes * sA;
+    P.lds[0] = chd::x_layout(nxm, R, P.tw_max, (int)sT, (int)sA).total;
+    P.lds[1] = (size_t)(P.seg_max[0] + 2 * P.tw_max) * P.lanes * sA;
+    P.lds[2] = (size_t)(P.seg_max[1] + 2 * P.tw_max) * P.lanes * sA;
     for (int p = 1; p < 3; ++p)
         if (P.lds[p] > LDS_HARD) return P.fail(CH_EUNSUPPORTED, "line segment too long for LDS");
     P.dt = dt;
     return CH_OK;
 }
 
-inline chd::PassArgs pass_args(const Plan& P, int k)
+inline chd::PassArgs pass_args(const Plan& P, int k, int pass)
 {
     chd::PassArgs pa{};
     pa.k = k;
     pa.e_mode = k;       // substage 1 writes E, 2 reads and writes, 3 reads
     pa.lanes = P.lanes;
-    pa.rp = P.x_rows + 1;
+    pa.rmax = P.x_rows;
     pa.tw_max = P.tw_max;
     pa.nx_max = P.nx_max;
-    pa.kx = 0;
+    pa.seg_max = pass == 2 ? P.seg_max[1] : P.seg_max[0];
+    pa.kmin = P.kmin;
     return pa;
-}
-
-// byte offset of the forward-recurrence buffer in the x pass's LDS
-inline size_t x_lds_split(const Plan& P)
-{
-    const size_t a = (size_t)(P.nx_max + 2 * P.tw_max) * (P.x_rows + 1) * esize(P.prec);
-    return (a + 15) & ~size_t(15);
 }
 
 }  // namespace chp

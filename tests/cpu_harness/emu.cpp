@@ -7,7 +7,7 @@
 // planned size, it checks the kernels' indexing without a GPU.
 //
 // usage: emu PARAMS IN_DIR OUT_DIR
-//   PARAMS: "nbox prec kappa eps solve x_rows seg_len waves dt nsteps" then
+//   PARAMS: "nbox prec kappa eps solve x_rows seg_len waves z_chunk dt nsteps" then
 //           per box "nx ny nz h Cn Pe bcx bcy bcz"
 //   IN_DIR/{C,u,v,w}.bin: packed float64 arrays (the library's layout)
 //   OUT_DIR/C.bin: packed float64 result; OUT_DIR/mass.txt: per-box mass;
@@ -43,6 +43,22 @@ static T* dev_copy(const std::vector<double>& v)
     return p;
 }
 
+template <typename T, typename A, int MI>
+static void run_x(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T* v, const T* w)
+{
+    const chd::BoxDesc* boxes = P.boxes.data();
+    const chd::PassArgs pa = chp::pass_args(P, k, 0);
+    chd::CpuExec ex{P.x_threads};
+    std::vector<chd::XState<T, A, MI>> st(ex.nth);
+    for (int task = 0; task < P.ntask[0]; ++task) {
+        unsigned char* lds = (unsigned char*)malloc(P.lds[0]);
+        memset(lds, 0xff, P.lds[0]);
+        const int b = chd::find_box(boxes, P.nbox, chd::PASS_X, task);
+        chd::pass_x_program<T, A, MI>(ex, st.data(), boxes[b], pa, task, C, u, v, w, E, qa, lds);
+        free(lds);
+    }
+}
+
 template <typename T, typename A>
 static void run(chp::Plan& P, T* C, T* E, T* qa, T* qb, const T* u, const T* v, const T* w,
                 int nsteps)
@@ -50,44 +66,23 @@ static void run(chp::Plan& P, T* C, T* E, T* qa, T* qb, const T* u, const T* v, 
     const chd::BoxDesc* boxes = P.boxes.data();
     for (int s = 0; s < nsteps; ++s)
         for (int k = 0; k < 3; ++k) {
-            const chd::PassArgs pa = chp::pass_args(P, k);
             // pass x
-            for (int task = 0; task < P.ntask[0]; ++task) {
-                unsigned char* lds = (unsigned char*)malloc(P.lds[0]);
-                memset(lds, 0xff, P.lds[0]);
-                T* tb = (T*)lds;
-                A* twb = (A*)(lds + chp::x_lds_split(P));
-                const int b = chd::find_box(boxes, P.nbox, chd::PASS_X, task);
-                const chd::BoxDesc& bd = boxes[b];
-                const chd::XTask t = chd::x_task(bd, pa, task);
-                const int nth = 256;
-                for (int tid = 0; tid < nth; ++tid)
-                    chd::x_phase_rhs<T>(tid, nth, bd, pa, t, C, u, v, w, E, tb);
-                for (int tid = 0; tid < nth; ++tid) chd::x_phase_halo<T>(tid, nth, bd, pa, t, tb);
-                for (int tid = 0; tid < nth; ++tid)
-                    chd::x_phase_fwd<T, A>(tid, nth, bd, pa, t, tb, twb);
-                for (int tid = 0; tid < nth; ++tid)
-                    chd::x_phase_bwd<T, A>(tid, nth, bd, pa, t, tb, twb);
-                for (int tid = 0; tid < nth; ++tid)
-                    chd::x_phase_store<T>(tid, nth, bd, pa, t, tb, qa);
-                free(lds);
-            }
+            if (P.mi == 1) run_x<T, A, 1>(P, k, C, E, qa, u, v, w);
+            else run_x<T, A, 2>(P, k, C, E, qa, u, v, w);
             // passes y, z
             for (int pass = 1; pass <= 2; ++pass) {
+                const chd::PassArgs pa = chp::pass_args(P, k, pass);
                 const T* in = pass == 1 ? qa : qb;
                 T* out = pass == 1 ? qb : C;
-                const int nth = P.lanes * P.chains;
+                chd::CpuExec ex{P.yz_threads};
+                std::vector<chd::LineState<A>> st(ex.nth);
                 for (int task = 0; task < P.ntask[pass]; ++task) {
-                    A* wb = (A*)malloc(P.lds[pass]);
-                    memset((void*)wb, 0xff, P.lds[pass]);
+                    unsigned char* lds = (unsigned char*)malloc(P.lds[pass]);
+                    memset(lds, 0xff, P.lds[pass]);
                     const int b = chd::find_box(boxes, P.nbox, pass, task);
-                    const chd::BoxDesc& bd = boxes[b];
-                    const chd::LTask t = chd::l_task(bd, pa, pass, task);
-                    for (int tid = 0; tid < nth; ++tid)
-                        chd::l_phase_fwd<T, A>(tid, nth, bd, pa, t, in, wb);
-                    for (int tid = 0; tid < nth; ++tid)
-                        chd::l_phase_bwd<T, A>(tid, nth, bd, pa, t, wb, out, pass == 2 ? 1 : 0);
-                    free(wb);
+                    chd::pass_line_program<T, A>(ex, st.data(), boxes[b], pa, pass, task, in, out,
+                                                 lds);
+                    free(lds);
                 }
             }
         }
@@ -147,8 +142,9 @@ static int go(chp::Plan& P, const std::string& in, const std::string& out, int n
     for (double x : m) fprintf(f, "%.17g\n", x);
     fclose(f);
     f = fopen((out + "/plan.txt").c_str(), "w");
-    fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu\n", P.x_rows, P.seg_cap, P.chains, P.tw_max,
-            P.acc64 ? 1 : 0, P.ntask[0], P.ntask[1], P.ntask[2], P.lds[0], P.lds[1], P.lds[2]);
+    fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu %d\n", P.x_rows, P.seg_cap, P.yz_threads,
+            P.tw_max, P.acc64 ? 1 : 0, P.ntask[0], P.ntask[1], P.ntask[2], P.lds[0], P.lds[1],
+            P.lds[2], P.zc);
     fclose(f);
     free(C); free(E); free(qa); free(qb); free(u); free(v); free(w);
     return 0;
@@ -162,10 +158,10 @@ int main(int argc, char** argv)
     }
     FILE* f = fopen(argv[1], "r");
     if (!f) return 2;
-    int nbox, prec, solve, x_rows, seg, waves, nsteps;
+    int nbox, prec, solve, x_rows, seg, waves, zchunk, nsteps;
     double kappa, eps, dt;
-    if (fscanf(f, "%d %d %lf %lf %d %d %d %d %lf %d", &nbox, &prec, &kappa, &eps, &solve,
-               &x_rows, &seg, &waves, &dt, &nsteps) != 10)
+    if (fscanf(f, "%d %d %lf %lf %d %d %d %d %d %lf %d", &nbox, &prec, &kappa, &eps, &solve,
+               &x_rows, &seg, &waves, &zchunk, &dt, &nsteps) != 11)
         return 2;
     std::vector<ch_grid> g(nbox);
     std::vector<double> Cn(nbox), Pe(nbox);
@@ -189,6 +185,7 @@ int main(int argc, char** argv)
     o.x_rows = x_rows;
     o.seg_len = seg;
     o.waves_yz = waves;
+    o.z_chunk = zchunk;
     chp::Plan P;
     if (chp::plan_init(P, nbox, g.data(), Cn.data(), Pe.data(), nullptr, bc.data(), &o) != CH_OK ||
         chp::plan_dt(P, dt) != CH_OK) {

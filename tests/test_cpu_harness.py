@@ -62,13 +62,16 @@ def test_config1_fp64_matches_oracle():
     assert abs(m - oracle.mass(ref, wl.h)) < 1e-13 * abs(m)
 
 
+@pytest.mark.parametrize("zc", [1, 3, 7])
 @pytest.mark.parametrize("shape,bc", [((20, 12, 16), (0, 0, 0)), ((16, 9, 24), (0, 0, 1)),
                                       ((12, 16, 8), (1, 0, 1)), ((1, 24, 16), (0, 0, 0))])
-def test_fp64_matches_oracle_ragged_and_walls(shape, bc):
+def test_fp64_matches_oracle_ragged_and_walls(shape, bc, zc):
     b = _box(shape, bc=bc, seed=1, amp=2.0)
     dt = 2e-4
-    # odd row counts and short segments force ragged tiles and segmented lines
-    out, masses, plan = run_emu([b], dt, 2, x_rows=3, seg=5, waves=3)
+    # odd row counts, ragged z chunks and short segments force ragged tiles,
+    # partial marches and segmented lines
+    out, masses, plan = run_emu([b], dt, 2, x_rows=3, seg=5, waves=3, z_chunk=zc)
+    assert plan["z_chunk"] == zc
     ref = _oracle(b, dt, 2)
     assert _rel(out[0], ref) < 1e-12
     assert plan["ntask"][1] > 0
@@ -108,3 +111,10 @@ def test_batch_equals_single_boxes_bitwise():
         assert np.array_equal(got, single)
         assert m == sm
         assert _rel(got, _oracle(b, dt, 2)) < 1e-12
+
+
+def test_long_x_lines_two_cells_per_thread():
+    # x lines longer than one work-group: each thread owns two cells
+    b = _box((8, 9, 1100), seed=12, amp=1.0, drops=False)
+    out, _, plan = run_emu([b], 2e-4, 1, z_chunk=3)
+    assert _rel(out[0], _oracle(b, 2e-4, 1)) < 1e-12

@@ -82,6 +82,8 @@ def test_config1_fp64_one_step_and_ten_steps():
     ((48, 48, 48), (0, 0, 0), {}),
     ((40, 33, 72), (0, 0, 1), {}),
     ((96, 96, 96), (0, 0, 0), {}),
+    ((96, 96, 96), (0, 0, 0), dict(x_rows=2, z_chunk=5)),
+    ((8, 9, 1100), (0, 0, 0), dict(z_chunk=3)),
 ])
 def test_fp64_parity_tiles_walls_ragged(shape, bc, opts):
     C, u, v, w, h = _case(shape, bc, seed=sum(shape), amp=2.0)
