@@ -73,7 +73,6 @@ struct PassArgs {
     int32_t tw_max;     // largest warm-up over boxes (LDS layout)
     int32_t nx_max;     // largest x extent over boxes (LDS layout)
     int32_t seg_max;    // y/z pass: longest segment over boxes (LDS layout)
-    int32_t kmin;       // shortest chunk of the chunked line recurrences
 };
 
 // Index of a cell that may lie outside [0, n): periodic wrap, or even
@@ -204,33 +203,61 @@ struct Chunk {
     bool live;
 };
 
-CH_HD Chunk line_chunk(int tid, int nth, int nl, int n, int tw, int kmin)
+// most chunks per line: every x-pass work-group has at least nx threads per
+// line and every y/z work-group at least 8 threads per lane column
+constexpr int X_CHAINS = 16;
+constexpr int YZ_CHAINS = 8;
+
+// Chunks of a line of n points: at most `cap` of them, none shorter than the
+// warm-up.  The split depends only on the line (n, tw) and the pass, never on
+// the launch, so a box gives bitwise the same result alone or in a batch.
+CH_HD int line_chunk_len(int n, int tw, int cap)
+{
+    int nch = n / 16;
+    if (nch > cap) nch = cap;
+    if (nch < 1) nch = 1;
+    int K = (n + nch - 1) / nch;
+    if (K < tw) K = tw;
+    return K < 1 ? 1 : K;
+}
+
+CH_HD Chunk line_chunk(int tid, int nl, int n, int tw, int cap)
 {
     Chunk ch;
-    const int nchmax = nth / nl;
+    const int K = line_chunk_len(n, tw, cap);
     ch.l = tid % nl;
     const int c = tid / nl;
-    int K = (n + nchmax - 1) / nchmax;
-    if (K < kmin) K = kmin;
-    if (K < 1) K = 1;
     ch.c0 = c * K;
-    ch.live = c < nchmax && ch.c0 < n;
+    ch.live = ch.c0 < n;
     const bool last = ch.c0 + K >= n;
     ch.fend = last ? n + tw : ch.c0 + K;
     ch.bend = ch.c0 + K < n ? ch.c0 + K : n;
     return ch;
 }
 
+// The recurrences walk the tile in batches of LB values: the batch's loads
+// are independent of the chain and go out together.
+constexpr int LB = 8;
+
 template <typename A>
-CH_HD void line_f1(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2, A ic,
+CH_HD void line_f1(const Chunk& ch, const A* tile, int pitch, int tw, A a1, A a2, A ic,
                    LineState<A>& st)
 {
     A w1 = A(0), w2 = A(0);
     if (ch.live) {
-        for (int p = ch.c0 - tw; p < ch.c0; ++p) {
-            const A w = tile[(p + tw) * pitch + ch.l] * ic - a1 * w1 - a2 * w2;
-            w2 = w1;
-            w1 = w;
+        const A* base = tile + ch.l;
+        for (int p0 = ch.c0 - tw; p0 < ch.c0; p0 += LB) {
+            A v[LB];
+#pragma unroll
+            for (int j = 0; j < LB; ++j)
+                v[j] = p0 + j < ch.c0 ? base[(p0 + j + tw) * pitch] : A(0);
+#pragma unroll
+            for (int j = 0; j < LB; ++j)
+                if (p0 + j < ch.c0) {
+                    const A w = v[j] * ic - a1 * w1 - a2 * w2;
+                    w2 = w1;
+                    w1 = w;
+                }
         }
     }
     st.s1 = w1;
@@ -243,12 +270,22 @@ CH_HD void line_f2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2, A ic
 {
     if (!ch.live) return;
     A w1 = st.s1, w2 = st.s2;
-    for (int p = ch.c0; p < ch.fend; ++p) {
-        A* at = tile + (p + tw) * pitch + ch.l;
-        const A w = *at * ic - a1 * w1 - a2 * w2;
-        *at = w;
-        w2 = w1;
-        w1 = w;
+    A* base = tile + ch.l;
+    for (int p0 = ch.c0; p0 < ch.fend; p0 += LB) {
+        A v[LB];
+#pragma unroll
+        for (int j = 0; j < LB; ++j)
+            v[j] = p0 + j < ch.fend ? base[(p0 + j + tw) * pitch] : A(0);
+#pragma unroll
+        for (int j = 0; j < LB; ++j) {
+            const A w = v[j] * ic - a1 * w1 - a2 * w2;
+            v[j] = w;
+            w2 = w1;
+            w1 = w;
+        }
+#pragma unroll
+        for (int j = 0; j < LB; ++j)
+            if (p0 + j < ch.fend) base[(p0 + j + tw) * pitch] = v[j];
     }
 }
 
@@ -258,10 +295,20 @@ CH_HD void line_b1(const Chunk& ch, const A* tile, int pitch, int tw, A a1, A a2
 {
     A y1 = A(0), y2 = A(0);
     if (ch.live) {
-        for (int p = ch.bend + tw - 1; p >= ch.bend; --p) {
-            const A y = tile[(p + tw) * pitch + ch.l] - a1 * y1 - a2 * y2;
-            y2 = y1;
-            y1 = y;
+        const A* base = tile + ch.l;
+        const int lo = ch.bend;
+        for (int p0 = ch.bend + tw - 1; p0 >= lo; p0 -= LB) {
+            A v[LB];
+#pragma unroll
+            for (int j = 0; j < LB; ++j)
+                v[j] = p0 - j >= lo ? base[(p0 - j + tw) * pitch] : A(0);
+#pragma unroll
+            for (int j = 0; j < LB; ++j)
+                if (p0 - j >= lo) {
+                    const A y = v[j] - a1 * y1 - a2 * y2;
+                    y2 = y1;
+                    y1 = y;
+                }
         }
     }
     st.s1 = y1;
@@ -274,12 +321,22 @@ CH_HD void line_b2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2,
 {
     if (!ch.live) return;
     A y1 = st.s1, y2 = st.s2;
-    for (int p = ch.bend - 1; p >= ch.c0; --p) {
-        A* at = tile + (p + tw) * pitch + ch.l;
-        const A y = *at - a1 * y1 - a2 * y2;
-        *at = y;
-        y2 = y1;
-        y1 = y;
+    A* base = tile + ch.l;
+    for (int p0 = ch.bend - 1; p0 >= ch.c0; p0 -= LB) {
+        A v[LB];
+#pragma unroll
+        for (int j = 0; j < LB; ++j)
+            v[j] = p0 - j >= ch.c0 ? base[(p0 - j + tw) * pitch] : A(0);
+#pragma unroll
+        for (int j = 0; j < LB; ++j) {
+            const A y = v[j] - a1 * y1 - a2 * y2;
+            v[j] = y;
+            y2 = y1;
+            y1 = y;
+        }
+#pragma unroll
+        for (int j = 0; j < LB; ++j)
+            if (p0 - j >= ch.c0) base[(p0 - j + tw) * pitch] = v[j];
     }
 }
 
@@ -516,19 +573,19 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
         });
         // ---- x solve
         ex.phase([&](int tid) {
-            const Chunk ch = line_chunk(tid, nth, rows, nx, tw, pa.kmin);
+            const Chunk ch = line_chunk(tid, rows, nx, tw, X_CHAINS);
             line_f1<A>(ch, tb, L.tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
         });
         ex.phase([&](int tid) {
-            const Chunk ch = line_chunk(tid, nth, rows, nx, tw, pa.kmin);
+            const Chunk ch = line_chunk(tid, rows, nx, tw, X_CHAINS);
             line_f2<A>(ch, tb, L.tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
         });
         ex.phase([&](int tid) {
-            const Chunk ch = line_chunk(tid, nth, rows, nx, tw, pa.kmin);
+            const Chunk ch = line_chunk(tid, rows, nx, tw, X_CHAINS);
             line_b1<A>(ch, tb, L.tbp, tw, a1, a2, st[ex.slot(tid)].ls);
         });
         ex.phase([&](int tid) {
-            const Chunk ch = line_chunk(tid, nth, rows, nx, tw, pa.kmin);
+            const Chunk ch = line_chunk(tid, rows, nx, tw, X_CHAINS);
             line_b2<A>(ch, tb, L.tbp, tw, a1, a2, st[ex.slot(tid)].ls);
         });
         // ---- store q
@@ -607,19 +664,19 @@ CH_HD void pass_line_program(X& ex, LineState<A>* st, const BoxDesc& bd, const P
         }
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nth, Lw, t.len, tw, pa.kmin);
+        const Chunk ch = line_chunk(tid, Lw, t.len, tw, YZ_CHAINS);
         line_f1<A>(ch, tile, Lw, tw, a1, a2, ic, st[ex.slot(tid)]);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nth, Lw, t.len, tw, pa.kmin);
+        const Chunk ch = line_chunk(tid, Lw, t.len, tw, YZ_CHAINS);
         line_f2<A>(ch, tile, Lw, tw, a1, a2, ic, st[ex.slot(tid)]);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nth, Lw, t.len, tw, pa.kmin);
+        const Chunk ch = line_chunk(tid, Lw, t.len, tw, YZ_CHAINS);
         line_b1<A>(ch, tile, Lw, tw, a1, a2, st[ex.slot(tid)]);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nth, Lw, t.len, tw, pa.kmin);
+        const Chunk ch = line_chunk(tid, Lw, t.len, tw, YZ_CHAINS);
         line_b2<A>(ch, tile, Lw, tw, a1, a2, st[ex.slot(tid)]);
     });
     ex.phase([&](int tid) {

@@ -93,7 +93,6 @@ struct Plan {
     bool acc64 = true;
     int tw_max = 0;
     int x_rows = 0, x_threads = 256, zc = 1, mi = 1, lanes = 32, yz_threads = 256, seg_cap = 0;
-    int kmin = 1;
     int ntask[3] = {0, 0, 0};
     size_t lds[3] = {0, 0, 0};
     int nx_max = 0, seg_max[2] = {0, 0};
@@ -250,7 +249,6 @@ inline ch_status plan_dt(Plan& P, double dt)
     P.mi = x_items(nxm);
     const int xcap = X_MAX_THREADS * P.mi;
     if (nxm > xcap) return P.fail(CH_EUNSUPPORTED, "x extent too large");
-    P.kmin = std::max(1, P.tw_max);
     // ---- x pass: rows per task and planes per task
     int R = P.opt.x_rows;
     if (R == 0) {
@@ -279,7 +277,8 @@ inline ch_status plan_dt(Plan& P, double dt)
     P.zc = zc;
     // ---- y/z passes: lanes of 128 bytes, whole lines when they fit
     P.lanes = (int)(128 / sA);
-    P.yz_threads = 64 * (P.opt.waves_yz > 0 ? P.opt.waves_yz : 4);
+    // at least YZ_CHAINS threads per lane column (see line_chunk)
+    P.yz_threads = std::max(chd::YZ_CHAINS * P.lanes, 64 * (P.opt.waves_yz > 0 ? P.opt.waves_yz : 4));
     int seg = P.opt.seg_len > 0 ? P.opt.seg_len
                                 : (int)(LDS_BUDGET / (P.lanes * sA)) - 2 * P.tw_max;
     if (seg < 16) seg = (int)(LDS_HARD / (P.lanes * sA)) - 2 * P.tw_max;
@@ -333,7 +332,6 @@ inline chd::PassArgs pass_args(const Plan& P, int k, int pass)
     pa.tw_max = P.tw_max;
     pa.nx_max = P.nx_max;
     pa.seg_max = pass == 2 ? P.seg_max[1] : P.seg_max[0];
-    pa.kmin = P.kmin;
     return pa;
 }
 
