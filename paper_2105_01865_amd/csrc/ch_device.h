@@ -73,6 +73,7 @@ struct PassArgs {
     int32_t tw_max;     // largest warm-up over boxes (LDS layout)
     int32_t nx_max;     // largest x extent over boxes (LDS layout)
     int32_t seg_max;    // y/z pass: longest segment over boxes (LDS layout)
+    int32_t zcmax;      // x pass: most planes per task (LDS layout)
 };
 
 // Index of a cell that may lie outside [0, n): periodic wrap, or even
@@ -81,6 +82,10 @@ CH_HD int map_idx(int i, int n, int bc)
 {
     if (i >= 0 && i < n) return i;
     if (n == 1) return 0;
+    if (i >= -n && i < 2 * n) {   // within one period: no division
+        if (bc == 0) return i < 0 ? i + n : i - n;
+        return i < 0 ? -1 - i : 2 * n - 1 - i;
+    }
     if (bc == 0) {
         int m = i % n;
         return m < 0 ? m + n : m;
@@ -91,33 +96,61 @@ CH_HD int map_idx(int i, int n, int bc)
     return m < n ? m : p - 1 - m;
 }
 
+// 1/x: one hardware reciprocal (1 ulp) in single precision on the GPU,
+// a correctly rounded division otherwise.
+CH_HD double fast_rcp(double x) { return 1.0 / x; }
+CH_HD float fast_rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
 // Fifth-order WENO (Jiang-Shu, point values as cell averages): value at the
 // face between c and d with upwind side a.
+//
+// Arithmetic arranged for few instructions, exact in real arithmetic:
+//  - the smoothness indicators 13/12 t^2 + 1/4 u^2 and eps are scaled by
+//    12/13 (the normalised weights do not change), so eps + beta is
+//    t^2 + (3/13) u^2 + (12/13) eps, two fused multiply-adds;
+//  - the weights d_j / (eps + beta_j)^2 are formed over the common
+//    denominator prod_j (eps + beta_j)^2, which leaves one division;
+//  - the linear weights (1/10, 6/10, 3/10) and the 1/6 of the candidate
+//    stencils are folded into the stencil coefficients.
+// `epsw` is (12/13) eps.
 template <typename T>
-CH_HD T weno5(T a, T b, T c, T d, T e, T eps)
+CH_HD T weno5(T a, T b, T c, T d, T e, T epsw)
 {
-    const T sixth = T(1) / T(6);
-    const T q0 = (T(2) * a - T(7) * b + T(11) * c) * sixth;
-    const T q1 = (-b + T(5) * c + T(2) * d) * sixth;
-    const T q2 = (T(2) * c + T(5) * d - e) * sixth;
-    const T k13 = T(13) / T(12), qu = T(0.25);
-    const T t0 = a - T(2) * b + c, u0 = a - T(4) * b + T(3) * c;
-    const T t1 = b - T(2) * c + d, u1 = b - d;
-    const T t2 = c - T(2) * d + e, u2 = T(3) * c - T(4) * d + e;
-    const T s0 = k13 * t0 * t0 + qu * u0 * u0;
-    const T s1 = k13 * t1 * t1 + qu * u1 * u1;
-    const T s2 = k13 * t2 * t2 + qu * u2 * u2;
-    const T e0 = eps + s0, e1 = eps + s1, e2 = eps + s2;
-    const T w0 = T(0.1) / (e0 * e0);
-    const T w1 = T(0.6) / (e1 * e1);
-    const T w2 = T(0.3) / (e2 * e2);
-    return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+    const T k3 = T(3) / T(13);
+    const T t0 = (a + c) - T(2) * b, u0 = (a - T(4) * b) + T(3) * c;
+    const T t1 = (b + d) - T(2) * c, u1 = b - d;
+    const T t2 = (c + e) - T(2) * d, u2 = (T(3) * c - T(4) * d) + e;
+    const T e0 = t0 * t0 + ((k3 * u0) * u0 + epsw);
+    const T e1 = t1 * t1 + ((k3 * u1) * u1 + epsw);
+    const T e2 = t2 * t2 + ((k3 * u2) * u2 + epsw);
+    const T p0 = e0 * e0, p1 = e1 * e1, p2 = e2 * e2;
+    const T p12 = p1 * p2, p02 = p0 * p2, p01 = p0 * p1;
+    // 1/10, 6/10, 3/10 times the candidate reconstructions (times 6)
+    const T q0 = (T(0.2) * a - T(0.7) * b) + T(1.1) * c;
+    const T q1 = (T(3) * c - T(0.6) * b) + T(1.2) * d;
+    const T q2 = (T(0.6) * c + T(1.5) * d) - T(0.3) * e;
+    const T num = p12 * q0 + (p02 * q1 + p01 * q2);
+    const T den = T(0.6) * p12 + (T(3.6) * p02 + T(1.8) * p01);
+    return num * fast_rcp(den);
 }
 
 template <typename T>
-CH_HD T psi_prime(const double* p, T c)
+struct Cubic {
+    T c0, c1, c2, c3;
+    CH_HD T operator()(T x) const { return ((c3 * x + c2) * x + c1) * x + c0; }
+};
+
+template <typename T>
+CH_HD Cubic<T> cubic(const double* p)
 {
-    return ((T(p[3]) * c + T(p[2])) * c + T(p[1])) * c + T(p[0]);
+    return Cubic<T>{T(p[0]), T(p[1]), T(p[2]), T(p[3])};
 }
 
 // Fourth difference (1,-4,6,-4,1) in nested form: differences of adjacent
@@ -128,6 +161,12 @@ CH_HD T d4(T m2, T m1, T c0, T p1, T p2)
     const T a = m1 - m2, b = c0 - m1, c = p1 - c0, d = p2 - p1;
     return ((d - c) - (c - b)) - ((c - b) - (b - a));
 }
+
+// compile-time integer tag
+template <int V>
+struct IC {
+    static constexpr int value = V;
+};
 
 // Box of a global task index (boxes sorted by task0 of the pass).
 CH_HD int find_box(const BoxDesc* boxes, int nbox, int pass, int task)
@@ -245,19 +284,23 @@ CH_HD void line_f1(const Chunk& ch, const A* tile, int pitch, int tw, A a1, A a2
 {
     A w1 = A(0), w2 = A(0);
     if (ch.live) {
-        const A* base = tile + ch.l;
-        for (int p0 = ch.c0 - tw; p0 < ch.c0; p0 += LB) {
+        const A* base = tile + tw * pitch + ch.l;
+        int p = ch.c0 - tw;
+        for (; p + LB <= ch.c0; p += LB) {
             A v[LB];
 #pragma unroll
-            for (int j = 0; j < LB; ++j)
-                v[j] = p0 + j < ch.c0 ? base[(p0 + j + tw) * pitch] : A(0);
+            for (int j = 0; j < LB; ++j) v[j] = base[(p + j) * pitch];
 #pragma unroll
-            for (int j = 0; j < LB; ++j)
-                if (p0 + j < ch.c0) {
-                    const A w = v[j] * ic - a1 * w1 - a2 * w2;
-                    w2 = w1;
-                    w1 = w;
-                }
+            for (int j = 0; j < LB; ++j) {
+                const A w = v[j] * ic - a1 * w1 - a2 * w2;
+                w2 = w1;
+                w1 = w;
+            }
+        }
+        for (; p < ch.c0; ++p) {
+            const A w = base[p * pitch] * ic - a1 * w1 - a2 * w2;
+            w2 = w1;
+            w1 = w;
         }
     }
     st.s1 = w1;
@@ -270,12 +313,12 @@ CH_HD void line_f2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2, A ic
 {
     if (!ch.live) return;
     A w1 = st.s1, w2 = st.s2;
-    A* base = tile + ch.l;
-    for (int p0 = ch.c0; p0 < ch.fend; p0 += LB) {
+    A* base = tile + tw * pitch + ch.l;
+    int p = ch.c0;
+    for (; p + LB <= ch.fend; p += LB) {
         A v[LB];
 #pragma unroll
-        for (int j = 0; j < LB; ++j)
-            v[j] = p0 + j < ch.fend ? base[(p0 + j + tw) * pitch] : A(0);
+        for (int j = 0; j < LB; ++j) v[j] = base[(p + j) * pitch];
 #pragma unroll
         for (int j = 0; j < LB; ++j) {
             const A w = v[j] * ic - a1 * w1 - a2 * w2;
@@ -284,8 +327,13 @@ CH_HD void line_f2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2, A ic
             w1 = w;
         }
 #pragma unroll
-        for (int j = 0; j < LB; ++j)
-            if (p0 + j < ch.fend) base[(p0 + j + tw) * pitch] = v[j];
+        for (int j = 0; j < LB; ++j) base[(p + j) * pitch] = v[j];
+    }
+    for (; p < ch.fend; ++p) {
+        const A w = base[p * pitch] * ic - a1 * w1 - a2 * w2;
+        base[p * pitch] = w;
+        w2 = w1;
+        w1 = w;
     }
 }
 
@@ -295,20 +343,23 @@ CH_HD void line_b1(const Chunk& ch, const A* tile, int pitch, int tw, A a1, A a2
 {
     A y1 = A(0), y2 = A(0);
     if (ch.live) {
-        const A* base = tile + ch.l;
-        const int lo = ch.bend;
-        for (int p0 = ch.bend + tw - 1; p0 >= lo; p0 -= LB) {
+        const A* base = tile + tw * pitch + ch.l;
+        int p = ch.bend + tw - 1;
+        for (; p - LB + 1 >= ch.bend; p -= LB) {
             A v[LB];
 #pragma unroll
-            for (int j = 0; j < LB; ++j)
-                v[j] = p0 - j >= lo ? base[(p0 - j + tw) * pitch] : A(0);
+            for (int j = 0; j < LB; ++j) v[j] = base[(p - j) * pitch];
 #pragma unroll
-            for (int j = 0; j < LB; ++j)
-                if (p0 - j >= lo) {
-                    const A y = v[j] - a1 * y1 - a2 * y2;
-                    y2 = y1;
-                    y1 = y;
-                }
+            for (int j = 0; j < LB; ++j) {
+                const A y = v[j] - a1 * y1 - a2 * y2;
+                y2 = y1;
+                y1 = y;
+            }
+        }
+        for (; p >= ch.bend; --p) {
+            const A y = base[p * pitch] - a1 * y1 - a2 * y2;
+            y2 = y1;
+            y1 = y;
         }
     }
     st.s1 = y1;
@@ -321,12 +372,12 @@ CH_HD void line_b2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2,
 {
     if (!ch.live) return;
     A y1 = st.s1, y2 = st.s2;
-    A* base = tile + ch.l;
-    for (int p0 = ch.bend - 1; p0 >= ch.c0; p0 -= LB) {
+    A* base = tile + tw * pitch + ch.l;
+    int p = ch.bend - 1;
+    for (; p - LB + 1 >= ch.c0; p -= LB) {
         A v[LB];
 #pragma unroll
-        for (int j = 0; j < LB; ++j)
-            v[j] = p0 - j >= ch.c0 ? base[(p0 - j + tw) * pitch] : A(0);
+        for (int j = 0; j < LB; ++j) v[j] = base[(p - j) * pitch];
 #pragma unroll
         for (int j = 0; j < LB; ++j) {
             const A y = v[j] - a1 * y1 - a2 * y2;
@@ -335,43 +386,55 @@ CH_HD void line_b2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2,
             y1 = y;
         }
 #pragma unroll
-        for (int j = 0; j < LB; ++j)
-            if (p0 - j >= ch.c0) base[(p0 - j + tw) * pitch] = v[j];
+        for (int j = 0; j < LB; ++j) base[(p - j) * pitch] = v[j];
+    }
+    for (; p >= ch.c0; --p) {
+        const A y = base[p * pitch] - a1 * y1 - a2 * y2;
+        base[p * pitch] = y;
+        y2 = y1;
+        y1 = y;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Pass X: explicit terms, RHS and the x-line solve of eq-fac-1 for a task of
-// `rows` complete x-lines (y0 .. y0+rows-1) marching over the planes
-// z0 .. z0+nzc-1.  Thread tid owns the cells item = tid + nth m (m < MI) of
-// the rows x nx plane tile for the whole march, and keeps for each the
-// column of C at z-3 .. z+3 and the flux through its low z face in
-// registers, so that each z face flux is computed once.  x and y face
-// fluxes are computed once per face and exchanged through LDS.
+// `rows` complete x-lines (y0 .. y0+rows-1) over the planes z0 .. z0+nzc-1.
+//
+// March: thread tid owns the cells item = tid + nth m (m < MI) of the
+// rows x nx plane tile and walks them up through the planes, keeping for
+// each the column of C at z-3 .. z+3 and the flux through its low z face in
+// registers, so each z face flux is computed once; x and y face fluxes are
+// computed once per face and exchanged through LDS.  The RHS of every plane
+// goes into one LDS tile of rows x nzc lines, which is then solved in place
+// by all threads at once and written out.  Two barriers per plane: the RHS
+// of plane z-1 is finished in the same phase that loads plane z.
 //
 // LDS (launch-wide pitches; all sizes from the largest box):
 //   pb: (rmax + 6) x (nx_max + 6) T  C of the plane, rows y0-3 .. y0+rows+2,
 //                                    columns -3 .. nx+2
 //   fx: rmax x (nx_max + 1) T        flux through x face f of each row
 //   fy: (rmax + 1) x nx_max T        flux through y face y0 + r
-//   tb: (nx_max + 2 tw_max) x (rmax + 1) A   RHS -> solve tile
+//   tb: (nx_max + 2 tw_max) x (rmax zcmax + 1) A   RHS -> solve tile, line
+//                                    zs * rows + r at column zs * rows + r
 // ---------------------------------------------------------------------------
 struct XLayout {
-    size_t pb, fx, fy, tb, total;  // byte offsets and total size
-    int pbp, fxp, fyp, tbp;        // pitches (elements)
+    size_t pb, mb, fx, fy, tb, total;  // byte offsets and total size
+    int pbp, mbp, fxp, fyp, tbp;       // pitches (elements)
 };
 
 CH_HD size_t al16(size_t b) { return (b + 15) & ~size_t(15); }
 
-CH_HD XLayout x_layout(int nx_max, int rmax, int tw_max, int sT, int sA)
+CH_HD XLayout x_layout(int nx_max, int rmax, int zcmax, int tw_max, int sT, int sA)
 {
     XLayout L;
     L.pbp = nx_max + 6;
+    L.mbp = nx_max + 2;
     L.fxp = nx_max + 1;
     L.fyp = nx_max;
-    L.tbp = rmax + 1;
+    L.tbp = rmax * zcmax + 1;
     L.pb = 0;
-    L.fx = al16(L.pb + (size_t)(rmax + 6) * L.pbp * sT);
+    L.mb = al16(L.pb + (size_t)(rmax + 6) * L.pbp * sT);
+    L.fx = al16(L.mb + (size_t)(rmax + 2) * L.mbp * sT);
     L.fy = al16(L.fx + (size_t)rmax * L.fxp * sT);
     L.tb = al16(L.fy + (size_t)(rmax + 1) * L.fyp * sT);
     L.total = al16(L.tb + (size_t)(nx_max + 2 * tw_max) * L.tbp * sA);
@@ -397,14 +460,37 @@ CH_HD XZTask xz_task(const BoxDesc& bd, int task)
     return t;
 }
 
+// Planes of x-pass inputs held in registers ahead of the plane being computed
+// (1 or 2).  One plane keeps the state within 128 VGPRs in FP32.
+#ifndef X_PREFETCH
+#define X_PREFETCH 1
+#endif
+
 template <typename T, typename A, int MI>
 struct XState {
     T cz[MI][7];     // C at z-3 .. z+3 of each owned cell
+    T mq[MI][3];     // psi'(C) at z-1, z, z+1
     T fzl[MI];       // flux through the low z face of the current plane
     T pz[MI];        // z flux difference of the current plane
     T plap[MI];      // sum of second differences of psi'(C)
     T pb4[MI];       // sum of fourth differences of C
+    T vel[MI][6];    // u, v, w on the low and high faces of the cell
+    T eold[MI];      // E of the previous substage
+    T eold_next[MI]; // E of the previous substage on this plane, until the
+                     // RHS of the plane below has used eold
+    // the next X_PREFETCH planes, loaded while this one is computed (set b
+    // holds planes z0 + b, z0 + b + X_PREFETCH, ...)
+    T ncz[X_PREFETCH][MI];       // C at z+3 of the plane
+    T nvel[X_PREFETCH][MI][4];   // u low, u high, v low, v high
+    T nwh[X_PREFETCH][MI];       // w on the high face
+    T neold[X_PREFETCH][MI];     // old E
+    T nhalo[X_PREFETCH][MI][6];  // C of the six halo rows at column hx[m]
     int rx[MI];      // (row << 16) | x of each owned cell, -1 if none
+    unsigned col[MI];   // y nx + x: offset of the cell in a plane of C, E, v, w
+    unsigned colu[MI];  // y fx + x: offset of its low x face in a plane of u
+    unsigned colvh[MI]; // offset of its high y face in a plane of v
+    int hx[MI];      // halo-row column this thread loads, -1 if none
+    int xmask[MI];   // halo columns of the plane tiles fed by the owned column
     LineState<A> ls;
 };
 
@@ -417,10 +503,13 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
     const XZTask t = xz_task(bd, task);
     const int nx = bd.n[0], ny = bd.n[1], nz = bd.n[2];
     const int fx = bd.nf[0], fy = bd.nf[1];
+    const int bcx = bd.bc[0];
     const int k = pa.k, tw = bd.tw[k];
     const int nth = ex.nth;
-    const XLayout L = x_layout(pa.nx_max, pa.rmax, pa.tw_max, (int)sizeof(T), (int)sizeof(A));
+    const XLayout L = x_layout(pa.nx_max, pa.rmax, pa.zcmax, pa.tw_max, (int)sizeof(T),
+                               (int)sizeof(A));
     T* pb = reinterpret_cast<T*>(smem + L.pb);
+    T* mb = reinterpret_cast<T*>(smem + L.mb);
     T* fxb = reinterpret_cast<T*>(smem + L.fx);
     T* fyb = reinterpret_cast<T*>(smem + L.fy);
     A* tb = reinterpret_cast<A*>(smem + L.tb);
@@ -431,174 +520,255 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
     const T* Wb = W + bd.w_off;
     T* Eb = E + bd.c_off;
     T* Qb = Q + bd.c_off;
-    const T eps = T(bd.eps);
+    const T epsw = T(bd.eps * (12.0 / 13.0));
     const T gdt = T(bd.gdt[k]), rdt = T(bd.rdt[k]), bdt = T(bd.bdt[k]);
     const T inv_h = T(bd.inv_h), lap_s = T(bd.inv_h2 * bd.inv_pe);
+    const Cubic<T> mu = cubic<T>(bd.psi);
     const A a1 = A(bd.a1[k]), a2 = A(bd.a2[k]), ic = A(bd.ic[k]);
     const int rows = t.rows;
     const int ncell = rows * nx;
+    const int nlines = rows * t.nzc;
+    // the six halo rows (y0-3 .. y0-1, y0+rows .. y0+rows+2) and their tile rows
+    int hrow[6];
+    unsigned hoff[6];
+#pragma unroll
+    for (int hr = 0; hr < 6; ++hr) {
+        const int prow = hr < 3 ? hr : rows + hr;
+        hrow[hr] = prow;
+        hoff[hr] = (unsigned)(map_idx(t.y0 - 3 + prow, ny, bd.bc[1]) * nx);
+    }
 
-    // owned cells
+    // all global loads of plane z for the owned cells, into prefetch set b
+    // (uniform plane bases, 32-bit offsets within a plane)
+    auto fetch = [&](XState<T, A, MI>& s, auto bset, int z) {
+        constexpr int b = decltype(bset)::value;
+        const T* Cq = Cb + (int64_t)map_idx(z + 3, nz, bd.bc[2]) * plane;
+        const T* Uz = Ub + (int64_t)z * ny * fx;
+        const T* Vz = Vb + (int64_t)z * fy * nx;
+        const T* Wh = Wb + (int64_t)((z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1) * plane;
+        const T* Ez = Eb + (int64_t)z * plane;
+        const T* Cz = Cb + (int64_t)z * plane;
+#pragma unroll
+        for (int m = 0; m < MI; ++m) {
+            if (s.rx[m] >= 0) {
+                const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
+                s.ncz[b][m] = Cq[s.col[m]];
+                s.nvel[b][m][0] = Uz[s.colu[m]];
+                s.nvel[b][m][1] = (x == nx - 1 && bcx != 0) ? Uz[s.colu[m] + 1] : T(0);
+                s.nvel[b][m][2] = Vz[s.col[m]];
+                s.nvel[b][m][3] = r == rows - 1 ? Vz[s.colvh[m]] : T(0);
+                s.nwh[b][m] = Wh[s.col[m]];
+                s.neold[b][m] = pa.e_mode != 0 ? Ez[s.col[m]] : T(0);
+            }
+            if (s.hx[m] >= 0) {
+#pragma unroll
+                for (int hr = 0; hr < 6; ++hr) s.nhalo[b][m][hr] = Cz[hoff[hr] + s.hx[m]];
+            }
+        }
+    };
+    // a value of plane-tile row prow at column x, and its copies in the halo
+    // columns (bit q of mask: column q - 3 for q < 3, nx + q - 3 otherwise)
+    auto put = [&](T* tile, int pitch, int halo, int prow, int x, int mask, T v) {
+        T* rp = tile + prow * pitch + halo;
+        rp[x] = v;
+        if (mask) {
+#pragma unroll
+            for (int q = 3 - halo; q < 3 + halo; ++q)
+                if ((mask >> q) & 1) rp[q < 3 ? q - 3 : nx + q - 3] = v;
+        }
+    };
+    // RHS of plane zs of the owned cells into the solve tile
+    auto rhs_plane = [&](XState<T, A, MI>& s, int zs) {
+        T* Ez = Eb + (int64_t)(t.z0 + zs) * plane;
+#pragma unroll
+        for (int m = 0; m < MI; ++m) {
+            if (s.rx[m] < 0) continue;
+            const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
+            const T fhi = x + 1 < nx ? fxb[r * L.fxp + x + 1]
+                                     : fxb[r * L.fxp + (bcx == 0 ? 0 : nx)];
+            const T adv = (fhi - fxb[r * L.fxp + x])
+                        + (fyb[(r + 1) * L.fyp + x] - fyb[r * L.fyp + x]) + s.pz[m];
+            const T e = -adv * inv_h + s.plap[m] * lap_s;
+            T rhs = gdt * e - bdt * s.pb4[m];
+            if (pa.e_mode != 0) rhs += rdt * s.eold[m];
+            if (pa.e_mode != 2) Ez[s.col[m]] = e;
+            tb[(x + tw) * L.tbp + zs * rows + r] = A(rhs);
+        }
+    };
+
+    // owned cells, the queue below the first plane, and the first plane's loads
     ex.phase([&](int tid) {
         XState<T, A, MI>& s = st[ex.slot(tid)];
+        const T* Wz = Wb + (int64_t)t.z0 * plane;
 #pragma unroll
         for (int m = 0; m < MI; ++m) {
             const int item = tid + nth * m;
             s.rx[m] = item < ncell ? ((item / nx) << 16) | (item % nx) : -1;
-        }
-    });
-
-    for (int zs = 0; zs < t.nzc; ++zs) {
-        const int z = t.z0 + zs;
-        // ---- load: C columns (queue), the plane tile with its halos
-        ex.phase([&](int tid) {
-            XState<T, A, MI>& s = st[ex.slot(tid)];
-    #pragma unroll
-        for (int m = 0; m < MI; ++m) {
-                if (s.rx[m] < 0) continue;
-                const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
-                const int64_t col = (int64_t)(t.y0 + r) * nx + x;
-                if (zs == 0) {
-#pragma unroll
-                    for (int q = 0; q < 7; ++q)
-                        s.cz[m][q] = Cb[(int64_t)map_idx(z - 3 + q, nz, bd.bc[2]) * plane + col];
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) s.cz[m][q] = s.cz[m][q + 1];
-                    s.cz[m][6] = Cb[(int64_t)map_idx(z + 3, nz, bd.bc[2]) * plane + col];
-                }
-                pb[(r + 3) * L.pbp + x + 3] = s.cz[m][3];
-            }
-            const int64_t zp = (int64_t)z * plane;
-            // rows y0-3 .. y0-1 and y0+rows .. y0+rows+2
-            for (int hr = 0; hr < 6; ++hr) {
-                const int prow = hr < 3 ? hr : rows + hr;
-                const int gy = map_idx(t.y0 - 3 + prow, ny, bd.bc[1]);
-                for (int x = tid; x < nx; x += nth)
-                    pb[prow * L.pbp + x + 3] = Cb[zp + (int64_t)gy * nx + x];
-            }
-            // columns -3..-1 and nx..nx+2 of every tile row
-            for (int j = tid; j < 6 * (rows + 6); j += nth) {
-                const int prow = j / 6, q = j - prow * 6;
-                const int xc = q < 3 ? q - 3 : nx + q - 3;
-                const int gy = map_idx(t.y0 - 3 + prow, ny, bd.bc[1]);
-                pb[prow * L.pbp + xc + 3] = Cb[zp + (int64_t)gy * nx + map_idx(xc, nx, bd.bc[0])];
-            }
-        });
-        // ---- faces, Laplacian of psi'(C), fourth differences
-        ex.phase([&](int tid) {
-            XState<T, A, MI>& s = st[ex.slot(tid)];
-    #pragma unroll
-        for (int m = 0; m < MI; ++m) {
-                if (s.rx[m] < 0) continue;
+            const int hxm = tid + nth * m;
+            s.hx[m] = hxm < nx ? hxm : -1;
+            int mask = 0;
+            if (s.rx[m] >= 0) {
                 const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
                 const int y = t.y0 + r;
+                const int yh = (y + 1 == ny && bd.bc[1] == 0) ? 0 : y + 1;
+                s.col[m] = (unsigned)(y * nx + x);
+                s.colu[m] = (unsigned)(y * fx + x);
+                s.colvh[m] = (unsigned)(yh * nx + x);
+                for (int q = 0; q < 6; ++q)
+                    if (map_idx(q < 3 ? q - 3 : nx + q - 3, nx, bcx) == x) mask |= 1 << q;
+#pragma unroll
+                for (int q = 1; q < 7; ++q)
+                    s.cz[m][q] = Cb[(int64_t)map_idx(t.z0 - 4 + q, nz, bd.bc[2]) * plane + s.col[m]];
+                s.mq[m][1] = mu(s.cz[m][3]);   // psi'(C) at z0-2 .. z0 after the first shift
+                s.mq[m][2] = mu(s.cz[m][4]);
+                s.vel[m][4] = Wz[s.col[m]];
+            }
+            s.xmask[m] = mask;
+        }
+        fetch(s, IC<0>{}, t.z0);
+        if (X_PREFETCH == 2 && t.nzc > 1) fetch(s, IC<X_PREFETCH - 1>{}, t.z0 + 1);
+    });
+
+    // one plane of the march; the prefetch set alternates, so the loop is
+    // unrolled by two to keep the set index a constant
+    auto plane_step = [&](auto bset, int zs) {
+        constexpr int b = decltype(bset)::value;
+        const int z = t.z0 + zs;
+        // ---- take this plane's loads, start the loads X_PREFETCH planes up, RHS of
+        //      the plane below
+        ex.phase([&](int tid) {
+            XState<T, A, MI>& s = st[ex.slot(tid)];
+            // take this plane's loads out of the prefetch registers; the halo
+            // rows go straight into the plane tiles
+            T own[MI];
+#pragma unroll
+            for (int m = 0; m < MI; ++m) {
+                if (s.rx[m] >= 0) {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) s.cz[m][q] = s.cz[m][q + 1];
+                    s.cz[m][6] = s.ncz[b][m];
+                    own[m] = s.cz[m][3];
+                    s.vel[m][0] = s.nvel[b][m][0];
+                    s.vel[m][1] = s.nvel[b][m][1];
+                    s.vel[m][2] = s.nvel[b][m][2];
+                    s.vel[m][3] = s.nvel[b][m][3];
+                    if (zs > 0) s.vel[m][4] = s.vel[m][5];
+                    s.vel[m][5] = s.nwh[b][m];
+                    s.eold_next[m] = s.neold[b][m];
+                }
+                if (s.hx[m] >= 0) {
+                    const int x = s.hx[m];
+                    const int mask = s.rx[m] >= 0 && (s.rx[m] & 0xffff) == x ? s.xmask[m] : 0;
+#pragma unroll
+                    for (int hr = 0; hr < 6; ++hr) put(pb, L.pbp, 3, hrow[hr], x, mask, s.nhalo[b][m][hr]);
+                    // psi'(C) of the two halo rows next to the tile
+                    put(mb, L.mbp, 1, 0, x, mask, mu(s.nhalo[b][m][2]));
+                    put(mb, L.mbp, 1, rows + 1, x, mask, mu(s.nhalo[b][m][3]));
+                }
+            }
+            // start the loads X_PREFETCH planes up, before any store of this phase
+            if (zs + X_PREFETCH < t.nzc) fetch(s, IC<b>{}, z + X_PREFETCH);
+            // RHS of the plane below (stores E)
+            if (zs > 0) rhs_plane(s, zs - 1);
+#pragma unroll
+            for (int m = 0; m < MI; ++m) {
+                if (s.rx[m] < 0) continue;
+                const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
+                s.eold[m] = s.eold_next[m];
+                s.mq[m][0] = s.mq[m][1];
+                s.mq[m][1] = s.mq[m][2];
+                s.mq[m][2] = mu(s.cz[m][4]);
+                put(pb, L.pbp, 3, r + 3, x, s.xmask[m], own[m]);
+                put(mb, L.mbp, 1, r + 1, x, s.xmask[m], s.mq[m][1]);
+            }
+        });
+        // ---- face fluxes, Laplacian of psi'(C), fourth differences
+        ex.phase([&](int tid) {
+            XState<T, A, MI>& s = st[ex.slot(tid)];
+#pragma unroll
+            for (int m = 0; m < MI; ++m) {
+                if (s.rx[m] < 0) continue;
+                const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
                 const T* row = pb + (r + 3) * L.pbp + x + 3;   // row[o] = C(x + o)
                 const T* colm = pb + r * L.pbp + x + 3;        // colm[o * pbp] = C(y - 3 + o)
-                // x: the low face of the cell, and face nx for the last cell
-                const int64_t ur = ((int64_t)z * ny + y) * fx;
-                {
-                    const T ul = Ub[ur + x];
-                    fxb[r * L.fxp + x] =
-                        ul * face_weno<T>(ul, row[-3], row[-2], row[-1], row[0], row[1], row[2], eps);
-                    if (x == nx - 1) {
-                        const T uh = Ub[ur + (bd.bc[0] == 0 ? 0 : nx)];
-                        fxb[r * L.fxp + nx] = uh * face_weno<T>(uh, row[-2], row[-1], row[0],
-                                                                 row[1], row[2], row[3], eps);
-                    }
-                }
+                const T* mrow = mb + (r + 1) * L.mbp + x + 1;  // mrow[o] = psi'(C)(x + o)
+                const int p = L.pbp, mp = L.mbp;
+                const T* vl = s.vel[m];
+                // x: the low face of the cell, and the wall face nx
+                fxb[r * L.fxp + x] =
+                    vl[0] * face_weno<T>(vl[0], row[-3], row[-2], row[-1], row[0], row[1], row[2], epsw);
+                if (x == nx - 1 && bcx != 0)
+                    fxb[r * L.fxp + nx] = vl[1] * face_weno<T>(vl[1], row[-2], row[-1], row[0],
+                                                                 row[1], row[2], row[3], epsw);
                 // y: the low face, and the top face for the last row
-                const int p = L.pbp;
-                {
-                    const T vl = Vb[((int64_t)z * fy + y) * nx + x];
-                    fyb[r * L.fyp + x] = vl * face_weno<T>(vl, colm[0], colm[p], colm[2 * p],
-                                                           colm[3 * p], colm[4 * p], colm[5 * p], eps);
-                    if (r == rows - 1) {
-                        const int yh = (y + 1 == ny && bd.bc[1] == 0) ? 0 : y + 1;
-                        const T vh = Vb[((int64_t)z * fy + yh) * nx + x];
-                        fyb[(r + 1) * L.fyp + x] =
-                            vh * face_weno<T>(vh, colm[p], colm[2 * p], colm[3 * p], colm[4 * p],
-                                              colm[5 * p], colm[6 * p], eps);
-                    }
-                }
+                fyb[r * L.fyp + x] = vl[2] * face_weno<T>(vl[2], colm[0], colm[p], colm[2 * p],
+                                                          colm[3 * p], colm[4 * p], colm[5 * p], epsw);
+                if (r == rows - 1)
+                    fyb[(r + 1) * L.fyp + x] =
+                        vl[3] * face_weno<T>(vl[3], colm[p], colm[2 * p], colm[3 * p], colm[4 * p],
+                                             colm[5 * p], colm[6 * p], epsw);
                 // z: the high face (the low one carries over from the plane below)
                 const T* c = s.cz[m];
-                {
-                    const int64_t wc = (int64_t)y * nx + x;
-                    if (zs == 0) {
-                        const T wl = Wb[(int64_t)z * plane + wc];
-                        s.fzl[m] = wl * face_weno<T>(wl, c[0], c[1], c[2], c[3], c[4], c[5], eps);
-                    }
-                    const int zh = (z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1;
-                    const T wh = Wb[(int64_t)zh * plane + wc];
-                    const T fzh = wh * face_weno<T>(wh, c[1], c[2], c[3], c[4], c[5], c[6], eps);
-                    s.pz[m] = fzh - s.fzl[m];
-                    s.fzl[m] = fzh;
-                }
-                const T mu0 = psi_prime<T>(bd.psi, c[3]);
-                s.plap[m] = (psi_prime<T>(bd.psi, row[1]) - mu0) - (mu0 - psi_prime<T>(bd.psi, row[-1]))
-                          + (psi_prime<T>(bd.psi, colm[4 * p]) - mu0)
-                          - (mu0 - psi_prime<T>(bd.psi, colm[2 * p]))
-                          + (psi_prime<T>(bd.psi, c[4]) - mu0) - (mu0 - psi_prime<T>(bd.psi, c[2]));
+                if (zs == 0)
+                    s.fzl[m] = vl[4] * face_weno<T>(vl[4], c[0], c[1], c[2], c[3], c[4], c[5], epsw);
+                const T fzh = vl[5] * face_weno<T>(vl[5], c[1], c[2], c[3], c[4], c[5], c[6], epsw);
+                s.pz[m] = fzh - s.fzl[m];
+                s.fzl[m] = fzh;
+                const T mu0 = s.mq[m][1];
+                s.plap[m] = (mrow[1] - mu0) - (mu0 - mrow[-1])
+                          + (mrow[mp] - mu0) - (mu0 - mrow[-mp])
+                          + (s.mq[m][2] - mu0) - (mu0 - s.mq[m][0]);
                 s.pb4[m] = d4<T>(row[-2], row[-1], row[0], row[1], row[2])
                          + d4<T>(colm[p], colm[2 * p], colm[3 * p], colm[4 * p], colm[5 * p])
                          + d4<T>(c[1], c[2], c[3], c[4], c[5]);
             }
         });
-        // ---- RHS into the solve tile
-        ex.phase([&](int tid) {
-            XState<T, A, MI>& s = st[ex.slot(tid)];
-    #pragma unroll
-        for (int m = 0; m < MI; ++m) {
-                if (s.rx[m] < 0) continue;
-                const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
-                const T adv = (fxb[r * L.fxp + x + 1] - fxb[r * L.fxp + x])
-                            + (fyb[(r + 1) * L.fyp + x] - fyb[r * L.fyp + x]) + s.pz[m];
-                const T e = -adv * inv_h + s.plap[m] * lap_s;
-                const int64_t at = (int64_t)z * plane + (int64_t)(t.y0 + r) * nx + x;
-                T rhs = gdt * e - bdt * s.pb4[m];
-                if (pa.e_mode != 0) rhs += rdt * Eb[at];
-                if (pa.e_mode != 2) Eb[at] = e;
-                tb[(x + tw) * L.tbp + r] = A(rhs);
-            }
-        });
-        // ---- halo of the solve tile
-        ex.phase([&](int tid) {
-            const int span = 2 * tw;
-            for (int j = tid; j < rows * span; j += nth) {
-                const int r = j / span, q = j - r * span;
-                const int pp = q < tw ? q - tw : nx + q - tw;
-                tb[(pp + tw) * L.tbp + r] = tb[(map_idx(pp, nx, bd.bc[0]) + tw) * L.tbp + r];
-            }
-        });
-        // ---- x solve
-        ex.phase([&](int tid) {
-            const Chunk ch = line_chunk(tid, rows, nx, tw, X_CHAINS);
-            line_f1<A>(ch, tb, L.tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
-        });
-        ex.phase([&](int tid) {
-            const Chunk ch = line_chunk(tid, rows, nx, tw, X_CHAINS);
-            line_f2<A>(ch, tb, L.tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
-        });
-        ex.phase([&](int tid) {
-            const Chunk ch = line_chunk(tid, rows, nx, tw, X_CHAINS);
-            line_b1<A>(ch, tb, L.tbp, tw, a1, a2, st[ex.slot(tid)].ls);
-        });
-        ex.phase([&](int tid) {
-            const Chunk ch = line_chunk(tid, rows, nx, tw, X_CHAINS);
-            line_b2<A>(ch, tb, L.tbp, tw, a1, a2, st[ex.slot(tid)].ls);
-        });
-        // ---- store q
-        ex.phase([&](int tid) {
-            XState<T, A, MI>& s = st[ex.slot(tid)];
-    #pragma unroll
-        for (int m = 0; m < MI; ++m) {
-                if (s.rx[m] < 0) continue;
-                const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
-                Qb[(int64_t)z * plane + (int64_t)(t.y0 + r) * nx + x] = T(tb[(x + tw) * L.tbp + r]);
-            }
-        });
+    };
+    for (int zs = 0; zs < t.nzc; zs += X_PREFETCH) {
+        plane_step(IC<0>{}, zs);
+        if (X_PREFETCH == 2 && zs + 1 < t.nzc) plane_step(IC<X_PREFETCH - 1>{}, zs + 1);
     }
+    // ---- RHS of the last plane
+    ex.phase([&](int tid) { rhs_plane(st[ex.slot(tid)], t.nzc - 1); });
+    // ---- halos of the solve tile
+    ex.phase([&](int tid) {
+        const int span = 2 * tw;
+        for (int j = tid; j < nlines * span; j += nth) {
+            const int ln = j / span, q = j - ln * span;
+            const int pp = q < tw ? q - tw : nx + q - tw;
+            tb[(pp + tw) * L.tbp + ln] = tb[(map_idx(pp, nx, bcx) + tw) * L.tbp + ln];
+        }
+    });
+    // ---- x solve of all lines at once
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
+        line_f1<A>(ch, tb, L.tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
+        line_f2<A>(ch, tb, L.tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
+        line_b1<A>(ch, tb, L.tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
+        line_b2<A>(ch, tb, L.tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+    });
+    // ---- store q, plane by plane, x fastest
+    ex.phase([&](int tid) {
+        XState<T, A, MI>& s = st[ex.slot(tid)];
+        for (int zs = 0; zs < t.nzc; ++zs) {
+            T* Qz = Qb + (int64_t)(t.z0 + zs) * plane;
+#pragma unroll
+            for (int m = 0; m < MI; ++m) {
+                if (s.rx[m] < 0) continue;
+                const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
+                Qz[s.col[m]] = T(tb[(x + tw) * L.tbp + zs * rows + r]);
+            }
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -656,11 +826,25 @@ CH_HD void pass_line_program(X& ex, LineState<A>* st, const BoxDesc& bd, const P
     const A a1 = A(bd.a1[k]), a2 = A(bd.a2[k]), ic = A(bd.ic[k]);
     A* tile = reinterpret_cast<A*>(smem);
     const int npos = t.len + 2 * tw;
+    // stage the segment with its halos: LB rows of loads in flight per thread
+    const int qstep = nth / Lw;
     ex.phase([&](int tid) {
         const int l = tid % Lw;
-        for (int q = tid / Lw; q < npos; q += nth / Lw) {
-            const int g = map_idx(t.s0 + q - tw, t.n, t.bc);
-            tile[q * Lw + l] = l < nlive ? A(Qin[t.base + (int64_t)g * t.stride + l]) : A(0);
+        const bool on = l < nlive;
+        for (int q0 = tid / Lw; q0 < npos; q0 += qstep * LB) {
+            A v[LB];
+#pragma unroll
+            for (int j = 0; j < LB; ++j) {
+                const int q = q0 + j * qstep;
+                v[j] = A(0);
+                if (q < npos && on)
+                    v[j] = A(Qin[t.base + (int64_t)map_idx(t.s0 + q - tw, t.n, t.bc) * t.stride + l]);
+            }
+#pragma unroll
+            for (int j = 0; j < LB; ++j) {
+                const int q = q0 + j * qstep;
+                if (q < npos) tile[q * Lw + l] = v[j];
+            }
         }
     });
     ex.phase([&](int tid) {
@@ -682,11 +866,30 @@ CH_HD void pass_line_program(X& ex, LineState<A>* st, const BoxDesc& bd, const P
     ex.phase([&](int tid) {
         const int l = tid % Lw;
         if (l >= nlive) return;
-        for (int q = tid / Lw; q < t.len; q += nth / Lw) {
-            T* dst = Qout + t.base + (int64_t)(t.s0 + q) * t.stride + l;
-            const A y = tile[(q + tw) * Lw + l];
-            if (pass == PASS_Z) *dst = T(A(*dst) + y);
-            else *dst = T(y);
+        for (int q0 = tid / Lw; q0 < t.len; q0 += qstep * LB) {
+            if (pass == PASS_Z) {
+                // C += dC: the LB reads of C go out together
+                A c[LB];
+#pragma unroll
+                for (int j = 0; j < LB; ++j) {
+                    const int q = q0 + j * qstep;
+                    c[j] = q < t.len ? A(Qout[t.base + (int64_t)(t.s0 + q) * t.stride + l]) : A(0);
+                }
+#pragma unroll
+                for (int j = 0; j < LB; ++j) {
+                    const int q = q0 + j * qstep;
+                    if (q < t.len)
+                        Qout[t.base + (int64_t)(t.s0 + q) * t.stride + l] =
+                            T(c[j] + tile[(q + tw) * Lw + l]);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < LB; ++j) {
+                    const int q = q0 + j * qstep;
+                    if (q < t.len)
+                        Qout[t.base + (int64_t)(t.s0 + q) * t.stride + l] = T(tile[(q + tw) * Lw + l]);
+                }
+            }
         }
     });
 }

@@ -27,8 +27,10 @@ __device__ __forceinline__ int xcd_task(int wg, int nwg)
     return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + l;
 }
 
-template <typename T, typename A, int MI>
-__global__ void __launch_bounds__(1024)
+// NT bounds the work-group size: 512-thread groups get the full 256 VGPRs a
+// lane can address, 1024-thread groups (x-lines longer than 512) half that.
+template <typename T, typename A, int MI, int NT>
+__global__ void __launch_bounds__(NT)
 k_pass_x(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
          const T* __restrict__ C, const T* __restrict__ U, const T* __restrict__ V,
          const T* __restrict__ W, T* __restrict__ E, T* __restrict__ Q)
@@ -183,17 +185,17 @@ k_interp(const T* __restrict__ src, int64_t sx, int64_t sy, int64_t tnx, int64_t
 // ---------------------------------------------------------------------------
 // host-side launchers (declared in ch_kernels.h)
 // ---------------------------------------------------------------------------
-template <typename T, typename A, int MI>
+template <typename T, typename A, int MI, int NT>
 static hipError_t launch_x(int nwg, int nth, size_t lds, hipStream_t st, const chd::BoxDesc* boxes,
                            int nbox, const chd::PassArgs& pa, const void* C, const void* U,
                            const void* V, const void* W, void* E, void* Q)
 {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)&k_pass_x<T, A, MI>,
+        hipError_t e = hipFuncSetAttribute((const void*)&k_pass_x<T, A, MI, NT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_pass_x<T, A, MI>), dim3(nwg), dim3(nth), lds, st, boxes, nbox, pa,
+    hipLaunchKernelGGL((k_pass_x<T, A, MI, NT>), dim3(nwg), dim3(nth), lds, st, boxes, nbox, pa,
                        (const T*)C, (const T*)U, (const T*)V, (const T*)W, (T*)E, (T*)Q);
     return hipGetLastError();
 }
@@ -204,8 +206,10 @@ hipError_t launch_pass_x(int mi, int nwg, int nth, size_t lds, hipStream_t st,
                          const void* C, const void* U, const void* V, const void* W, void* E,
                          void* Q)
 {
-    if (mi == 1) return launch_x<T, A, 1>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
-    return launch_x<T, A, 2>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    if (mi == 1 && nth <= 512)
+        return launch_x<T, A, 1, 512>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    if (mi == 1) return launch_x<T, A, 1, 1024>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    return launch_x<T, A, 2, 1024>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
 }
 
 template <typename T, typename A>

@@ -250,30 +250,42 @@ inline ch_status plan_dt(Plan& P, double dt)
     const int xcap = X_MAX_THREADS * P.mi;
     if (nxm > xcap) return P.fail(CH_EUNSUPPORTED, "x extent too large");
     // ---- x pass: rows per task and planes per task
+    // chunks per x line (fixed by the line: see line_chunk_len)
+    auto nch_x = [](int n) { return std::max(1, std::min(n / 16, chd::X_CHAINS)); };
+    auto xlds = [&](int R, int zc) {
+        return chd::x_layout(nxm, R, zc, P.tw_max, (int)sT, (int)sA).total;
+    };
     int R = P.opt.x_rows;
     if (R == 0) {
-        const int cand[] = {16, 12, 8, 6, 4, 3, 2, 1};
+        const int cand[] = {2, 1};
         for (int c : cand)
-            if (c <= std::max(1, nym) && c * nxm <= xcap &&
-                chd::x_layout(nxm, c, P.tw_max, (int)sT, (int)sA).total <= LDS_BUDGET) {
+            if (c <= std::max(1, nym) && c * nxm <= xcap && xlds(c, 1) <= LDS_BUDGET) {
                 R = c;
                 break;
             }
         if (R == 0) R = 1;
     }
     if (R * nxm > xcap) return P.fail(CH_EINVAL, "x_rows too large for the x extent");
-    if (chd::x_layout(nxm, R, P.tw_max, (int)sT, (int)sA).total > LDS_HARD)
-        return P.fail(CH_EUNSUPPORTED, "x lines too long for LDS");
     P.x_rows = R;
     P.x_threads = ((R * nxm + P.mi - 1) / P.mi + 63) / 64 * 64;
+    if (P.x_threads > X_MAX_THREADS) return P.fail(CH_EINVAL, "x_rows too large for the x extent");
+    // planes per task: every line of a task needs its chunks' threads
+    int zlim = 64;
+    for (int b = 0; b < P.nbox; ++b) {
+        const int rb = std::min(R, P.boxes[b].n[1]);
+        zlim = std::min(zlim, P.x_threads / (rb * nch_x(P.boxes[b].n[0])));
+    }
     int zc = P.opt.z_chunk;
     if (zc == 0) {
         // enough tasks to fill the chip a few times over, marching as far as
         // that allows (each task reloads 6 planes to start its march)
         const int64_t rows_total = cells / std::max(1, nxm);
-        const int64_t want = 2048;
-        zc = (int)std::max<int64_t>(1, std::min<int64_t>(32, rows_total / R / want));
+        zc = (int)std::max<int64_t>(1, std::min<int64_t>(16, rows_total / R / 2048));
+        zc = std::min(zc, zlim);
+        while (zc > 1 && xlds(R, zc) > LDS_BUDGET) --zc;
     }
+    if (zc > zlim) return P.fail(CH_EINVAL, "z_chunk too large for this x extent");
+    if (xlds(R, zc) > LDS_HARD) return P.fail(CH_EUNSUPPORTED, "x tile too large for LDS");
     P.zc = zc;
     // ---- y/z passes: lanes of 128 bytes, whole lines when they fit
     P.lanes = (int)(128 / sA);
@@ -313,7 +325,7 @@ inline ch_status plan_dt(Plan& P, double dt)
         }
     }
     for (int p = 0; p < 3; ++p) P.ntask[p] = (int)t0[p];
-    P.lds[0] = chd::x_layout(nxm, R, P.tw_max, (int)sT, (int)sA).total;
+    P.lds[0] = xlds(R, zc);
     P.lds[1] = (size_t)(P.seg_max[0] + 2 * P.tw_max) * P.lanes * sA;
     P.lds[2] = (size_t)(P.seg_max[1] + 2 * P.tw_max) * P.lanes * sA;
     for (int p = 1; p < 3; ++p)
@@ -332,6 +344,7 @@ inline chd::PassArgs pass_args(const Plan& P, int k, int pass)
     pa.tw_max = P.tw_max;
     pa.nx_max = P.nx_max;
     pa.seg_max = pass == 2 ? P.seg_max[1] : P.seg_max[0];
+    pa.zcmax = P.zc;
     return pa;
 }
 
