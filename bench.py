@@ -7,22 +7,43 @@ resident in HBM before the timed region starts.
 
 A step is one full RK3 step (3 substages x {x pass, y solve, z solve}).
 `value` is the FP32 throughput in grid-point updates per second (Gpts/s);
-the FP64 throughput, the FP32-vs-FP64 error after the timed steps, the
+the FP64 throughput, the FP32-vs-FP64 error after warmup + timed steps, the
 roofline of the dominant kernel (the x pass) and the FP64 CPU oracle's
-throughput on a bounded sample are reported on the same JSON line.
+throughput on a bounded sample of the same workload are reported on the
+same JSON line.
 
     python bench.py [--steps K] [--warmup W]
+    python bench.py --counter-probe    # 2 FP32 steps + one 256 MiB device
+                                       # copy, for rocprofv3 counter runs
 """
 import argparse
+import hashlib
 import json
-import math
 import os
+import re
 import sys
 import time
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
+# Vector FMA rate without packed FP32 (which this library does not emit):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz, the same in FP32 and FP64.
+VALU_PEAK_TFLOPS = 78.6
 METRIC = ("CH grid-point updates/s (Gpts/s) FP32 & batched vs FP64 at stated error; "
           "%HBM peak")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_x_256cube_fp32_traffic.md")
+X_SOURCES = ("ch_device.h", "ch_kernels.hip", "ch_plan.h")
+
+
+def x_pass_flops_per_point():
+    """Algorithmic flops of one x-pass launch per grid point (fused
+    multiply-add = 2, add / multiply / reciprocal = 1):
+      WENO5 face value times velocity, 55 per face, one face per cell and
+      direction: 165;  flux divergence and 1/h: 6;  psi'(C) and its 7-point
+      Laplacian: 13;  three fourth differences and their sum: 26;  E and the
+      RHS: 7;  the x-line recurrences (forward 5, backward 4): 9."""
+    return 165 + 6 + 13 + 26 + 7 + 9
 
 
 def x_pass_bytes_per_point(s):
@@ -38,6 +59,49 @@ def step_bytes_per_point(s):
     return 34.0 * s
 
 
+def x_source_hash():
+    h = hashlib.sha256()
+    for f in X_SOURCES:
+        with open(os.path.join(ROOT, "paper_2105_01865_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per x-pass launch from the committed counter summary, if it
+    was taken on the current kernel sources; otherwise None."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    src = re.search(r"^source-hash:\s*(\w+)", text, re.M)
+    val = re.search(r"^traffic-bytes-per-launch:\s*([0-9.eE+]+)", text, re.M)
+    if not src or not val or src.group(1) != x_source_hash():
+        return None
+    return float(val.group(1))
+
+
+def counter_probe():
+    """A short run for rocprofv3 counter passes: two FP32 steps of the
+    workload, then one device-to-device copy of 256 MiB (the kernel whose
+    FETCH_SIZE / WRITE_SIZE readings calibrate the counters)."""
+    import torch
+    from paper_2105_01865_amd import ch, inputs
+    wl = inputs.make_workload(2)
+    stream = torch.cuda.Stream()
+    s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, precision="fp32", stream=stream)
+    s.set_field(torch.from_numpy(wl.C).to("cuda", torch.float32))
+    U, V, W = (torch.from_numpy(a).to("cuda", torch.float32) for a in (wl.u, wl.v, wl.w))
+    s.step(U, V, W, wl.dt, 2)
+    torch.cuda.synchronize()
+    s.close()
+    a = torch.ones(64 << 20, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print("counter probe done", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -45,12 +109,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--n", type=int, default=None, help="shrink the box (testing only)")
+    ap.add_argument("--counter-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library "
               "has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.counter_probe:
+        counter_probe()
+        return
 
     import numpy as np
     import torch
@@ -58,7 +125,7 @@ def main():
     from paper_2105_01865_amd import ch, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    wl = inputs.make_workload(2, n=args.n)
+    wl = inputs.make_workload(2)
     pts = wl.points
     stream = torch.cuda.Stream()
     h = wl.h
@@ -84,7 +151,7 @@ def main():
         m1 = s.mass()
         C = s.get_field().double().cpu().numpy()
         cfg = s.config()
-        # the dominant kernel, timed launch by launch with HIP events on the
+        # every kernel, timed launch by launch with HIP events on the
         # library's stream over a profiled run of the same steps
         s.set_field(C0)
         s.profile(True)
@@ -109,15 +176,18 @@ def main():
     v64vol = float((C64 >= 0.5).sum()) * h ** 3
     vol_err = abs(v32vol - v64vol) / v64vol
 
+    def kern(r):
+        return {k: dict(avg_us=round(1e3 * r["prof"][k][0] / max(1, r["prof"][k][1]), 2),
+                        launches=r["prof"][k][1]) for k in ("x", "y", "z")}
+
     # roofline of the x pass (FP32 run: the headline precision)
     xms, xn = r32["prof"]["x"]
     x_avg_s = xms / xn * 1e-3
+    x_flops = x_pass_flops_per_point() * pts
+    achieved = x_flops / x_avg_s / 1e12
     x_bytes = x_pass_bytes_per_point(4) * pts
-    achieved = x_bytes / x_avg_s / 1e9
-    kern = {k: dict(avg_us=1e3 * r32["prof"][k][0] / max(1, r32["prof"][k][1]),
-                    launches=r32["prof"][k][1]) for k in ("x", "y", "z")}
-    kern64 = {k: dict(avg_us=1e3 * r64["prof"][k][0] / max(1, r64["prof"][k][1]),
-                      launches=r64["prof"][k][1]) for k in ("x", "y", "z")}
+    x_gbs = x_bytes / x_avg_s / 1e9
+    traffic = measured_traffic()
 
     line = {
         "metric": METRIC,
@@ -145,25 +215,38 @@ def main():
                                   "drop_volume_err": vol_err},
         "hbm_frac_step_model": round(step_bytes_per_point(4) * pts /
                                      (r32["ms"] / nstep * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "roofline": {"bound": "hbm", "kernel": "k_pass_x (explicit terms + RHS + x solve)",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_point": x_pass_bytes_per_point(4),
+        "roofline": {"bound": "alu", "kernel": "k_pass_x (explicit terms + RHS + x solve), fp32",
+                     "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
+                     "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 "
+                     "FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "flops_per_point": x_pass_flops_per_point(),
                      "avg_launch_us": round(x_avg_s * 1e6, 2),
+                     "hbm_view": {"bytes_per_point": x_pass_bytes_per_point(4),
+                                  "achieved_gbs": round(x_gbs, 1),
+                                  "frac_of_8000": round(x_gbs / HBM_PEAK_GBS, 4)},
                      "window": f"{args.profile_steps} profiled steps, HIP events per launch"},
-        "kernels_fp32": kern,
-        "kernels_fp64": kern64,
+        "kernels_fp32": kern(r32),
+        "kernels_fp64": kern(r64),
     }
 
     if not args.no_cpu_baseline:
+        # the FP64 oracle on the same workload, whole RK3 steps until about
+        # 10 s of work (at most 30 s)
         import oracle
+        C = wl.C
+        steps = 0
         t0 = time.perf_counter()
-        oracle.step(wl.C, wl.u, wl.v, wl.w, h, wl.Cn, wl.Pe, wl.dt, 1)
-        el = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": round(pts / el / 1e9, 6), "unit": "Gpts/s",
+        while True:
+            C = oracle.step(C, wl.u, wl.v, wl.w, h, wl.Cn, wl.Pe, wl.dt, 1)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= 10.0 or el / steps * (steps + 1) > 30.0:
+                break
+        line["cpu_baseline"] = {"value": round(pts * steps / el / 1e9, 6), "unit": "Gpts/s",
                                 "cores": oracle.threads(), "kind": "oracle",
-                                "sample": f"1 RK3 step of the same {wl.shape[2]}^3 workload in "
-                                          f"FP64 ({el:.1f} s)"}
+                                "sample": f"{steps} RK3 step(s) of the same {wl.shape[2]}^3 "
+                                          f"workload in FP64, {el:.1f} s"}
     print(json.dumps(line), flush=True)
 
 

@@ -96,9 +96,19 @@ CH_HD int map_idx(int i, int n, int bc)
     return m < n ? m : p - 1 - m;
 }
 
-// 1/x: one hardware reciprocal (1 ulp) in single precision on the GPU,
-// a correctly rounded division otherwise.
-CH_HD double fast_rcp(double x) { return 1.0 / x; }
+// 1/x: on the GPU one hardware reciprocal (1 ulp) in single precision, and in
+// double the hardware estimate refined by two Newton steps (r += r (1 - x r)),
+// which leaves an error of a few ulp; a correctly rounded division on the host.
+CH_HD double fast_rcp(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+#else
+    return 1.0 / x;
+#endif
+}
 CH_HD float fast_rcp(float x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -108,37 +118,51 @@ CH_HD float fast_rcp(float x)
 #endif
 }
 
+// Wait until every global load the wave has issued has landed (vmcnt(0);
+// expcnt and lgkmcnt untouched).  Used at the end of a loop's prologue: a load
+// left pending there makes the compiler's conservative merge at the loop
+// header wait, in every iteration, for the iteration's own prefetches.
+CH_HD void wait_loads()
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+#endif
+}
+
 // Fifth-order WENO (Jiang-Shu, point values as cell averages): value at the
 // face between c and d with upwind side a.
 //
 // Arithmetic arranged for few instructions, exact in real arithmetic:
-//  - the smoothness indicators 13/12 t^2 + 1/4 u^2 and eps are scaled by
-//    12/13 (the normalised weights do not change), so eps + beta is
-//    t^2 + (3/13) u^2 + (12/13) eps, two fused multiply-adds;
-//  - the weights d_j / (eps + beta_j)^2 are formed over the common
-//    denominator prod_j (eps + beta_j)^2, which leaves one division;
-//  - the linear weights (1/10, 6/10, 3/10) and the 1/6 of the candidate
-//    stencils are folded into the stencil coefficients.
+//  - everything is written in the first differences d1..d4 of the stencil:
+//    per substencil k the second difference t_k and the combination u_k
+//    (a - 4b + 3c, d - b, 3c - 4d + e), so that beta_k = 13/12 t_k^2 +
+//    1/4 u_k^2 and the candidate value is q_k = c + t_k/12 + s_k u_k/4
+//    (s = +1, +1, -1);
+//  - the smoothness indicators and eps are scaled by 12/13 (the normalised
+//    weights do not change): eps + beta is t^2 + (3/13) u^2 + (12/13) eps;
+//  - the weights g_k / (eps + beta_k)^2 (g = 1/10, 6/10, 3/10) are formed
+//    over the common denominator prod_k (eps + beta_k)^2, which leaves one
+//    reciprocal; the factor 10 g_k is folded into the q_k - c coefficients.
 // `epsw` is (12/13) eps.
 template <typename T>
 CH_HD T weno5(T a, T b, T c, T d, T e, T epsw)
 {
     const T k3 = T(3) / T(13);
-    const T t0 = (a + c) - T(2) * b, u0 = (a - T(4) * b) + T(3) * c;
-    const T t1 = (b + d) - T(2) * c, u1 = b - d;
-    const T t2 = (c + e) - T(2) * d, u2 = (T(3) * c - T(4) * d) + e;
+    const T d1 = b - a, d2 = c - b, d3 = d - c, d4 = e - d;
+    const T t0 = d2 - d1, t1 = d3 - d2, t2 = d4 - d3;
+    const T u0 = T(3) * d2 - d1, u1 = d2 + d3, u2 = d4 - T(3) * d3;
     const T e0 = t0 * t0 + ((k3 * u0) * u0 + epsw);
     const T e1 = t1 * t1 + ((k3 * u1) * u1 + epsw);
     const T e2 = t2 * t2 + ((k3 * u2) * u2 + epsw);
     const T p0 = e0 * e0, p1 = e1 * e1, p2 = e2 * e2;
     const T p12 = p1 * p2, p02 = p0 * p2, p01 = p0 * p1;
-    // 1/10, 6/10, 3/10 times the candidate reconstructions (times 6)
-    const T q0 = (T(0.2) * a - T(0.7) * b) + T(1.1) * c;
-    const T q1 = (T(3) * c - T(0.6) * b) + T(1.2) * d;
-    const T q2 = (T(0.6) * c + T(1.5) * d) - T(0.3) * e;
-    const T num = p12 * q0 + (p02 * q1 + p01 * q2);
-    const T den = T(0.6) * p12 + (T(3.6) * p02 + T(1.8) * p01);
-    return num * fast_rcp(den);
+    // 10 g_k (q_k - c)
+    const T r0 = T(1) / T(12) * t0 + T(0.25) * u0;
+    const T r1 = T(0.5) * t1 + T(1.5) * u1;
+    const T r2 = T(0.25) * t2 - T(0.75) * u2;
+    const T num = p12 * r0 + (p02 * r1 + p01 * r2);
+    const T den = p12 + (T(6) * p02 + T(3) * p01);
+    return c + num * fast_rcp(den);
 }
 
 template <typename T>
@@ -153,13 +177,13 @@ CH_HD Cubic<T> cubic(const double* p)
     return Cubic<T>{T(p[0]), T(p[1]), T(p[2]), T(p[3])};
 }
 
-// Fourth difference (1,-4,6,-4,1) in nested form: differences of adjacent
-// values first, which keeps single precision accurate on smooth data.
+// Fourth difference (1,-4,6,-4,1) from the differences to the centre value,
+// which keeps single precision accurate on smooth data.
 template <typename T>
 CH_HD T d4(T m2, T m1, T c0, T p1, T p2)
 {
-    const T a = m1 - m2, b = c0 - m1, c = p1 - c0, d = p2 - p1;
-    return ((d - c) - (c - b)) - ((c - b) - (b - a));
+    const T s2 = (m2 - c0) + (p2 - c0), s1 = (m1 - c0) + (p1 - c0);
+    return s2 - T(4) * s1;
 }
 
 // compile-time integer tag
@@ -484,13 +508,16 @@ struct XState {
     T nvel[X_PREFETCH][MI][4];   // u low, u high, v low, v high
     T nwh[X_PREFETCH][MI];       // w on the high face
     T neold[X_PREFETCH][MI];     // old E
-    T nhalo[X_PREFETCH][MI][6];  // C of the six halo rows at column hx[m]
+    T nhalo[X_PREFETCH][MI][6];  // C of the halo rows hr with hr mod rows equal to
+                                 // the owned row, at the owned column
     int rx[MI];      // (row << 16) | x of each owned cell, -1 if none
     unsigned col[MI];   // y nx + x: offset of the cell in a plane of C, E, v, w
     unsigned colu[MI];  // y fx + x: offset of its low x face in a plane of u
     unsigned colvh[MI]; // offset of its high y face in a plane of v
-    int hx[MI];      // halo-row column this thread loads, -1 if none
-    int xmask[MI];   // halo columns of the plane tiles fed by the owned column
+    int cxp[MI];     // halo column (-3 .. nx+2) that copies the owned column in
+                     // the C tile, or the column itself if none (nx >= 6)
+    int cxm[MI];     // the same for the psi'(C) tile (-1 .. nx)
+    int xmask[MI];   // all halo columns fed by the owned column (any nx)
     LineState<A> ls;
 };
 
@@ -528,15 +555,18 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
     const int rows = t.rows;
     const int ncell = rows * nx;
     const int nlines = rows * t.nzc;
-    // the six halo rows (y0-3 .. y0-1, y0+rows .. y0+rows+2) and their tile rows
-    int hrow[6];
+    // the six halo rows (y0-3 .. y0-1, y0+rows .. y0+rows+2), their tile rows,
+    // and the owned row whose threads load them (hr mod rows)
+    int hrow[6], hown[6];
     unsigned hoff[6];
 #pragma unroll
     for (int hr = 0; hr < 6; ++hr) {
         const int prow = hr < 3 ? hr : rows + hr;
         hrow[hr] = prow;
+        hown[hr] = hr % rows;
         hoff[hr] = (unsigned)(map_idx(t.y0 - 3 + prow, ny, bd.bc[1]) * nx);
     }
+    const bool one_copy = nx >= 6;   // every column feeds at most one halo column
 
     // all global loads of plane z for the owned cells, into prefetch set b
     // (uniform plane bases, 32-bit offsets within a plane)
@@ -559,19 +589,21 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 s.nvel[b][m][3] = r == rows - 1 ? Vz[s.colvh[m]] : T(0);
                 s.nwh[b][m] = Wh[s.col[m]];
                 s.neold[b][m] = pa.e_mode != 0 ? Ez[s.col[m]] : T(0);
-            }
-            if (s.hx[m] >= 0) {
 #pragma unroll
-                for (int hr = 0; hr < 6; ++hr) s.nhalo[b][m][hr] = Cz[hoff[hr] + s.hx[m]];
+                for (int hr = 0; hr < 6; ++hr)
+                    if (hown[hr] == r) s.nhalo[b][m][hr] = Cz[hoff[hr] + x];
             }
         }
     };
-    // a value of plane-tile row prow at column x, and its copies in the halo
-    // columns (bit q of mask: column q - 3 for q < 3, nx + q - 3 otherwise)
-    auto put = [&](T* tile, int pitch, int halo, int prow, int x, int mask, T v) {
+    // a value of an owned row at column x, and its copies in the halo columns:
+    // the one column cx when nx >= 6, else every bit q of mask (column q - 3
+    // for q < 3, nx + q - 3 otherwise)
+    auto put = [&](T* tile, int pitch, int halo, int prow, int x, int cx, int mask, T v) {
         T* rp = tile + prow * pitch + halo;
         rp[x] = v;
-        if (mask) {
+        if (one_copy) {
+            rp[cx] = v;
+        } else if (mask) {
 #pragma unroll
             for (int q = 3 - halo; q < 3 + halo; ++q)
                 if ((mask >> q) & 1) rp[q < 3 ? q - 3 : nx + q - 3] = v;
@@ -604,9 +636,9 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
         for (int m = 0; m < MI; ++m) {
             const int item = tid + nth * m;
             s.rx[m] = item < ncell ? ((item / nx) << 16) | (item % nx) : -1;
-            const int hxm = tid + nth * m;
-            s.hx[m] = hxm < nx ? hxm : -1;
             int mask = 0;
+            s.cxp[m] = 0;
+            s.cxm[m] = 0;
             if (s.rx[m] >= 0) {
                 const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
                 const int y = t.y0 + r;
@@ -614,8 +646,14 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 s.col[m] = (unsigned)(y * nx + x);
                 s.colu[m] = (unsigned)(y * fx + x);
                 s.colvh[m] = (unsigned)(yh * nx + x);
+                s.cxp[m] = x;
+                s.cxm[m] = x;
                 for (int q = 0; q < 6; ++q)
-                    if (map_idx(q < 3 ? q - 3 : nx + q - 3, nx, bcx) == x) mask |= 1 << q;
+                    if (map_idx(q < 3 ? q - 3 : nx + q - 3, nx, bcx) == x) {
+                        mask |= 1 << q;
+                        s.cxp[m] = q < 3 ? q - 3 : nx + q - 3;
+                        if (q == 2 || q == 3) s.cxm[m] = q == 2 ? -1 : nx;
+                    }
 #pragma unroll
                 for (int q = 1; q < 7; ++q)
                     s.cz[m][q] = Cb[(int64_t)map_idx(t.z0 - 4 + q, nz, bd.bc[2]) * plane + s.col[m]];
@@ -625,6 +663,7 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
             }
             s.xmask[m] = mask;
         }
+        wait_loads();
         fetch(s, IC<0>{}, t.z0);
         if (X_PREFETCH == 2 && t.nzc > 1) fetch(s, IC<X_PREFETCH - 1>{}, t.z0 + 1);
     });
@@ -655,15 +694,17 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                     if (zs > 0) s.vel[m][4] = s.vel[m][5];
                     s.vel[m][5] = s.nwh[b][m];
                     s.eold_next[m] = s.neold[b][m];
-                }
-                if (s.hx[m] >= 0) {
-                    const int x = s.hx[m];
-                    const int mask = s.rx[m] >= 0 && (s.rx[m] & 0xffff) == x ? s.xmask[m] : 0;
+                    // halo rows (no halo columns: only owned rows are read
+                    // across x), and psi'(C) of the two next to the tile
+                    const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
 #pragma unroll
-                    for (int hr = 0; hr < 6; ++hr) put(pb, L.pbp, 3, hrow[hr], x, mask, s.nhalo[b][m][hr]);
-                    // psi'(C) of the two halo rows next to the tile
-                    put(mb, L.mbp, 1, 0, x, mask, mu(s.nhalo[b][m][2]));
-                    put(mb, L.mbp, 1, rows + 1, x, mask, mu(s.nhalo[b][m][3]));
+                    for (int hr = 0; hr < 6; ++hr) {
+                        if (hown[hr] != r) continue;
+                        const T v = s.nhalo[b][m][hr];
+                        pb[hrow[hr] * L.pbp + 3 + x] = v;
+                        if (hr == 2) mb[1 + x] = mu(v);
+                        if (hr == 3) mb[(rows + 1) * L.mbp + 1 + x] = mu(v);
+                    }
                 }
             }
             // start the loads X_PREFETCH planes up, before any store of this phase
@@ -678,8 +719,8 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 s.mq[m][0] = s.mq[m][1];
                 s.mq[m][1] = s.mq[m][2];
                 s.mq[m][2] = mu(s.cz[m][4]);
-                put(pb, L.pbp, 3, r + 3, x, s.xmask[m], own[m]);
-                put(mb, L.mbp, 1, r + 1, x, s.xmask[m], s.mq[m][1]);
+                put(pb, L.pbp, 3, r + 3, x, s.cxp[m], s.xmask[m], own[m]);
+                put(mb, L.mbp, 1, r + 1, x, s.cxm[m], s.xmask[m], s.mq[m][1]);
             }
         });
         // ---- face fluxes, Laplacian of psi'(C), fourth differences
@@ -715,9 +756,8 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 s.pz[m] = fzh - s.fzl[m];
                 s.fzl[m] = fzh;
                 const T mu0 = s.mq[m][1];
-                s.plap[m] = (mrow[1] - mu0) - (mu0 - mrow[-1])
-                          + (mrow[mp] - mu0) - (mu0 - mrow[-mp])
-                          + (s.mq[m][2] - mu0) - (mu0 - s.mq[m][0]);
+                s.plap[m] = ((mrow[1] + mrow[-1]) + (mrow[mp] + mrow[-mp]))
+                          + (s.mq[m][2] + s.mq[m][0]) - T(6) * mu0;
                 s.pb4[m] = d4<T>(row[-2], row[-1], row[0], row[1], row[2])
                          + d4<T>(colm[p], colm[2 * p], colm[3 * p], colm[4 * p], colm[5 * p])
                          + d4<T>(c[1], c[2], c[3], c[4], c[5]);

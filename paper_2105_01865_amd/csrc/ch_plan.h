@@ -24,6 +24,11 @@ constexpr double RK_R[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 
 constexpr size_t LDS_BUDGET = 64 * 1024;   // default per work-group
 constexpr size_t LDS_HARD = 160 * 1024;    // gfx950 LDS per CU
+// x-pass tile budget: the share of a CU's LDS that lets as many 256-thread
+// work-groups run as the x kernel's registers allow (4 in single precision,
+// 3 in double)
+constexpr size_t X_LDS_BUDGET_F32 = 40 * 1024;
+constexpr size_t X_LDS_BUDGET_F64 = 53 * 1024;
 constexpr int X_MAX_THREADS = 1024;        // largest x-pass work-group
 
 // cells of an x-pass plane tile per thread: one, two for very long x lines
@@ -255,15 +260,13 @@ inline ch_status plan_dt(Plan& P, double dt)
     auto xlds = [&](int R, int zc) {
         return chd::x_layout(nxm, R, zc, P.tw_max, (int)sT, (int)sA).total;
     };
+    const size_t xbudget = sT == 4 ? X_LDS_BUDGET_F32 : X_LDS_BUDGET_F64;
     int R = P.opt.x_rows;
     if (R == 0) {
-        const int cand[] = {2, 1};
-        for (int c : cand)
-            if (c <= std::max(1, nym) && c * nxm <= xcap && xlds(c, 1) <= LDS_BUDGET) {
-                R = c;
-                break;
-            }
-        if (R == 0) R = 1;
+        // about 256 threads per work-group: one row of a long line, several
+        // of short ones (each extra row also shares its y faces)
+        R = std::max(1, std::min({256 / std::max(1, nxm), std::max(1, nym), 16}));
+        while (R > 1 && (R * nxm > xcap || xlds(R, 1) > xbudget)) --R;
     }
     if (R * nxm > xcap) return P.fail(CH_EINVAL, "x_rows too large for the x extent");
     P.x_rows = R;
@@ -282,7 +285,7 @@ inline ch_status plan_dt(Plan& P, double dt)
         const int64_t rows_total = cells / std::max(1, nxm);
         zc = (int)std::max<int64_t>(1, std::min<int64_t>(16, rows_total / R / 2048));
         zc = std::min(zc, zlim);
-        while (zc > 1 && xlds(R, zc) > LDS_BUDGET) --zc;
+        while (zc > 1 && xlds(R, zc) > xbudget) --zc;
     }
     if (zc > zlim) return P.fail(CH_EINVAL, "z_chunk too large for this x extent");
     if (xlds(R, zc) > LDS_HARD) return P.fail(CH_EUNSUPPORTED, "x tile too large for LDS");
