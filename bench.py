@@ -102,6 +102,101 @@ def counter_probe():
     print("counter probe done", flush=True)
 
 
+def _timed_events(stream, fn):
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def bench_ensemble(args, stream):
+    """The batched ensemble: 48 independent periodic boxes with edges from
+    {48, 64, 96, 128, 160, 192}, 1-20 drops each, per-box ABC flows; all boxes
+    advance in one graph launch per step."""
+    import numpy as np
+    import torch
+    from paper_2105_01865_amd import ch, inputs
+    E = inputs.ensemble(48)
+    pts = sum(w.points for w in E)
+    res = {}
+    fields = {}
+    for prec in ("fp32", "fp64"):
+        b = ch.Batch([w.shape for w in E], [w.h for w in E], [w.Cn for w in E],
+                     [w.Pe for w in E], stream=stream, precision=prec)
+        U, V, W = (b.pack([getattr(w, f) for w in E], f) for f in "uvw")
+        b.set_field(b.pack([w.C for w in E], "c"))
+        m0 = np.array(b.mass())
+        b.step(U, V, W, 1e-4, args.warmup)
+        ms = _timed_events(stream, lambda: b.step(U, V, W, 1e-4, args.ensemble_steps))
+        m1 = np.array(b.mass())
+        fields[prec] = b.get_field().double().cpu().numpy()
+        b.profile(True)
+        b.step(U, V, W, 1e-4, 5)
+        kern = {k: b.profile_read(k) for k in ("x", "y", "z")}
+        b.profile(False)
+        b.close()
+        res[prec] = {"value": round(pts * args.ensemble_steps / (ms * 1e-3) / 1e9, 4),
+                     "unit": "Gpts/s", "ms_per_step": round(ms / args.ensemble_steps, 4),
+                     "max_box_mass_drift": float(np.max(np.abs(m1 - m0) / np.abs(m0))),
+                     "kernels_avg_us": {k: round(1e3 * v[0] / max(1, v[1]), 1)
+                                        for k, v in kern.items()}}
+    d = fields["fp32"] - fields["fp64"]
+    return {"workload": "48 periodic boxes, edge ~ U{48,64,96,128,160,192}, h = 1/edge, "
+                        "1-20 tanh drops R~U[4,12]h, ABC flow A,B,C~U[0.05,0.2], dt=1e-4",
+            "points": pts, "steps": args.ensemble_steps, "fp32": res["fp32"], "fp64": res["fp64"],
+            "fp32_over_fp64": round(res["fp32"]["value"] / res["fp64"]["value"], 3),
+            "l2_rel_fp32_vs_fp64": float(np.linalg.norm(d) / np.linalg.norm(fields["fp64"]))}
+
+
+def bench_multires(args, stream):
+    """The multiple-resolution workload: 512^3 fine mesh, periodic in x and y,
+    no-flux walls in z, 1000 drops; the velocity lives on a 256 x 256 x 192
+    mesh stretched in z and is transferred to the fine faces every step."""
+    import numpy as np
+    import torch
+    from paper_2105_01865_amd import ch, inputs
+    wl = inputs.make_workload(3)
+    zf, uc, vc, wc = (wl.coarse[k] for k in ("zf", "uc", "vc", "wc"))
+    res = {}
+    fields = {}
+    for prec in ("fp32", "fp64"):
+        dt_ = torch.float32 if prec == "fp32" else torch.float64
+        s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, bc=wl.bc, precision=prec, stream=stream)
+        ip = ch.Interp(wl.shape, wl.h, uc.shape, zf, precision=prec, stream=stream)
+        UC, VC, WC = (torch.from_numpy(a).to("cuda", dt_) for a in (uc, vc, wc))
+        s.set_field(torch.from_numpy(wl.C).to("cuda", dt_))
+        m0 = s.mass()
+        s.step_multires(ip, UC, VC, WC, wl.dt, args.warmup)
+        ms = _timed_events(stream, lambda: s.step_multires(ip, UC, VC, WC, wl.dt,
+                                                           args.multires_steps))
+        m1 = s.mass()
+        fields[prec] = s.get_field().double().cpu().numpy()
+        s.profile(True)
+        s.step_multires(ip, UC, VC, WC, wl.dt, 5)
+        kern = {k: s.profile_read(k) for k in ("x", "y", "z", "interp")}
+        s.profile(False)
+        s.close()
+        ip.close()
+        res[prec] = {"value": round(wl.points * args.multires_steps / (ms * 1e-3) / 1e9, 4),
+                     "unit": "Gpts/s", "ms_per_step": round(ms / args.multires_steps, 4),
+                     "mass_drift": abs(m1 - m0) / abs(m0),
+                     "kernels_avg_us": {k: round(1e3 * v[0] / max(1, v[1]), 1)
+                                        for k, v in kern.items()}}
+    d = fields["fp32"] - fields["fp64"]
+    return {"workload": "512^3 fine mesh, periodic x,y, no-flux z, 1000 tanh drops R~U[4,12]h; "
+                        "velocity on 256x256x192 (tanh-stretched z) transferred every step "
+                        "(transfer inside the step time)",
+            "points": wl.points, "steps": args.multires_steps, "dt": wl.dt,
+            "fp32": res["fp32"], "fp64": res["fp64"],
+            "fp32_over_fp64": round(res["fp32"]["value"] / res["fp64"]["value"], 3),
+            "l2_rel_fp32_vs_fp64": float(np.linalg.norm(d) / np.linalg.norm(fields["fp64"]))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +204,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=200)
+    ap.add_argument("--multires-steps", type=int, default=100)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched-ensemble and multiple-resolution lines")
     ap.add_argument("--counter-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -229,6 +328,10 @@ def main():
         "kernels_fp32": kern(r32),
         "kernels_fp64": kern(r64),
     }
+
+    if not args.no_extra:
+        line["batched"] = bench_ensemble(args, stream)
+        line["multires"] = bench_multires(args, stream)
 
     if not args.no_cpu_baseline:
         # the FP64 oracle on the same workload, whole RK3 steps until about

@@ -178,7 +178,9 @@ void ch_batch_destroy(ch_batch* b);
  * y; no-flux z) by tensor-product cubic Hermite interpolation with four
  * points per direction (slopes: chord through the two neighbours; beyond a
  * wall the tangential components continue evenly, the normal one oddly).
- * The 1-D stencils are built once at creation.  Coarse arrays: uc, vc
+ * The 1-D stencils are built once at creation; the coarse mesh needs at
+ * least 4 cells per axis and at most 8192 along x (CH_EINVAL /
+ * CH_EUNSUPPORTED otherwise).  Coarse arrays: uc, vc
  * [ncz][ncy][ncx], wc [ncz+1][ncy][ncx]; fine: u, v [nz][ny][nx],
  * w [nz+1][ny][nx]; all device memory in the given precision. */
 ch_status ch_interp_create(const ch_grid* fine, int64_t ncx, int64_t ncy, int64_t ncz,

@@ -27,8 +27,9 @@ __device__ __forceinline__ int xcd_task(int wg, int nwg)
     return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + l;
 }
 
-// NT bounds the work-group size: 512-thread groups get the full 256 VGPRs a
-// lane can address, 1024-thread groups (x-lines longer than 512) half that.
+// NT bounds the work-group size and so the registers per lane: 512 VGPRs per
+// SIMD lane over the group's waves per SIMD (256 for 512 threads, 170 for
+// 768, 128 for 1024).
 template <typename T, typename A, int MI, int NT>
 __global__ void __launch_bounds__(NT)
 k_pass_x(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
@@ -149,8 +150,11 @@ k_check_velocity(const chd::BoxDesc* __restrict__ boxes, int nbox, const T* __re
     }
 }
 
-// Coarse -> fine velocity transfer: each fine face takes 4 x 4 x 4 coarse
-// values with separable weights from precomputed 1-D stencils.
+// Coarse-to-fine velocity transfer, one target x-row per work-group and
+// iteration: the 4 x 4 source rows of the row's z and y stencils are first
+// combined into one coarse row in LDS (16 taps per coarse x point, coalesced
+// reads), then every target point takes its 4-point x stencil from LDS.
+// Exactly the separable tensor-product interpolation, summed z-y first.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_interp(const T* __restrict__ src, int64_t sx, int64_t sy, int64_t tnx, int64_t tny,
@@ -158,27 +162,30 @@ k_interp(const T* __restrict__ src, int64_t sx, int64_t sy, int64_t tnx, int64_t
          const int* __restrict__ iy, const double* __restrict__ wy,
          const int* __restrict__ iz, const double* __restrict__ wz, T* __restrict__ dst)
 {
-    const int64_t total = tnx * tny * tnz;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e % tnx;
-        const int64_t j = (e / tnx) % tny;
-        const int64_t k = e / (tnx * tny);
-        T acc = T(0);
-        for (int c = 0; c < 4; ++c) {
-            const T wzc = T(wz[4 * k + c]);
-            const int64_t zo = (int64_t)iz[4 * k + c] * sy;
-            T accy = T(0);
-            for (int b = 0; b < 4; ++b) {
-                const T wyb = T(wy[4 * j + b]);
-                const int64_t yo = (zo + iy[4 * j + b]) * sx;
-                T accx = T(0);
-                for (int a = 0; a < 4; ++a) accx += T(wx[4 * i + a]) * src[yo + ix[4 * i + a]];
-                accy += wyb * accx;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* row = reinterpret_cast<T*>(smem);
+    const int64_t nrows = tny * tnz;
+    for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+        const int64_t j = r % tny, k = r / tny;
+        __syncthreads();   // the previous row's readers are done with `row`
+        for (int64_t cx = threadIdx.x; cx < sx; cx += blockDim.x) {
+            T acc = T(0);
+            for (int c = 0; c < 4; ++c) {
+                const T* plane = src + (int64_t)iz[4 * k + c] * sy * sx + cx;
+                T accy = T(0);
+                for (int b = 0; b < 4; ++b)
+                    accy += T(wy[4 * j + b]) * plane[(int64_t)iy[4 * j + b] * sx];
+                acc += T(wz[4 * k + c]) * accy;
             }
-            acc += wzc * accy;
+            row[cx] = acc;
         }
-        dst[e] = acc;
+        __syncthreads();
+        T* out = dst + r * tnx;
+        for (int64_t i = threadIdx.x; i < tnx; i += blockDim.x) {
+            T acc = T(0);
+            for (int a = 0; a < 4; ++a) acc += T(wx[4 * i + a]) * row[ix[4 * i + a]];
+            out[i] = acc;
+        }
     }
 }
 
@@ -209,6 +216,8 @@ hipError_t launch_pass_x(int mi, int nwg, int nth, size_t lds, hipStream_t st,
     if (mi == 1 && nth <= 512)
         return launch_x<T, A, 1, 512>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
     if (mi == 1) return launch_x<T, A, 1, 1024>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    if (nth <= 768)
+        return launch_x<T, A, 2, 768>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
     return launch_x<T, A, 2, 1024>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
 }
 
@@ -261,11 +270,10 @@ hipError_t launch_interp(hipStream_t st, const void* src, int64_t sx, int64_t sy
                          const int* iy, const double* wy, const int* iz, const double* wz,
                          void* dst)
 {
-    const int64_t total = tnx * tny * tnz;
-    int64_t nwg = (total + 255) / 256;
-    if (nwg > 65536 * 4) nwg = 65536 * 4;
-    hipLaunchKernelGGL((k_interp<T>), dim3((unsigned)nwg), dim3(256), 0, st, (const T*)src, sx,
-                       sy, tnx, tny, tnz, ix, wx, iy, wy, iz, wz, (T*)dst);
+    const int64_t rows = tny * tnz;
+    const int64_t nwg = rows < 262144 ? rows : 262144;
+    hipLaunchKernelGGL((k_interp<T>), dim3((unsigned)nwg), dim3(256), (size_t)sx * sizeof(T), st,
+                       (const T*)src, sx, sy, tnx, tny, tnz, ix, wx, iy, wy, iz, wz, (T*)dst);
     return hipGetLastError();
 }
 

@@ -695,6 +695,7 @@ ch_status ch_interp_create(const ch_grid* fine, int64_t ncx, int64_t ncy, int64_
         return fail(CH_EINVAL, "meshes too small");
     if ((double)ncx * ncy * (ncz + 1) >= 2147483647.0)
         return fail(CH_EINVAL, "coarse mesh too large");
+    if (ncx > 8192) return fail(CH_EUNSUPPORTED, "coarse x extent above 8192 (one row in LDS)");
     if (zf[0] != 0.0 || zf[ncz] != 1.0) return fail(CH_EINVAL, "zf must run from 0 to 1");
     for (int64_t k = 0; k < ncz; ++k)
         if (!(zf[k + 1] > zf[k])) return fail(CH_EINVAL, "zf must increase");

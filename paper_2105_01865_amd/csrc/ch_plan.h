@@ -24,11 +24,12 @@ constexpr double RK_R[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 
 constexpr size_t LDS_BUDGET = 64 * 1024;   // default per work-group
 constexpr size_t LDS_HARD = 160 * 1024;    // gfx950 LDS per CU
-// x-pass tile budget: the share of a CU's LDS that lets as many 256-thread
-// work-groups run as the x kernel's registers allow (4 in single precision,
-// 3 in double)
-constexpr size_t X_LDS_BUDGET_F32 = 40 * 1024;
-constexpr size_t X_LDS_BUDGET_F64 = 53 * 1024;
+// Waves per SIMD that the x kernel's registers allow (512 VGPRs per lane
+// over 118 in single precision, 157 in double, for one cell per thread).
+// The x tile's LDS budget is the CU's LDS shared by the work-groups that
+// many waves make room for.
+constexpr int X_WAVES_F32 = 4;
+constexpr int X_WAVES_F64 = 3;
 constexpr int X_MAX_THREADS = 1024;        // largest x-pass work-group
 
 // cells of an x-pass plane tile per thread: one, two for very long x lines
@@ -260,13 +261,19 @@ inline ch_status plan_dt(Plan& P, double dt)
     auto xlds = [&](int R, int zc) {
         return chd::x_layout(nxm, R, zc, P.tw_max, (int)sT, (int)sA).total;
     };
-    const size_t xbudget = sT == 4 ? X_LDS_BUDGET_F32 : X_LDS_BUDGET_F64;
+    const int xwaves = sT == 4 ? X_WAVES_F32 : X_WAVES_F64;
+    auto xbudget_for = [&](int R) {
+        const int threads = ((R * nxm + P.mi - 1) / P.mi + 63) / 64 * 64;
+        const int per_simd = (threads / 64 + 3) / 4;   // waves of one group per SIMD
+        const int groups = std::max(1, xwaves / std::max(1, per_simd));
+        return LDS_HARD / (size_t)groups;
+    };
     int R = P.opt.x_rows;
     if (R == 0) {
         // about 256 threads per work-group: one row of a long line, several
         // of short ones (each extra row also shares its y faces)
         R = std::max(1, std::min({256 / std::max(1, nxm), std::max(1, nym), 16}));
-        while (R > 1 && (R * nxm > xcap || xlds(R, 1) > xbudget)) --R;
+        while (R > 1 && (R * nxm > xcap || xlds(R, 1) > xbudget_for(R))) --R;
     }
     if (R * nxm > xcap) return P.fail(CH_EINVAL, "x_rows too large for the x extent");
     P.x_rows = R;
@@ -285,6 +292,7 @@ inline ch_status plan_dt(Plan& P, double dt)
         const int64_t rows_total = cells / std::max(1, nxm);
         zc = (int)std::max<int64_t>(1, std::min<int64_t>(16, rows_total / R / 2048));
         zc = std::min(zc, zlim);
+        const size_t xbudget = xbudget_for(R);
         while (zc > 1 && xlds(R, zc) > xbudget) --zc;
     }
     if (zc > zlim) return P.fail(CH_EINVAL, "z_chunk too large for this x extent");

@@ -232,3 +232,36 @@ def test_config2_full_size_fp64_one_step_against_oracle():
     got32, _ = run_gpu(wl.C, wl.u, wl.v, wl.w, wl.h, wl.Cn, wl.Pe, wl.dt, 1, precision="fp32")
     print(f"  256^3 fp32 rel={rel(got32, ref):.3e}")
     assert rel(got32, ref) <= 5e-6
+
+
+def test_config5_full_ensemble_sampled_boxes_against_oracle():
+    """The whole 48-box ensemble (about 1.2e8 points) in one batch, in the
+    launch configuration the benchmark times: every box conserves its mass,
+    and the smallest boxes of each edge up to 96 match the oracle."""
+    E = inputs.ensemble(48)
+    shapes = [w.shape for w in E]
+    hs = [w.h for w in E]
+    pick = []
+    for edge in (48, 64, 96):
+        pick.append(next(i for i, w in enumerate(E) if w.shape[0] == edge))
+    refs = {i: oracle.step(E[i].C, E[i].u, E[i].v, E[i].w, E[i].h, E[i].Cn, E[i].Pe, 1e-4, 1)
+            for i in pick}
+    for prec, tol in (("fp64", TOL64), ("fp32", 5e-6)):
+        print(f"[gpu] ensemble of {len(E)} boxes, {prec}", flush=True)
+        st = torch.cuda.Stream()
+        b = ch.Batch(shapes, hs, [w.Cn for w in E], [w.Pe for w in E], stream=st,
+                     precision=prec)
+        b.set_field(b.pack([w.C for w in E], "c"))
+        m0 = b.mass()
+        b.step(b.pack([w.u for w in E], "u"), b.pack([w.v for w in E], "v"),
+               b.pack([w.w for w in E], "w"), 1e-4, 1)
+        m1 = b.mass()
+        outs = b.unpack(b.get_field())
+        b.close()
+        drift = max(abs(a - c) / abs(a) for a, c in zip(m0, m1))
+        print(f"  max mass drift {drift:.2e}")
+        assert drift <= (1e-13 if prec == "fp64" else 1e-6)
+        for i in pick:
+            e = rel(outs[i].double().cpu().numpy(), refs[i])
+            print(f"  box {i} edge {shapes[i][0]}: rel {e:.2e}")
+            assert e <= tol
