@@ -197,6 +197,41 @@ def bench_multires(args, stream):
             "l2_rel_fp32_vs_fp64": float(np.linalg.norm(d) / np.linalg.norm(fields["fp64"]))}
 
 
+def bench_large(args, stream):
+    """The 1536^3 periodic box in single precision (inputs built on the GPU):
+    FP32 throughput over a few steps, and the whole box's mass drift."""
+    import torch
+    from paper_2105_01865_amd import ch, inputs_gpu
+    torch.cuda.empty_cache()
+    wl = inputs_gpu.large_workload()
+    s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, precision="fp32", stream=stream)
+    s.set_field(wl.C)
+    del wl.C
+    m0 = s.mass()
+    s.step(wl.u, wl.v, wl.w, wl.dt, 1)
+    ms = _timed_events(stream, lambda: s.step(wl.u, wl.v, wl.w, wl.dt, args.large_steps))
+    m1 = s.mass()
+    s.profile(True)
+    s.step(wl.u, wl.v, wl.w, wl.dt, 2)
+    kern = {k: s.profile_read(k) for k in ("x", "y", "z")}
+    s.profile(False)
+    cfg = s.config()
+    s.close()
+    del wl
+    torch.cuda.empty_cache()
+    pts = 1536 ** 3
+    return {"workload": "1536^3 periodic box, FP32 storage, 4000 tanh drops R~U[4,20]h, "
+                        "k^-5/3 field 1<=k<=48 rms 1 (inputs generated on the GPU), "
+                        "dt from the advective bound",
+            "points": pts, "steps": args.large_steps,
+            "fp32": {"value": round(pts * args.large_steps / (ms * 1e-3) / 1e9, 4),
+                     "unit": "Gpts/s", "ms_per_step": round(ms / args.large_steps, 3),
+                     "mass_drift": abs(m1 - m0) / abs(m0),
+                     "kernels_avg_us": {k: round(1e3 * v[0] / max(1, v[1]), 1)
+                                        for k, v in kern.items()}},
+            "plan": cfg}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +241,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--multires-steps", type=int, default=100)
+    ap.add_argument("--large-steps", type=int, default=10)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-ensemble and multiple-resolution lines")
     ap.add_argument("--counter-probe", action="store_true")
@@ -332,6 +368,7 @@ def main():
     if not args.no_extra:
         line["batched"] = bench_ensemble(args, stream)
         line["multires"] = bench_multires(args, stream)
+        line["large"] = bench_large(args, stream)
 
     if not args.no_cpu_baseline:
         # the FP64 oracle on the same workload, whole RK3 steps until about

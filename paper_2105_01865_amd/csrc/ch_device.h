@@ -27,6 +27,8 @@
 #pragma once
 
 #include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
 
 #if defined(__HIPCC__)
 #include <hip/hip_runtime.h>
@@ -115,6 +117,88 @@ CH_HD float fast_rcp(float x)
     return __builtin_amdgcn_rcpf(x);
 #else
     return 1.0f / x;
+#endif
+}
+
+// One plane of a field seen from a wave-uniform base: elements are read and
+// written at 32-bit byte offsets.  On the GPU it is a raw buffer resource
+// (base, size in bytes; dword 3 = 32-bit data format), so the load unit
+// forms the address from the scalar base and the lane offset with no
+// per-lane 64-bit arithmetic, and an offset at or past `bytes` reads zero
+// and drops a store.
+#if !defined(__HIP_DEVICE_COMPILE__)
+// host execution of the kernel code (tests): an access past a plane is a bug
+inline void plane_overrun(uint32_t boff, uint32_t n)
+{
+    fprintf(stderr, "plane access at byte %u of a %u-byte plane\n", boff, n);
+    abort();
+}
+#endif
+
+#ifndef CH_BUFFER_LOADS
+#define CH_BUFFER_LOADS 1
+#endif
+
+template <typename T>
+struct PlaneRef {
+#if defined(__HIP_DEVICE_COMPILE__) && CH_BUFFER_LOADS
+    __amdgpu_buffer_rsrc_t rs;
+    __device__ PlaneRef(const T* base, uint32_t bytes)
+        : rs(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)bytes,
+                                               0x00020000))
+    {
+    }
+    __device__ T operator()(uint32_t boff) const
+    {
+        if constexpr (sizeof(T) == 4) {
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, boff, 0, 0));
+        } else {
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, boff, 0, 0));
+        }
+    }
+    __device__ void store(uint32_t boff, T v) const
+    {
+        if constexpr (sizeof(T) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, boff, 0, 0);
+        } else {
+            typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, boff, 0, 0);
+        }
+    }
+#else
+    const char* p;
+    uint32_t n;
+    CH_HD PlaneRef(const T* base, uint32_t bytes) : p(reinterpret_cast<const char*>(base)), n(bytes)
+    {
+    }
+    CH_HD T operator()(uint32_t boff) const
+    {
+#if defined(__HIP_DEVICE_COMPILE__)
+        return *reinterpret_cast<const T*>(p + boff);
+#else
+        if (boff + sizeof(T) > n) plane_overrun(boff, n);
+        return *reinterpret_cast<const T*>(p + boff);
+#endif
+    }
+    CH_HD void store(uint32_t boff, T v) const
+    {
+#if defined(__HIP_DEVICE_COMPILE__)
+        *reinterpret_cast<T*>(const_cast<char*>(p) + boff) = v;
+#else
+        if (boff + sizeof(T) > n) plane_overrun(boff, n);
+        *reinterpret_cast<T*>(const_cast<char*>(p) + boff) = v;
+#endif
+    }
+#endif
+};
+
+// Keep the instruction scheduler from moving code across this point, so
+// that the work of two cells of one thread runs one after the other and
+// shares its temporary registers.
+CH_HD void sched_fence()
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_sched_barrier(0);
 #endif
 }
 
@@ -511,9 +595,9 @@ struct XState {
     T nhalo[X_PREFETCH][MI][6];  // C of the halo rows hr with hr mod rows equal to
                                  // the owned row, at the owned column
     int rx[MI];      // (row << 16) | x of each owned cell, -1 if none
-    unsigned col[MI];   // y nx + x: offset of the cell in a plane of C, E, v, w
-    unsigned colu[MI];  // y fx + x: offset of its low x face in a plane of u
-    unsigned colvh[MI]; // offset of its high y face in a plane of v
+    uint32_t col[MI];   // byte offset of the cell in a plane of C, E, v, w
+    uint32_t colu[MI];  // byte offset of its low x face in a plane of u
+    uint32_t colvh[MI]; // byte offset of its high y face in a plane of v
     int cxp[MI];     // halo column (-3 .. nx+2) that copies the owned column in
                      // the C tile, or the column itself if none (nx >= 6)
     int cxm[MI];     // the same for the psi'(C) tile (-1 .. nx)
@@ -535,12 +619,17 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
     const int nth = ex.nth;
     const XLayout L = x_layout(pa.nx_max, pa.rmax, pa.zcmax, pa.tw_max, (int)sizeof(T),
                                (int)sizeof(A));
+    constexpr uint32_t sT = sizeof(T);
     T* pb = reinterpret_cast<T*>(smem + L.pb);
     T* mb = reinterpret_cast<T*>(smem + L.mb);
     T* fxb = reinterpret_cast<T*>(smem + L.fx);
     T* fyb = reinterpret_cast<T*>(smem + L.fy);
     A* tb = reinterpret_cast<A*>(smem + L.tb);
     const int64_t plane = (int64_t)nx * ny;
+    // bytes of one plane of C, E, q and w, of u, and of v
+    const uint32_t pbytes = (uint32_t)(plane * sT);
+    const uint32_t ubytes = (uint32_t)((int64_t)ny * fx * sT);
+    const uint32_t vbytes = (uint32_t)((int64_t)fy * nx * sT);
     const T* Cb = C + bd.c_off;
     const T* Ub = U + bd.u_off;
     const T* Vb = V + bd.v_off;
@@ -558,13 +647,13 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
     // the six halo rows (y0-3 .. y0-1, y0+rows .. y0+rows+2), their tile rows,
     // and the owned row whose threads load them (hr mod rows)
     int hrow[6], hown[6];
-    unsigned hoff[6];
+    uint32_t hoffb[6];   // byte offsets of the halo rows in a plane
 #pragma unroll
     for (int hr = 0; hr < 6; ++hr) {
         const int prow = hr < 3 ? hr : rows + hr;
         hrow[hr] = prow;
         hown[hr] = hr % rows;
-        hoff[hr] = (unsigned)(map_idx(t.y0 - 3 + prow, ny, bd.bc[1]) * nx);
+        hoffb[hr] = (uint32_t)(map_idx(t.y0 - 3 + prow, ny, bd.bc[1]) * nx) * sT;
     }
     const bool one_copy = nx >= 6;   // every column feeds at most one halo column
 
@@ -572,26 +661,28 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
     // (uniform plane bases, 32-bit offsets within a plane)
     auto fetch = [&](XState<T, A, MI>& s, auto bset, int z) {
         constexpr int b = decltype(bset)::value;
-        const T* Cq = Cb + (int64_t)map_idx(z + 3, nz, bd.bc[2]) * plane;
-        const T* Uz = Ub + (int64_t)z * ny * fx;
-        const T* Vz = Vb + (int64_t)z * fy * nx;
-        const T* Wh = Wb + (int64_t)((z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1) * plane;
-        const T* Ez = Eb + (int64_t)z * plane;
-        const T* Cz = Cb + (int64_t)z * plane;
+        const PlaneRef<T> Cq(Cb + (int64_t)map_idx(z + 3, nz, bd.bc[2]) * plane, pbytes);
+        const PlaneRef<T> Uz(Ub + (int64_t)z * ny * fx, ubytes);
+        const PlaneRef<T> Vz(Vb + (int64_t)z * fy * nx, vbytes);
+        const PlaneRef<T> Wh(Wb + (int64_t)((z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1) * plane,
+                             pbytes);
+        const PlaneRef<T> Ez(Eb + (int64_t)z * plane, pbytes);
+        const PlaneRef<T> Cz(Cb + (int64_t)z * plane, pbytes);
 #pragma unroll
         for (int m = 0; m < MI; ++m) {
             if (s.rx[m] >= 0) {
                 const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
-                s.ncz[b][m] = Cq[s.col[m]];
-                s.nvel[b][m][0] = Uz[s.colu[m]];
-                s.nvel[b][m][1] = (x == nx - 1 && bcx != 0) ? Uz[s.colu[m] + 1] : T(0);
-                s.nvel[b][m][2] = Vz[s.col[m]];
-                s.nvel[b][m][3] = r == rows - 1 ? Vz[s.colvh[m]] : T(0);
-                s.nwh[b][m] = Wh[s.col[m]];
-                s.neold[b][m] = pa.e_mode != 0 ? Ez[s.col[m]] : T(0);
+                s.ncz[b][m] = Cq(s.col[m]);
+                s.nvel[b][m][0] = Uz(s.colu[m]);
+                s.nvel[b][m][1] = (x == nx - 1 && bcx != 0) ? Uz(s.colu[m] + sT) : T(0);
+                s.nvel[b][m][2] = Vz(s.col[m]);
+                s.nvel[b][m][3] = r == rows - 1 ? Vz(s.colvh[m]) : T(0);
+                s.nwh[b][m] = Wh(s.col[m]);
+                s.neold[b][m] = pa.e_mode != 0 ? Ez(s.col[m]) : T(0);
+                const uint32_t xb = (uint32_t)x * sT;
 #pragma unroll
                 for (int hr = 0; hr < 6; ++hr)
-                    if (hown[hr] == r) s.nhalo[b][m][hr] = Cz[hoff[hr] + x];
+                    if (hown[hr] == r) s.nhalo[b][m][hr] = Cz(hoffb[hr] + xb);
             }
         }
     };
@@ -611,7 +702,7 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
     };
     // RHS of plane zs of the owned cells into the solve tile
     auto rhs_plane = [&](XState<T, A, MI>& s, int zs) {
-        T* Ez = Eb + (int64_t)(t.z0 + zs) * plane;
+        const PlaneRef<T> Ez(Eb + (int64_t)(t.z0 + zs) * plane, pbytes);
 #pragma unroll
         for (int m = 0; m < MI; ++m) {
             if (s.rx[m] < 0) continue;
@@ -623,7 +714,7 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
             const T e = -adv * inv_h + s.plap[m] * lap_s;
             T rhs = gdt * e - bdt * s.pb4[m];
             if (pa.e_mode != 0) rhs += rdt * s.eold[m];
-            if (pa.e_mode != 2) Ez[s.col[m]] = e;
+            if (pa.e_mode != 2) Ez.store(s.col[m], e);
             tb[(x + tw) * L.tbp + zs * rows + r] = A(rhs);
         }
     };
@@ -643,9 +734,9 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
                 const int y = t.y0 + r;
                 const int yh = (y + 1 == ny && bd.bc[1] == 0) ? 0 : y + 1;
-                s.col[m] = (unsigned)(y * nx + x);
-                s.colu[m] = (unsigned)(y * fx + x);
-                s.colvh[m] = (unsigned)(yh * nx + x);
+                s.col[m] = (uint32_t)(y * nx + x) * sT;
+                s.colu[m] = (uint32_t)(y * fx + x) * sT;
+                s.colvh[m] = (uint32_t)(yh * nx + x) * sT;
                 s.cxp[m] = x;
                 s.cxm[m] = x;
                 for (int q = 0; q < 6; ++q)
@@ -656,10 +747,11 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                     }
 #pragma unroll
                 for (int q = 1; q < 7; ++q)
-                    s.cz[m][q] = Cb[(int64_t)map_idx(t.z0 - 4 + q, nz, bd.bc[2]) * plane + s.col[m]];
+                    s.cz[m][q] = PlaneRef<T>(Cb + (int64_t)map_idx(t.z0 - 4 + q, nz, bd.bc[2]) * plane,
+                                             pbytes)(s.col[m]);
                 s.mq[m][1] = mu(s.cz[m][3]);   // psi'(C) at z0-2 .. z0 after the first shift
                 s.mq[m][2] = mu(s.cz[m][4]);
-                s.vel[m][4] = Wz[s.col[m]];
+                s.vel[m][4] = PlaneRef<T>(Wz, pbytes)(s.col[m]);
             }
             s.xmask[m] = mask;
         }
@@ -761,6 +853,7 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 s.pb4[m] = d4<T>(row[-2], row[-1], row[0], row[1], row[2])
                          + d4<T>(colm[p], colm[2 * p], colm[3 * p], colm[4 * p], colm[5 * p])
                          + d4<T>(c[1], c[2], c[3], c[4], c[5]);
+                if (m + 1 < MI) sched_fence();
             }
         });
     };
@@ -800,12 +893,12 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
     ex.phase([&](int tid) {
         XState<T, A, MI>& s = st[ex.slot(tid)];
         for (int zs = 0; zs < t.nzc; ++zs) {
-            T* Qz = Qb + (int64_t)(t.z0 + zs) * plane;
+            const PlaneRef<T> Qz(Qb + (int64_t)(t.z0 + zs) * plane, pbytes);
 #pragma unroll
             for (int m = 0; m < MI; ++m) {
                 if (s.rx[m] < 0) continue;
                 const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
-                Qz[s.col[m]] = T(tb[(x + tw) * L.tbp + zs * rows + r]);
+                Qz.store(s.col[m], T(tb[(x + tw) * L.tbp + zs * rows + r]));
             }
         }
     });

@@ -167,7 +167,9 @@ inline ch_status plan_init(Plan& P, int nbox, const ch_grid* g, const double* Cn
             if (bb[d] != CH_PERIODIC && bb[d] != CH_NOFLUX)
                 return P.fail(CH_EINVAL, "unknown boundary condition");
         }
-        if ((double)n[0] * (double)n[1] >= 2147483647.0)
+        // byte offsets within one plane of a field (faces included) are
+        // 32-bit in the kernels
+        if ((double)(n[0] + 1) * (double)(n[1] + 1) * 8.0 >= 4294967296.0)
             return P.fail(CH_EINVAL, "a plane of the mesh is too large");
         if (!(P.g[b].h > 0.0) || !std::isfinite(P.g[b].h))
             return P.fail(CH_EINVAL, "h must be > 0 and finite");
