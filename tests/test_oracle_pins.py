@@ -374,12 +374,9 @@ def test_uniform_field_stays_uniform():
     assert np.abs(C1 - 0.37).max() < 1e-15
 
 
-def _fourier_amplification(th, U, h, Cn, Pe, dt, kappa, C0):
-    """Closed-form per-step amplification of a small mode exp(i theta . j)
-    about a uniform state C0 (linearised CH, new scheme, RK3 + CN + AF)."""
+def _adv_symbol(th, U, h):
+    """Symbol of div(u C) for uniform u with the linear (UW5) face values."""
     w5 = _uw5_weights_from_polynomials()
-    lamL = sum(4 / h ** 2 * math.sin(t / 2) ** 2 for t in th)
-    lamB = kappa * Cn ** 2 * sum(16 / h ** 4 * math.sin(t / 2) ** 4 for t in th)
     a = 0.0
     for t, Ud in zip(th, U):
         # face value at i-1/2 as a function of the mode: upwind from the left
@@ -387,6 +384,15 @@ def _fourier_amplification(th, U, h, Cn, Pe, dt, kappa, C0):
         offs = range(-3, 2) if Ud >= 0 else range(2, -3, -1)
         face = sum(wm * np.exp(1j * t * o) for wm, o in zip(w5, offs))
         a += Ud * (np.exp(1j * t) - 1.0) * face / h
+    return a
+
+
+def _fourier_amplification(th, U, h, Cn, Pe, dt, kappa, C0):
+    """Closed-form per-step amplification of a small mode exp(i theta . j)
+    about a uniform state C0 (linearised CH, new scheme, RK3 + CN + AF)."""
+    lamL = sum(4 / h ** 2 * math.sin(t / 2) ** 2 for t in th)
+    lamB = kappa * Cn ** 2 * sum(16 / h ** 4 * math.sin(t / 2) ** 4 for t in th)
+    a = _adv_symbol(th, U, h)
     psi2 = 3 * C0 ** 2 - 3 * C0 + 0.5
     e = -a - psi2 * lamL / Pe
     gam, rho = (8 / 15, 5 / 12, 3 / 4), (0.0, -17 / 60, -5 / 12)
@@ -555,9 +561,63 @@ def test_explicit25_step_conserves_and_reduces_in_one_dimension():
     F = np.broadcast_to(prof[:, None, None], (nz, 8, 8)).copy()
     z0 = np.zeros_like(F)
     diffs = []
-    for dt in (4e-6, 2e-6):
+    for dt in (2e-3, 1e-3):          # well inside the explicit limit (4.4e-3)
         a = oracle.step_explicit25(F, z0, z0, z0, h, h, 0.9 / h, dt, 1)
         b = oracle.step(F, z0, z0, z0, h, h, 0.9 / h, dt, 1, kappa=1.0)
         diffs.append(np.abs(a - b).max())
     assert diffs[1] < diffs[0] / 3.0      # second order in dt
     assert diffs[0] < 1e-3 * np.abs(a - F).max()
+
+
+def _mode(n, m, C0, eps):
+    i = [np.arange(k) for k in n]
+    th = [2 * math.pi * m[d] / n[d] for d in range(3)]
+    phase = (th[2] * i[2][:, None, None] + th[1] * i[1][None, :, None]
+             + th[0] * i[0][None, None, :])
+    return th, phase, C0 + eps * np.cos(phase)
+
+
+@pytest.mark.parametrize("C0", [0.0, 0.5])
+@pytest.mark.parametrize("U", [(0.0, 0.0, 0.0), (0.7, -0.4, 0.25)])
+def test_explicit25_fourier_mode_grows_by_the_rk3_polynomial(C0, U):
+    """With every term explicit, one step of a linear constant-coefficient
+    problem multiplies a mode by the Taylor polynomial 1 + z + z^2/2 + z^3/6
+    of z = dt e (three-stage third-order RK), where e is the linearised
+    operator's symbol; the 25-point biharmonic's symbol is the square of the
+    7-point Laplacian's, Cn^2 (sum_d 4 sin^2(theta_d/2) / h^2)^2."""
+    n, m = (16, 12, 10), (1, 2, 3)
+    h = 1.0 / 16
+    Cn, Pe, eps, dt = h, 0.9 / h, 1e-7, 4e-5
+    th, phase, C = _mode(n, m, C0, eps)
+    u, v, w = (np.full(C.shape, Ud) for Ud in U)
+    C1 = oracle.step_explicit25(C, u, v, w, h, Cn, Pe, dt, 1)
+    lamL = sum(4 / h ** 2 * math.sin(t / 2) ** 2 for t in th)
+    psi2 = 3 * C0 ** 2 - 3 * C0 + 0.5
+    e = -_adv_symbol(th, U, h) - psi2 * lamL / Pe - Cn ** 2 * lamL ** 2 / Pe
+    z = dt * e
+    G = 1 + z + z ** 2 / 2 + z ** 3 / 6
+    got = (C1 - C0) / eps
+    assert np.abs(got - np.real(G * np.exp(1j * phase))).max() < 2e-6 * max(1.0, abs(G))
+
+
+def test_explicit25_stability_limit():
+    """The highest mode (theta = pi on every axis, symbol 144 Cn^2/h^4 for
+    the biharmonic) decays just below the explicit limit dt = 2.5127 Pe /
+    lambda (the RK3 polynomial's real-axis bound) and grows just above it;
+    the implicit scheme takes 40 times that step and still damps it."""
+    n = (8, 8, 8)
+    h = 1.0 / 8
+    Cn, Pe, eps = h, 0.9 / h, 1e-9
+    i = np.arange(8)
+    chk = (-1.0) ** (i[:, None, None] + i[None, :, None] + i[None, None, :])
+    C = 1.0 + eps * chk                    # about a well: psi'' = 1/2 > 0
+    z0 = np.zeros(C.shape)
+    lam = (144 * Cn ** 2 / h ** 4 + 0.5 * 12 / h ** 2) / Pe
+    zmax = 2.5127453266183286              # 1 + z + z^2/2 + z^3/6 = -1 at -zmax
+    for f, grows in ((0.99, False), (1.01, True)):
+        dt = f * zmax / lam
+        C1 = oracle.step_explicit25(C, z0, z0, z0, h, Cn, Pe, dt, 50)
+        amp = np.abs(C1 - 1.0).max() / eps
+        assert (amp > 1.0) == grows
+    C1 = oracle.step(C, z0, z0, z0, h, Cn, Pe, 40 * zmax / lam, 5)
+    assert np.abs(C1 - 1.0).max() / eps < 1.0
