@@ -232,6 +232,53 @@ def bench_large(args, stream):
             "plan": cfg}
 
 
+def bench_explicit25(args, stream, line):
+    """The paper's starting point, the explicit 25-point biharmonic (no line
+    solves), on the same 256^3 workload: its throughput at 0.85 of the
+    biharmonic's RK3 stability bound (advection and the psi'' term move the
+    practical limit to 0.90-0.95 of it at 256^3), stability checked at 0.85
+    and 1.05 of the bound, and the time to reach a given simulated time
+    against the implicit scheme at the workload's dt."""
+    import numpy as np
+    import torch
+    from paper_2105_01865_amd import ch, inputs
+    wl = inputs.make_workload(2)
+    # highest mode of the 25-point operator: 144 Cn^2/h^4; RK3 real-axis bound
+    zmax = 2.5127453266183286
+    dt_lim = zmax * wl.Pe / (144.0 * wl.Cn ** 2 / wl.h ** 4)
+    res = {}
+    for prec in ("fp32", "fp64"):
+        dt_ = torch.float32 if prec == "fp32" else torch.float64
+        U, V, W = (torch.from_numpy(a).to("cuda", dt_) for a in (wl.u, wl.v, wl.w))
+        C0 = torch.from_numpy(wl.C).to("cuda", dt_)
+        s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, precision=prec, stream=stream)
+        s.set_field(C0)
+        s.step_explicit25(U, V, W, 0.85 * dt_lim, args.warmup)
+        ms = _timed_events(stream, lambda: s.step_explicit25(U, V, W, 0.85 * dt_lim,
+                                                             args.explicit_steps))
+        res[prec] = {"value": round(wl.points * args.explicit_steps / (ms * 1e-3) / 1e9, 4),
+                     "unit": "Gpts/s", "ms_per_step": round(ms / args.explicit_steps, 4)}
+        if prec == "fp32":
+            growth = {}
+            for f in (0.85, 1.05):
+                s.set_field(C0)
+                s.step_explicit25(U, V, W, f * dt_lim, args.explicit_steps)
+                C = s.get_field().double().cpu().numpy()
+                growth[str(f)] = float(np.abs(C - 0.5).max()) if np.all(np.isfinite(C)) else None
+            res["max_abs_C_minus_half_after_steps"] = growth
+        s.close()
+    impl32 = line["ms_per_step"]
+    impl_dt = wl.dt
+    tts = (res["fp32"]["ms_per_step"] / (0.85 * dt_lim)) / (impl32 / impl_dt)
+    return {"workload": line["config"]["workload"] + "; explicit 25-point biharmonic",
+            "dt_bound_biharmonic": dt_lim, "dt_used": 0.85 * dt_lim,
+            "steps": args.explicit_steps,
+            "fp32": res["fp32"], "fp64": res["fp64"],
+            "stability_check_fp32": res["max_abs_C_minus_half_after_steps"],
+            "implicit_dt": impl_dt,
+            "time_to_solution_explicit_over_implicit_fp32": round(tts, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +289,7 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--multires-steps", type=int, default=100)
     ap.add_argument("--large-steps", type=int, default=10)
+    ap.add_argument("--explicit-steps", type=int, default=200)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-ensemble and multiple-resolution lines")
     ap.add_argument("--counter-probe", action="store_true")
@@ -369,6 +417,7 @@ def main():
         line["batched"] = bench_ensemble(args, stream)
         line["multires"] = bench_multires(args, stream)
         line["large"] = bench_large(args, stream)
+        line["explicit25"] = bench_explicit25(args, stream, line)
 
     if not args.no_cpu_baseline:
         # the FP64 oracle on the same workload, whole RK3 steps until about

@@ -134,6 +134,21 @@ ch_status ch_get_field(ch_state* s, void* C, int on_device);
 ch_status ch_step(ch_state* s, const void* u, const void* v, const void* w,
                   double dt, int nsteps);
 
+/* Enqueue nsteps RK3 steps of the explicit 25-point scheme the paper starts
+ * from (sec. 3.1, eq-disbi in three dimensions): no Crank-Nicolson and no
+ * line solves, every term advanced by the low-storage RK3 (sec. 2):
+ *   N_k = -div(u C) + lap psi'(C)/Pe - B(C)/Pe,
+ *   B   = Cn^2/h^4 [ sum_d (1,-4,6,-4,1)_d + 2 sum_{d<e} (1,-2,1)_d (1,-2,1)_e ] C,
+ *   C  += dt (gamma_k N_k + rho_k N_{k-1}),
+ * the full 25-point discrete biharmonic with its mixed terms (kappa is not
+ * used).  Stable only below the explicit limit, about
+ * dt < 2.51 Pe h^4 / (144 Cn^2) for the biharmonic's highest mode, which is
+ * what the paper's implicit scheme removes.  Same arguments, layout and
+ * errors as ch_step; the state's buffers are reused (C and a solve buffer
+ * trade places each substage), so a later ch_step re-plans. */
+ch_status ch_step_explicit25(ch_state* s, const void* u, const void* v, const void* w,
+                             double dt, int nsteps);
+
 /* Mass h^3 sum C in double, summed in a fixed order (the quantity behind
  * the mass-loss measure of sec. 4.3.1).  Waits for the stream. */
 ch_status ch_mass(ch_state* s, double* out);

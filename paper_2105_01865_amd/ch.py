@@ -68,6 +68,7 @@ SIGNATURES = {
     "ch_set_field": (_I, [_VP, _VP, _I]),
     "ch_get_field": (_I, [_VP, _VP, _I]),
     "ch_step": (_I, [_VP, _VP, _VP, _VP, _D, _I]),
+    "ch_step_explicit25": (_I, [_VP, _VP, _VP, _VP, _D, _I]),
     "ch_mass": (_I, [_VP, _PD]),
     "ch_check_velocity": (_I, [_VP, _VP, _VP, _VP]),
     "ch_destroy": (None, [_VP]),
@@ -220,6 +221,16 @@ class State(_StreamMixin):
         pw = _dev_tensor(w, self.dtype, sw, "w")
         self._enter()
         _check(lib().ch_step(self._h, pu, pv, pw, float(dt), int(nsteps)))
+        self._leave()
+
+    def step_explicit25(self, u, v, w, dt, nsteps=1):
+        """Steps of the explicit 25-point scheme (no line solves)."""
+        su, sv, sw = self.vel_shapes()
+        pu = _dev_tensor(u, self.dtype, su, "u")
+        pv = _dev_tensor(v, self.dtype, sv, "v")
+        pw = _dev_tensor(w, self.dtype, sw, "w")
+        self._enter()
+        _check(lib().ch_step_explicit25(self._h, pu, pv, pw, float(dt), int(nsteps)))
         self._leave()
 
     def step_multires(self, interp, uc, vc, wc, dt, nsteps=1):

@@ -526,13 +526,16 @@ CH_HD void line_b2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2,
 //                                    zs * rows + r at column zs * rows + r
 // ---------------------------------------------------------------------------
 struct XLayout {
-    size_t pb, mb, fx, fy, tb, total;  // byte offsets and total size
-    int pbp, mbp, fxp, fyp, tbp;       // pitches (elements)
+    size_t pb, mb, fx, fy, tb, zm, zp, total;  // byte offsets and total size
+    int pbp, mbp, fxp, fyp, tbp;               // pitches (elements)
 };
 
 CH_HD size_t al16(size_t b) { return (b + 15) & ~size_t(15); }
 
-CH_HD XLayout x_layout(int nx_max, int rmax, int zcmax, int tw_max, int sT, int sA)
+// e25: the explicit 25-point mode, which has no solve tile and keeps the
+// owned row of the planes z-1 and z+1 (pitch mbp, one halo column a side).
+CH_HD XLayout x_layout(int nx_max, int rmax, int zcmax, int tw_max, int sT, int sA,
+                       bool e25 = false)
 {
     XLayout L;
     L.pbp = nx_max + 6;
@@ -545,7 +548,14 @@ CH_HD XLayout x_layout(int nx_max, int rmax, int zcmax, int tw_max, int sT, int 
     L.fx = al16(L.mb + (size_t)(rmax + 2) * L.mbp * sT);
     L.fy = al16(L.fx + (size_t)rmax * L.fxp * sT);
     L.tb = al16(L.fy + (size_t)(rmax + 1) * L.fyp * sT);
-    L.total = al16(L.tb + (size_t)(nx_max + 2 * tw_max) * L.tbp * sA);
+    if (e25) {
+        L.zm = L.tb;
+        L.zp = al16(L.zm + (size_t)L.mbp * sT);
+        L.total = al16(L.zp + (size_t)L.mbp * sT);
+    } else {
+        L.zm = L.zp = 0;
+        L.total = al16(L.tb + (size_t)(nx_max + 2 * tw_max) * L.tbp * sA);
+    }
     return L;
 }
 
@@ -603,9 +613,13 @@ struct XState {
     int cxm[MI];     // the same for the psi'(C) tile (-1 .. nx)
     int xmask[MI];   // all halo columns fed by the owned column (any nx)
     LineState<A> ls;
+    // explicit 25-point mode: mixed second differences of the plane below
+    // (xy and xz), and C of the rows y-1, y+1 at the planes z-2, z-1
+    T pmix[MI];
+    T hq[MI][2][2];
 };
 
-template <typename T, typename A, int MI, class X>
+template <typename T, typename A, int MI, bool E25, class X>
 CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const PassArgs& pa,
                           int task, const T* __restrict__ C, const T* __restrict__ U,
                           const T* __restrict__ V, const T* __restrict__ W, T* __restrict__ E,
@@ -618,13 +632,15 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
     const int k = pa.k, tw = bd.tw[k];
     const int nth = ex.nth;
     const XLayout L = x_layout(pa.nx_max, pa.rmax, pa.zcmax, pa.tw_max, (int)sizeof(T),
-                               (int)sizeof(A));
+                               (int)sizeof(A), E25);
     constexpr uint32_t sT = sizeof(T);
     T* pb = reinterpret_cast<T*>(smem + L.pb);
     T* mb = reinterpret_cast<T*>(smem + L.mb);
     T* fxb = reinterpret_cast<T*>(smem + L.fx);
     T* fyb = reinterpret_cast<T*>(smem + L.fy);
     A* tb = reinterpret_cast<A*>(smem + L.tb);
+    T* zmb = reinterpret_cast<T*>(smem + L.zm);   // explicit mode: owned row at z-1
+    T* zpb = reinterpret_cast<T*>(smem + L.zp);   // and at z+1
     const int64_t plane = (int64_t)nx * ny;
     // bytes of one plane of C, E, q and w, of u, and of v
     const uint32_t pbytes = (uint32_t)(plane * sT);
@@ -700,9 +716,12 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 if ((mask >> q) & 1) rp[q < 3 ? q - 3 : nx + q - 3] = v;
         }
     };
-    // RHS of plane zs of the owned cells into the solve tile
-    auto rhs_plane = [&](XState<T, A, MI>& s, int zs) {
+    // RHS of plane zs of the owned cells into the solve tile; in the explicit
+    // 25-point mode, C + dt (gamma N + rho N_old) into Q instead, with yz the
+    // mixed yz difference and cc the C of each owned cell at plane zs
+    auto rhs_plane = [&](XState<T, A, MI>& s, int zs, const T* yz, const T* cc) {
         const PlaneRef<T> Ez(Eb + (int64_t)(t.z0 + zs) * plane, pbytes);
+        const PlaneRef<T> Qz(Qb + (int64_t)(t.z0 + zs) * plane, pbytes);
 #pragma unroll
         for (int m = 0; m < MI; ++m) {
             if (s.rx[m] < 0) continue;
@@ -712,10 +731,20 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
             const T adv = (fhi - fxb[r * L.fxp + x])
                         + (fyb[(r + 1) * L.fyp + x] - fyb[r * L.fyp + x]) + s.pz[m];
             const T e = -adv * inv_h + s.plap[m] * lap_s;
-            T rhs = gdt * e - bdt * s.pb4[m];
-            if (pa.e_mode != 0) rhs += rdt * s.eold[m];
-            if (pa.e_mode != 2) Ez.store(s.col[m], e);
-            tb[(x + tw) * L.tbp + zs * rows + r] = A(rhs);
+            if constexpr (E25) {
+                // every term explicit: N = E - Cn^2/(h^4 Pe) (25-point lap^2 C),
+                // kept in place of E for the next substage
+                const T nk = e - bdt * (s.pb4[m] + T(2) * (s.pmix[m] + yz[m]));
+                T rhs = gdt * nk;
+                if (pa.e_mode != 0) rhs += rdt * s.eold[m];
+                if (pa.e_mode != 2) Ez.store(s.col[m], nk);
+                Qz.store(s.col[m], cc[m] + rhs);
+            } else {
+                T rhs = gdt * e - bdt * s.pb4[m];
+                if (pa.e_mode != 0) rhs += rdt * s.eold[m];
+                if (pa.e_mode != 2) Ez.store(s.col[m], e);
+                tb[(x + tw) * L.tbp + zs * rows + r] = A(rhs);
+            }
         }
     };
 
@@ -752,6 +781,15 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 s.mq[m][1] = mu(s.cz[m][3]);   // psi'(C) at z0-2 .. z0 after the first shift
                 s.mq[m][2] = mu(s.cz[m][4]);
                 s.vel[m][4] = PlaneRef<T>(Wz, pbytes)(s.col[m]);
+                if constexpr (E25) {
+                    // rows y-1, y+1 at plane z0-1 (the first shift moves them down)
+                    const PlaneRef<T> Cm(Cb + (int64_t)map_idx(t.z0 - 1, nz, bd.bc[2]) * plane,
+                                         pbytes);
+                    const uint32_t xb = (uint32_t)x * sT;
+                    s.hq[m][0][0] = s.hq[m][1][0] = T(0);
+                    s.hq[m][0][1] = Cm(hoffb[2] + xb);
+                    s.hq[m][1][1] = Cm(hoffb[3] + xb);
+                }
             }
             s.xmask[m] = mask;
         }
@@ -793,16 +831,40 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                     for (int hr = 0; hr < 6; ++hr) {
                         if (hown[hr] != r) continue;
                         const T v = s.nhalo[b][m][hr];
-                        pb[hrow[hr] * L.pbp + 3 + x] = v;
+                        if (E25 && (hr == 2 || hr == 3))   // the mixed xy term reads x +- 1
+                            put(pb, L.pbp, 3, hrow[hr], x, s.cxp[m], s.xmask[m], v);
+                        else
+                            pb[hrow[hr] * L.pbp + 3 + x] = v;
                         if (hr == 2) mb[1 + x] = mu(v);
                         if (hr == 3) mb[(rows + 1) * L.mbp + 1 + x] = mu(v);
                     }
                 }
             }
+            // explicit mode: the mixed yz difference of the plane below, from the
+            // rows y-1, y+1 at z-2, z-1 (queue) and z (this plane's halo)
+            T yz[MI], cc[MI];
+            if constexpr (E25) {
+#pragma unroll
+                for (int m = 0; m < MI; ++m) {
+                    if (s.rx[m] < 0) continue;
+                    const T* c = s.cz[m];
+                    const T* hm = s.hq[m][0];
+                    const T* hp = s.hq[m][1];
+                    const T lo = (hm[0] - hm[1]) + (s.nhalo[b][m][2] - hm[1]);
+                    const T mid = (c[1] - c[2]) + (c[3] - c[2]);
+                    const T hi = (hp[0] - hp[1]) + (s.nhalo[b][m][3] - hp[1]);
+                    yz[m] = (lo + hi) - T(2) * mid;
+                    cc[m] = c[2];
+                    s.hq[m][0][0] = hm[1];
+                    s.hq[m][0][1] = s.nhalo[b][m][2];
+                    s.hq[m][1][0] = hp[1];
+                    s.hq[m][1][1] = s.nhalo[b][m][3];
+                }
+            }
             // start the loads X_PREFETCH planes up, before any store of this phase
             if (zs + X_PREFETCH < t.nzc) fetch(s, IC<b>{}, z + X_PREFETCH);
             // RHS of the plane below (stores E)
-            if (zs > 0) rhs_plane(s, zs - 1);
+            if (zs > 0) rhs_plane(s, zs - 1, yz, cc);
 #pragma unroll
             for (int m = 0; m < MI; ++m) {
                 if (s.rx[m] < 0) continue;
@@ -813,6 +875,10 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 s.mq[m][2] = mu(s.cz[m][4]);
                 put(pb, L.pbp, 3, r + 3, x, s.cxp[m], s.xmask[m], own[m]);
                 put(mb, L.mbp, 1, r + 1, x, s.cxm[m], s.xmask[m], s.mq[m][1]);
+                if constexpr (E25) {
+                    put(zmb, L.mbp, 1, 0, x, s.cxm[m], s.xmask[m], s.cz[m][2]);
+                    put(zpb, L.mbp, 1, 0, x, s.cxm[m], s.xmask[m], s.cz[m][4]);
+                }
             }
         });
         // ---- face fluxes, Laplacian of psi'(C), fourth differences
@@ -853,6 +919,15 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 s.pb4[m] = d4<T>(row[-2], row[-1], row[0], row[1], row[2])
                          + d4<T>(colm[p], colm[2 * p], colm[3 * p], colm[4 * p], colm[5 * p])
                          + d4<T>(c[1], c[2], c[3], c[4], c[5]);
+                if constexpr (E25) {
+                    // mixed second differences xy (rows y -+ 1 of this plane) and xz
+                    // (the owned row at z -+ 1)
+                    auto d2x = [](const T* q) { return (q[-1] - q[0]) + (q[1] - q[0]); };
+                    const T dx0 = d2x(row);
+                    const T xy = (d2x(row - p) + d2x(row + p)) - T(2) * dx0;
+                    const T xz = (d2x(zmb + 1 + x) + d2x(zpb + 1 + x)) - T(2) * dx0;
+                    s.pmix[m] = xy + xz;
+                }
                 if (m + 1 < MI) sched_fence();
             }
         });
@@ -862,7 +937,30 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
         if (X_PREFETCH == 2 && zs + 1 < t.nzc) plane_step(IC<X_PREFETCH - 1>{}, zs + 1);
     }
     // ---- RHS of the last plane
-    ex.phase([&](int tid) { rhs_plane(st[ex.slot(tid)], t.nzc - 1); });
+    ex.phase([&](int tid) {
+        XState<T, A, MI>& s = st[ex.slot(tid)];
+        T yz[MI], cc[MI];
+        if constexpr (E25) {
+            // rows y -+ 1 at the plane above the chunk, loaded here once
+            const int zl = t.z0 + t.nzc - 1;
+            const PlaneRef<T> Cn1(Cb + (int64_t)map_idx(zl + 1, nz, bd.bc[2]) * plane, pbytes);
+#pragma unroll
+            for (int m = 0; m < MI; ++m) {
+                if (s.rx[m] < 0) continue;
+                const uint32_t xb = (uint32_t)(s.rx[m] & 0xffff) * sT;
+                const T* c = s.cz[m];
+                const T* hm = s.hq[m][0];
+                const T* hp = s.hq[m][1];
+                const T lo = (hm[0] - hm[1]) + (Cn1(hoffb[2] + xb) - hm[1]);
+                const T mid = (c[2] - c[3]) + (c[4] - c[3]);
+                const T hi = (hp[0] - hp[1]) + (Cn1(hoffb[3] + xb) - hp[1]);
+                yz[m] = (lo + hi) - T(2) * mid;
+                cc[m] = c[3];
+            }
+        }
+        rhs_plane(s, t.nzc - 1, yz, cc);
+    });
+    if constexpr (E25) return;   // no solve: the new C is written
     // ---- halos of the solve tile
     ex.phase([&](int tid) {
         const int span = 2 * tw;

@@ -12,6 +12,8 @@
 // halos) land on the same XCD and its L2.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ch_device.h"
 #include "ch_kernels.h"
 
@@ -29,8 +31,9 @@ __device__ __forceinline__ int xcd_task(int wg, int nwg)
 
 // NT bounds the work-group size and so the registers per lane: 512 VGPRs per
 // SIMD lane over the group's waves per SIMD (256 for 512 threads, 170 for
-// 768, 128 for 1024).
-template <typename T, typename A, int MI, int NT>
+// 768, 128 for 1024).  E25 selects the explicit 25-point scheme (no solve,
+// the new C is written to Q).
+template <typename T, typename A, int MI, int NT, bool E25>
 __global__ void __launch_bounds__(NT)
 k_pass_x(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
          const T* __restrict__ C, const T* __restrict__ U, const T* __restrict__ V,
@@ -41,7 +44,7 @@ k_pass_x(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
     const int b = chd::find_box(boxes, nbox, chd::PASS_X, task);
     chd::GpuExec ex{(int)threadIdx.x, (int)blockDim.x};
     chd::XState<T, A, MI> st;
-    chd::pass_x_program<T, A, MI>(ex, &st, boxes[b], pa, task, C, U, V, W, E, Q, smem);
+    chd::pass_x_program<T, A, MI, E25>(ex, &st, boxes[b], pa, task, C, U, V, W, E, Q, smem);
 }
 
 template <typename T, typename A, int PASS>
@@ -192,33 +195,50 @@ k_interp(const T* __restrict__ src, int64_t sx, int64_t sy, int64_t tnx, int64_t
 // ---------------------------------------------------------------------------
 // host-side launchers (declared in ch_kernels.h)
 // ---------------------------------------------------------------------------
-template <typename T, typename A, int MI, int NT>
+template <typename T, typename A, int MI, int NT, bool E25>
 static hipError_t launch_x(int nwg, int nth, size_t lds, hipStream_t st, const chd::BoxDesc* boxes,
                            int nbox, const chd::PassArgs& pa, const void* C, const void* U,
                            const void* V, const void* W, void* E, void* Q)
 {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)&k_pass_x<T, A, MI, NT>,
+        hipError_t e = hipFuncSetAttribute((const void*)&k_pass_x<T, A, MI, NT, E25>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_pass_x<T, A, MI, NT>), dim3(nwg), dim3(nth), lds, st, boxes, nbox, pa,
+    hipLaunchKernelGGL((k_pass_x<T, A, MI, NT, E25>), dim3(nwg), dim3(nth), lds, st, boxes, nbox, pa,
                        (const T*)C, (const T*)U, (const T*)V, (const T*)W, (T*)E, (T*)Q);
     return hipGetLastError();
+}
+
+template <typename T, typename A, bool E25>
+static hipError_t launch_x_mode(int mi, int nwg, int nth, size_t lds, hipStream_t st,
+                                const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
+                                const void* C, const void* U, const void* V, const void* W,
+                                void* E, void* Q)
+{
+    if (mi == 1 && nth <= 512)
+        return launch_x<T, A, 1, 512, E25>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    if (mi == 1)
+        return launch_x<T, A, 1, 1024, E25>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    if (nth <= 768)
+        return launch_x<T, A, 2, 768, E25>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    return launch_x<T, A, 2, 1024, E25>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
 }
 
 template <typename T, typename A>
 hipError_t launch_pass_x(int mi, int nwg, int nth, size_t lds, hipStream_t st,
                          const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
                          const void* C, const void* U, const void* V, const void* W, void* E,
-                         void* Q)
+                         void* Q, bool e25)
 {
-    if (mi == 1 && nth <= 512)
-        return launch_x<T, A, 1, 512>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
-    if (mi == 1) return launch_x<T, A, 1, 1024>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
-    if (nth <= 768)
-        return launch_x<T, A, 2, 768>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
-    return launch_x<T, A, 2, 1024>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    if constexpr (std::is_same<T, A>::value) {
+        if (e25)
+            return launch_x_mode<T, A, true>(mi, nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W,
+                                             E, Q);
+    } else {
+        if (e25) return hipErrorInvalidValue;   // the explicit mode has no solve precision
+    }
+    return launch_x_mode<T, A, false>(mi, nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
 }
 
 template <typename T, typename A>
@@ -281,7 +301,7 @@ hipError_t launch_interp(hipStream_t st, const void* src, int64_t sx, int64_t sy
     template hipError_t launch_pass_x<T, A>(int, int, int, size_t, hipStream_t,                 \
                                             const chd::BoxDesc*, int,                           \
                                             const chd::PassArgs&, const void*, const void*,     \
-                                            const void*, const void*, void*, void*);            \
+                                            const void*, const void*, void*, void*, bool);      \
     template hipError_t launch_pass_line<T, A>(int, int, int, size_t, hipStream_t,              \
                                                const chd::BoxDesc*, int, const chd::PassArgs&,  \
                                                const void*, void*);

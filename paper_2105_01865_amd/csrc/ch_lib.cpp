@@ -139,8 +139,9 @@ ch_status init_engine(Engine& e, int nbox, const ch_grid* g, const double* Cn, c
 
 // New coefficients and launch configuration for dt; the table is read by
 // work already in the stream, so wait before replacing it.
-ch_status set_dt(Engine& e, double dt)
+ch_status set_dt(Engine& e, double dt, bool e25 = false)
 {
+    e.P.e25 = e25;
     ch_status st = chp::plan_dt(e.P, dt);
     if (st != CH_OK) {
         e.P.dt = NAN;
@@ -184,7 +185,7 @@ hipError_t enqueue_substage(Engine& e, int k, const void* u, const void* v, cons
         if (p == 0)
             err = chk::launch_pass_x<T, A>(e.P.mi, e.P.ntask[0], e.P.x_threads, e.P.lds[0],
                                            e.stream, e.d_boxes, e.P.nbox, pa,
-                                           e.C, u, v, w, e.E, e.qa);
+                                           e.C, u, v, w, e.E, e.qa, false);
         else if (p == 1)
             err = chk::launch_pass_line<T, A>(chd::PASS_Y, e.P.ntask[1], e.P.yz_threads,
                                               e.P.lds[1], e.stream, e.d_boxes, e.P.nbox, pa, e.qa,
@@ -200,6 +201,56 @@ hipError_t enqueue_substage(Engine& e, int k, const void* u, const void* v, cons
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
+}
+
+// One substage of the explicit 25-point scheme: the x-pass program in its
+// explicit mode writes C + RHS to qa, which then becomes C.
+template <typename T>
+hipError_t enqueue_substage_e25(Engine& e, int k, const void* u, const void* v, const void* w)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (e.prof) {
+        a = take_event(e);
+        b = take_event(e);
+        if (a) (void)hipEventRecord(a, e.stream);
+    }
+    const chd::PassArgs pa = chp::pass_args(e.P, k, 0);
+    hipError_t err = chk::launch_pass_x<T, T>(e.P.mi, e.P.ntask[0], e.P.x_threads, e.P.lds[0],
+                                              e.stream, e.d_boxes, e.P.nbox, pa, e.C, u, v, w,
+                                              e.E, e.qa, true);
+    if (e.prof && a && b) {
+        (void)hipEventRecord(b, e.stream);
+        e.ev_pending.push_back({0, {a, b}});
+    }
+    if (err == hipSuccess) std::swap(e.C, e.qa);
+    return err;
+}
+
+ch_status run_steps_e25(Engine& e, const void* u, const void* v, const void* w, double dt,
+                        int nsteps)
+{
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CH_EINVAL, "dt must be > 0 and finite");
+    if (nsteps < 0) return fail(CH_EINVAL, "nsteps must be >= 0");
+    if (!u || !v || !w) return fail(CH_EINVAL, "null velocity");
+    HIP_TRY(hipSetDevice(e.device));
+    if (dt != e.P.dt || !e.P.e25) {
+        ch_status st = set_dt(e, dt, true);
+        if (st != CH_OK) return st;
+    }
+    // the buffers of C and qa trade places every substage: a captured step
+    // of the implicit scheme would address the wrong one
+    if (e.gexec && nsteps > 0) {
+        (void)hipGraphExecDestroy(e.gexec);
+        e.gexec = nullptr;
+    }
+    for (int s = 0; s < nsteps; ++s)
+        for (int k = 0; k < 3; ++k) {
+            hipError_t err = e.P.prec == CH_FP64 ? enqueue_substage_e25<double>(e, k, u, v, w)
+                                                 : enqueue_substage_e25<float>(e, k, u, v, w);
+            if (err != hipSuccess)
+                return fail(CH_EHIP, "kernel launch failed: %s", hipGetErrorString(err));
+        }
+    return CH_OK;
 }
 
 struct InterpData;
@@ -290,7 +341,7 @@ ch_status run_steps(Engine& e, const void* u, const void* v, const void* w, doub
     if (!ip && (!u || !v || !w)) return fail(CH_EINVAL, "null velocity");
     if (ip && (!uc || !vc || !wc)) return fail(CH_EINVAL, "null coarse velocity");
     HIP_TRY(hipSetDevice(e.device));
-    if (dt != e.P.dt) {
+    if (dt != e.P.dt || e.P.e25) {
         ch_status st = set_dt(e, dt);
         if (st != CH_OK) return st;
     }
@@ -539,6 +590,13 @@ ch_status ch_step(ch_state* s, const void* u, const void* v, const void* w, doub
 {
     CHECK_STATE(s);
     return run_steps(s->e, u, v, w, dt, nsteps, nullptr, nullptr, nullptr, nullptr);
+}
+
+ch_status ch_step_explicit25(ch_state* s, const void* u, const void* v, const void* w,
+                             double dt, int nsteps)
+{
+    CHECK_STATE(s);
+    return run_steps_e25(s->e, u, v, w, dt, nsteps);
 }
 
 ch_status ch_mass(ch_state* s, double* out)

@@ -97,6 +97,7 @@ struct Plan {
     // for the current dt
     double dt = NAN;
     bool acc64 = true;
+    bool e25 = false;   // explicit 25-point scheme: no line solves, one row per x task
     int tw_max = 0;
     int x_rows = 0, x_threads = 256, zc = 1, mi = 1, lanes = 32, yz_threads = 256, seg_cap = 0;
     int ntask[3] = {0, 0, 0};
@@ -227,12 +228,22 @@ inline ch_status plan_dt(Plan& P, double dt)
     for (int b = 0; b < P.nbox; ++b) {
         chd::BoxDesc& d = P.boxes[b];
         const double h = P.g[b].h, Cn = P.Cn[b], Pe = P.Pe[b], kap = P.opt.kappa;
-        const double bih = kap * Cn * Cn / (h * h * h * h);
+        // the per-direction fourth differences carry kappa; the explicit
+        // 25-point operator is Cn^2/h^4 times the full discrete lap^2, and it
+        // enters the explicit operator N with weight 1/Pe
+        const double bih = (P.e25 ? 1.0 : kap) * Cn * Cn / (h * h * h * h);
         for (int k = 0; k < 3; ++k) {
             const double al = RK_G[k] + RK_R[k];
             d.gdt[k] = RK_G[k] * dt;
             d.rdt[k] = RK_R[k] * dt;
             d.bdt[k] = al * dt / Pe * bih;
+            if (P.e25) {
+                d.bdt[k] = bih / Pe;   // the biharmonic is an explicit term (gamma/rho)
+                d.a1[k] = d.a2[k] = 0.0;
+                d.ic[k] = 1.0;
+                d.tw[k] = 0;
+                continue;
+            }
             const double r = 0.5 * al * dt / Pe * bih;
             rmax = std::max(rmax, r);
             int tw = 0;
@@ -261,7 +272,7 @@ inline ch_status plan_dt(Plan& P, double dt)
     // chunks per x line (fixed by the line: see line_chunk_len)
     auto nch_x = [](int n) { return std::max(1, std::min(n / 16, chd::X_CHAINS)); };
     auto xlds = [&](int R, int zc) {
-        return chd::x_layout(nxm, R, zc, P.tw_max, (int)sT, (int)sA).total;
+        return chd::x_layout(nxm, R, zc, P.tw_max, (int)sT, (int)sA, P.e25).total;
     };
     const int xwaves = sT == 4 ? X_WAVES_F32 : X_WAVES_F64;
     auto xbudget_for = [&](int R) {
@@ -270,7 +281,7 @@ inline ch_status plan_dt(Plan& P, double dt)
         const int groups = std::max(1, xwaves / std::max(1, per_simd));
         return LDS_HARD / (size_t)groups;
     };
-    int R = P.opt.x_rows;
+    int R = P.e25 ? 1 : P.opt.x_rows;   // the explicit mode reads rows y -+ 1 as halo
     if (R == 0) {
         // about 256 threads per work-group: one row of a long line, several
         // of short ones (each extra row also shares its y faces)
@@ -283,7 +294,7 @@ inline ch_status plan_dt(Plan& P, double dt)
     if (P.x_threads > X_MAX_THREADS) return P.fail(CH_EINVAL, "x_rows too large for the x extent");
     // planes per task: every line of a task needs its chunks' threads
     int zlim = 64;
-    for (int b = 0; b < P.nbox; ++b) {
+    for (int b = 0; b < P.nbox && !P.e25; ++b) {
         const int rb = std::min(R, P.boxes[b].n[1]);
         zlim = std::min(zlim, P.x_threads / (rb * nch_x(P.boxes[b].n[0])));
     }

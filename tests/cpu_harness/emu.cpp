@@ -7,8 +7,9 @@
 // planned size, it checks the kernels' indexing without a GPU.
 //
 // usage: emu PARAMS IN_DIR OUT_DIR
-//   PARAMS: "nbox prec kappa eps solve x_rows seg_len waves z_chunk dt nsteps" then
-//           per box "nx ny nz h Cn Pe bcx bcy bcz"
+//   PARAMS: "nbox prec kappa eps solve x_rows seg_len waves z_chunk dt nsteps mode"
+//           then per box "nx ny nz h Cn Pe bcx bcy bcz"; mode 0 is the
+//           factorised implicit scheme, 1 the explicit 25-point scheme
 //   IN_DIR/{C,u,v,w}.bin: packed float64 arrays (the library's layout)
 //   OUT_DIR/C.bin: packed float64 result; OUT_DIR/mass.txt: per-box mass;
 //   OUT_DIR/plan.txt: x_rows seg_cap chains tw_max acc64 ntask0..2 lds0..2
@@ -43,7 +44,7 @@ static T* dev_copy(const std::vector<double>& v)
     return p;
 }
 
-template <typename T, typename A, int MI>
+template <typename T, typename A, int MI, bool E25 = false>
 static void run_x(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T* v, const T* w)
 {
     const chd::BoxDesc* boxes = P.boxes.data();
@@ -54,7 +55,8 @@ static void run_x(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T* v
         unsigned char* lds = (unsigned char*)malloc(P.lds[0]);
         memset(lds, 0xff, P.lds[0]);
         const int b = chd::find_box(boxes, P.nbox, chd::PASS_X, task);
-        chd::pass_x_program<T, A, MI>(ex, st.data(), boxes[b], pa, task, C, u, v, w, E, qa, lds);
+        chd::pass_x_program<T, A, MI, E25>(ex, st.data(), boxes[b], pa, task, C, u, v, w, E, qa,
+                                           lds);
         free(lds);
     }
 }
@@ -117,6 +119,20 @@ static std::vector<double> masses(const chp::Plan& P, const T* C)
     return out;
 }
 
+// the explicit 25-point scheme: one x-pass program per substage, C + RHS
+// into qa, which becomes C
+template <typename T>
+static void run_e25(chp::Plan& P, T*& C, T* E, T*& qa, const T* u, const T* v, const T* w,
+                    int nsteps)
+{
+    for (int s = 0; s < nsteps; ++s)
+        for (int k = 0; k < 3; ++k) {
+            if (P.mi == 1) run_x<T, T, 1, true>(P, k, C, E, qa, u, v, w);
+            else run_x<T, T, 2, true>(P, k, C, E, qa, u, v, w);
+            std::swap(C, qa);
+        }
+}
+
 template <typename T>
 static int go(chp::Plan& P, const std::string& in, const std::string& out, int nsteps)
 {
@@ -129,7 +145,8 @@ static int go(chp::Plan& P, const std::string& in, const std::string& out, int n
     T* u = dev_copy<T>(read_bin(in + "/u.bin", P.tot[1]));
     T* v = dev_copy<T>(read_bin(in + "/v.bin", P.tot[2]));
     T* w = dev_copy<T>(read_bin(in + "/w.bin", P.tot[3]));
-    if (P.prec == CH_FP64) run<T, T>(P, C, E, qa, qb, u, v, w, nsteps);
+    if (P.e25) run_e25<T>(P, C, E, qa, u, v, w, nsteps);
+    else if (P.prec == CH_FP64) run<T, T>(P, C, E, qa, qb, u, v, w, nsteps);
     else if (P.acc64) run<T, double>(P, C, E, qa, qb, u, v, w, nsteps);
     else run<T, float>(P, C, E, qa, qb, u, v, w, nsteps);
     std::vector<double> res(P.tot[0]);
@@ -158,10 +175,10 @@ int main(int argc, char** argv)
     }
     FILE* f = fopen(argv[1], "r");
     if (!f) return 2;
-    int nbox, prec, solve, x_rows, seg, waves, zchunk, nsteps;
+    int nbox, prec, solve, x_rows, seg, waves, zchunk, nsteps, mode;
     double kappa, eps, dt;
-    if (fscanf(f, "%d %d %lf %lf %d %d %d %d %d %lf %d", &nbox, &prec, &kappa, &eps, &solve,
-               &x_rows, &seg, &waves, &zchunk, &dt, &nsteps) != 11)
+    if (fscanf(f, "%d %d %lf %lf %d %d %d %d %d %lf %d %d", &nbox, &prec, &kappa, &eps, &solve,
+               &x_rows, &seg, &waves, &zchunk, &dt, &nsteps, &mode) != 12)
         return 2;
     std::vector<ch_grid> g(nbox);
     std::vector<double> Cn(nbox), Pe(nbox);
@@ -187,6 +204,7 @@ int main(int argc, char** argv)
     o.waves_yz = waves;
     o.z_chunk = zchunk;
     chp::Plan P;
+    P.e25 = mode == 1;
     if (chp::plan_init(P, nbox, g.data(), Cn.data(), Pe.data(), nullptr, bc.data(), &o) != CH_OK ||
         chp::plan_dt(P, dt) != CH_OK) {
         fprintf(stderr, "plan failed: %s\n", P.err.c_str());

@@ -27,13 +27,13 @@ def pack(arrays):
 
 
 def run_emu(boxes, dt, nsteps, prec=0, kappa=4.0, eps=1e-6, solve=0, x_rows=0, seg=0,
-            waves=0, z_chunk=0):
+            waves=0, z_chunk=0, mode=0):
     """boxes: list of dicts with C, u, v, w, h, Cn, Pe, bc.  Returns (list of
     C arrays, masses, plan dict)."""
     with tempfile.TemporaryDirectory() as d:
         with open(os.path.join(d, "params.txt"), "w") as f:
             f.write(f"{len(boxes)} {prec} {kappa!r} {eps!r} {solve} {x_rows} {seg} {waves} "
-                    f"{z_chunk} {dt!r} {nsteps}\n")
+                    f"{z_chunk} {dt!r} {nsteps} {mode}\n")
             for b in boxes:
                 nz, ny, nx = b["C"].shape
                 bc = b.get("bc", (0, 0, 0))

@@ -118,3 +118,24 @@ def test_long_x_lines_two_cells_per_thread():
     b = _box((8, 9, 1100), seed=12, amp=1.0, drops=False)
     out, _, plan = run_emu([b], 2e-4, 1, z_chunk=3)
     assert _rel(out[0], _oracle(b, 2e-4, 1)) < 1e-12
+
+
+@pytest.mark.parametrize("zc", [1, 3])
+@pytest.mark.parametrize("shape,bc", [((20, 12, 16), (0, 0, 0)), ((16, 9, 24), (0, 0, 1)),
+                                      ((12, 16, 8), (1, 0, 1)), ((1, 24, 16), (0, 0, 0)),
+                                      ((8, 8, 1100), (0, 0, 0))])
+def test_explicit25_matches_oracle(shape, bc, zc):
+    """The explicit 25-point mode of the x-pass program (no solves, mixed
+    second differences, C + RHS written out) against the oracle's explicit
+    scheme, including walls, a degenerate axis and two cells per thread."""
+    b = _box(shape, bc=bc, seed=11)
+    dt = 1e-4 if shape[2] < 1000 else 2e-6       # below the explicit limit
+    ref = oracle.step_explicit25(b["C"], b["u"], b["v"], b["w"], b["h"], b["Cn"], b["Pe"], dt,
+                                 2, bc=bc)
+    out, masses, plan = run_emu([b], dt, 2, mode=1, z_chunk=zc)
+    assert plan["x_rows"] == 1
+    assert _rel(out[0], ref) < 1e-12
+    assert _rel(out[0] - b["C"], ref - b["C"]) < 1e-9
+    assert abs(masses[0] - oracle.mass(ref, b["h"])) < 1e-12 * abs(masses[0])
+    out32, _, _ = run_emu([b], dt, 2, prec=1, mode=1, z_chunk=zc)
+    assert _rel(out32[0], ref) < 2e-6

@@ -265,3 +265,53 @@ def test_config5_full_ensemble_sampled_boxes_against_oracle():
             e = rel(outs[i].double().cpu().numpy(), refs[i])
             print(f"  box {i} edge {shapes[i][0]}: rel {e:.2e}")
             assert e <= tol
+
+
+def test_explicit25_against_oracle():
+    """The explicit 25-point scheme (no line solves) against the oracle's:
+    config 1, a walled ragged box, FP32, and the 256^3 box at full size."""
+    wl = inputs.make_workload(1)
+    cases = [(wl.C, wl.u, wl.v, wl.w, wl.h, (0, 0, 0), 1e-4, 2)]
+    C, u, v, w, h = _case((16, 9, 24), bc=(0, 0, 1), seed=21)
+    cases.append((C, u, v, w, h, (0, 0, 1), 1e-4, 2))
+    for C, u, v, w, h, bc, dt, n in cases:
+        ref = oracle.step_explicit25(C, u, v, w, h, h, 0.9 / h, dt, n, bc=bc)
+        for prec, tol in (("fp64", TOL64 * n), ("fp32", 5e-6)):
+            print(f"[gpu] explicit25 shape={C.shape} bc={bc} {prec}", flush=True)
+            dt_ = torch.float64 if prec == "fp64" else torch.float32
+            s = ch.State(C.shape, h, h, 0.9 / h, bc=bc, precision=prec, stream=torch.cuda.Stream())
+            s.set_field(dev(C, dt_))
+            s.step_explicit25(dev(u, dt_), dev(v, dt_), dev(w, dt_), dt, n)
+            got = s.get_field().double().cpu().numpy()
+            s.close()
+            print(f"  rel {rel(got, ref):.2e}")
+            assert rel(got, ref) <= tol
+    wl = inputs.make_workload(2)
+    ref = oracle.step_explicit25(wl.C, wl.u, wl.v, wl.w, wl.h, wl.Cn, wl.Pe, 5e-5, 1)
+    s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, stream=torch.cuda.Stream())
+    s.set_field(dev(wl.C))
+    s.step_explicit25(dev(wl.u), dev(wl.v), dev(wl.w), 5e-5, 1)
+    got = s.get_field().cpu().numpy()
+    s.close()
+    print(f"  256^3 explicit25 rel {rel(got, ref):.2e}")
+    assert rel(got, ref) <= TOL64
+
+
+def test_explicit_and_implicit_steps_interleave():
+    """Explicit steps trade the state's buffers; implicit steps after them
+    (captured and replayed as graphs) must still use the right ones."""
+    C, u, v, w, h = _case((24, 16, 32), seed=22)
+    Pe, dt = 0.9 / h, 1e-4
+    ref = oracle.step(C, u, v, w, h, h, Pe, dt, 2)
+    ref = oracle.step_explicit25(ref, u, v, w, h, h, Pe, dt, 1)
+    ref = oracle.step(ref, u, v, w, h, h, Pe, dt, 2)
+    st = torch.cuda.Stream()
+    s = ch.State(C.shape, h, h, Pe, stream=st)
+    s.set_field(dev(C))
+    U, V, W = dev(u), dev(v), dev(w)
+    s.step(U, V, W, dt, 2)
+    s.step_explicit25(U, V, W, dt, 1)
+    s.step(U, V, W, dt, 2)
+    got = s.get_field().cpu().numpy()
+    s.close()
+    assert rel(got, ref) <= 5 * TOL64
