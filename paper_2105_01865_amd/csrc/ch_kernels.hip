@@ -19,6 +19,13 @@
 
 namespace chk {
 
+// Waves per SIMD the single-precision, one-cell-per-thread x kernel of the
+// implicit scheme is compiled for (its register budget); the other variants
+// keep the compiler's choice (forcing them spills).
+#ifndef X_WAVES_F32_HINT
+#define X_WAVES_F32_HINT 5
+#endif
+
 // Work-groups are dispatched round-robin over the 8 XCDs of the chip; give
 // each XCD a contiguous range of tasks.
 __device__ __forceinline__ int xcd_task(int wg, int nwg)
@@ -35,6 +42,7 @@ __device__ __forceinline__ int xcd_task(int wg, int nwg)
 // the new C is written to Q).
 template <typename T, typename A, int MI, int NT, bool E25>
 __global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MI == 1 && !E25 ? X_WAVES_F32_HINT : 1)))
 k_pass_x(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
          const T* __restrict__ C, const T* __restrict__ U, const T* __restrict__ V,
          const T* __restrict__ W, T* __restrict__ E, T* __restrict__ Q)

@@ -25,10 +25,11 @@ constexpr double RK_R[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 constexpr size_t LDS_BUDGET = 64 * 1024;   // default per work-group
 constexpr size_t LDS_HARD = 160 * 1024;    // gfx950 LDS per CU
 // Waves per SIMD that the x kernel's registers allow (512 VGPRs per lane
-// over 118 in single precision, 157 in double, for one cell per thread).
+// over 96 in single precision (the kernel is built for 5 waves), 140 in
+// double, for one cell per thread).
 // The x tile's LDS budget is the CU's LDS shared by the work-groups that
 // many waves make room for.
-constexpr int X_WAVES_F32 = 4;
+constexpr int X_WAVES_F32 = 5;
 constexpr int X_WAVES_F64 = 3;
 constexpr int X_MAX_THREADS = 1024;        // largest x-pass work-group
 
@@ -279,7 +280,9 @@ inline ch_status plan_dt(Plan& P, double dt)
         const int threads = ((R * nxm + P.mi - 1) / P.mi + 63) / 64 * 64;
         const int per_simd = (threads / 64 + 3) / 4;   // waves of one group per SIMD
         const int groups = std::max(1, xwaves / std::max(1, per_simd));
-        return LDS_HARD / (size_t)groups;
+        // measured on gfx950: five groups of the single-precision kernel
+        // share a CU only with about 2 KB of LDS headroom each
+        return LDS_HARD / (size_t)groups - (groups >= 5 ? 2048 : 0);
     };
     int R = P.e25 ? 1 : P.opt.x_rows;   // the explicit mode reads rows y -+ 1 as halo
     if (R == 0) {
