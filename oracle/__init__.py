@@ -65,6 +65,10 @@ def lib():
                                              ctypes.c_double, _I64, _D]
         L.oracle_interp_velocity.restype = ctypes.c_int
         L.oracle_interp_velocity.argtypes = [_I64, _D, _D, _D, _D, _I64, _D, _D, _D]
+        L.oracle_solenoidal_velocity.restype = ctypes.c_int
+        L.oracle_solenoidal_velocity.argtypes = [_I64, _D, _D, _D, _D, _I64, _D, _D, _D, _D]
+        L.oracle_project_c.restype = ctypes.c_int
+        L.oracle_project_c.argtypes = [_I64, _D, _I64, _D, _D]
         _lib = L
     return _lib
 
@@ -228,3 +232,41 @@ def interp_velocity(zf, uc, vc, wc, nf):
     if rc:
         raise RuntimeError("oracle_interp_velocity failed")
     return uf, vf, wf
+
+
+def solenoidal_velocity(zf, uc, vc, wc, nf):
+    """The solenoidal variant of the transfer (sec. 3.4): coarse normal
+    gradients interpolated to the fine cell centres, each component
+    integrated along its direction from its reference plane (u on x = 0, v on
+    y = 0, w = 0 on the bottom wall; the top wall stays 0).  Shapes as in
+    interp_velocity.  Returns uf, vf, wf and the largest |closure sum| of the
+    x, y and z lines."""
+    zf, uc, vc, wc = map(_f64, (zf, uc, vc, wc))
+    ncz, ncy, ncx = uc.shape
+    assert vc.shape == uc.shape and wc.shape == (ncz + 1, ncy, ncx) and zf.shape == (ncz + 1,)
+    nfx, nfy, nfz = nf
+    uf = np.empty((nfz, nfy, nfx))
+    vf = np.empty((nfz, nfy, nfx))
+    wf = np.empty((nfz + 1, nfy, nfx))
+    resid = np.zeros(3)
+    rc = lib().oracle_solenoidal_velocity((ctypes.c_int64 * 3)(ncx, ncy, ncz), _dp(zf), _dp(uc),
+                                          _dp(vc), _dp(wc), (ctypes.c_int64 * 3)(nfx, nfy, nfz),
+                                          _dp(uf), _dp(vf), _dp(wf), _dp(resid))
+    if rc:
+        raise RuntimeError("oracle_solenoidal_velocity failed")
+    return uf, vf, wf, resid
+
+
+def project_c(Cf, zf, nc):
+    """Back-coupling of C (sec. 3.4): fine cell-centred C -> coarse cell
+    centres (ncx, ncy, ncz) of the stretched mesh with faces zf."""
+    Cf, zf = _f64(Cf), _f64(zf)
+    nfz, nfy, nfx = Cf.shape
+    ncx, ncy, ncz = nc
+    assert zf.shape == (ncz + 1,)
+    Cc = np.empty((ncz, ncy, ncx))
+    rc = lib().oracle_project_c((ctypes.c_int64 * 3)(nfx, nfy, nfz), _dp(Cf),
+                                (ctypes.c_int64 * 3)(ncx, ncy, ncz), _dp(zf), _dp(Cc))
+    if rc:
+        raise RuntimeError("oracle_project_c failed")
+    return Cc

@@ -18,9 +18,12 @@
  *   - Beyond a wall the source is continued by reflection: tangential
  *     components (cell-centred in z) evenly, the wall-normal component
  *     (on z faces, zero on the walls) oddly.
- *   - The plain form is used: u, v and w are interpolated directly.  The
- *     paper's solenoidal variant (interpolating gradients and integrating
- *     from a reference plane) is not this function.
+ *   - oracle_interp_velocity is the plain form: u, v and w interpolated
+ *     directly.  oracle_solenoidal_velocity is the paper's variant that
+ *     keeps the fine field divergence-free (its readings are listed there).
+ *   - oracle_project_c is the back-coupling of C: fine cell centres to
+ *     coarse cell centres by the same interpolant (C continues evenly
+ *     beyond the walls).
  *
  * Geometry (unit box):
  *   coarse: ncx x ncy cells of width 1/ncx, 1/ncy; ncz cells between the
@@ -181,5 +184,177 @@ int oracle_interp_velocity(const int64_t nc[3], const double* zf, const double* 
     interp_component(aw, wc, nfx, fxc, nfy, fyc, nfz + 1, fzf, wf);
     free(cxf); free(cxc); free(cyf); free(cyc); free(czc);
     free(fxf); free(fxc); free(fyf); free(fyc); free(fzf); free(fzc);
+    return 0;
+}
+
+/* Coordinates of the coarse and fine meshes (see the header comment). */
+typedef struct {
+    int64_t ncx, ncy, ncz, nfx, nfy, nfz;
+    double *cxf, *cxc, *cyf, *cyc, *czc, *fxf, *fxc, *fyf, *fyc, *fzf, *fzc;
+    const double* zf;
+} meshes_t;
+
+static void meshes_free(meshes_t* m)
+{
+    free(m->cxf); free(m->cxc); free(m->cyf); free(m->cyc); free(m->czc);
+    free(m->fxf); free(m->fxc); free(m->fyf); free(m->fyc); free(m->fzf); free(m->fzc);
+}
+
+static int meshes_init(meshes_t* m, const int64_t nc[3], const double* zf, const int64_t nf[3])
+{
+    m->ncx = nc[0]; m->ncy = nc[1]; m->ncz = nc[2];
+    m->nfx = nf[0]; m->nfy = nf[1]; m->nfz = nf[2];
+    m->zf = zf;
+    m->cxf = malloc(sizeof(double) * m->ncx); m->cxc = malloc(sizeof(double) * m->ncx);
+    m->cyf = malloc(sizeof(double) * m->ncy); m->cyc = malloc(sizeof(double) * m->ncy);
+    m->czc = malloc(sizeof(double) * m->ncz);
+    m->fxf = malloc(sizeof(double) * m->nfx); m->fxc = malloc(sizeof(double) * m->nfx);
+    m->fyf = malloc(sizeof(double) * m->nfy); m->fyc = malloc(sizeof(double) * m->nfy);
+    m->fzf = malloc(sizeof(double) * (m->nfz + 1)); m->fzc = malloc(sizeof(double) * m->nfz);
+    if (!m->cxf || !m->cxc || !m->cyf || !m->cyc || !m->czc || !m->fxf || !m->fxc || !m->fyf ||
+        !m->fyc || !m->fzf || !m->fzc) {
+        meshes_free(m);
+        return -1;
+    }
+    for (int64_t i = 0; i < m->ncx; ++i) { m->cxf[i] = (double)i / m->ncx; m->cxc[i] = (i + 0.5) / m->ncx; }
+    for (int64_t j = 0; j < m->ncy; ++j) { m->cyf[j] = (double)j / m->ncy; m->cyc[j] = (j + 0.5) / m->ncy; }
+    for (int64_t k = 0; k < m->ncz; ++k) m->czc[k] = 0.5 * (zf[k] + zf[k + 1]);
+    for (int64_t i = 0; i < m->nfx; ++i) { m->fxf[i] = (double)i / m->nfx; m->fxc[i] = (i + 0.5) / m->nfx; }
+    for (int64_t j = 0; j < m->nfy; ++j) { m->fyf[j] = (double)j / m->nfy; m->fyc[j] = (j + 0.5) / m->nfy; }
+    for (int64_t k = 0; k <= m->nfz; ++k) m->fzf[k] = (double)k / m->nfz;
+    for (int64_t k = 0; k < m->nfz; ++k) m->fzc[k] = (k + 0.5) / m->nfz;
+    return 0;
+}
+
+/* Solenoidal coarse-to-fine transfer (sec. 3.4): instead of the velocity,
+ * its normal gradients are interpolated, and each fine component is then
+ * integrated along its own direction from a reference plane.  Readings where
+ * the paper is brief:
+ *   - The normal gradients are the coarse cell-centred differences
+ *       gx = (u[i+1] - u[i]) ncx,  gy = (v[j+1] - v[j]) ncy,
+ *       gz = (w[k+1] - w[k]) / (zf[k+1] - zf[k]),
+ *     and all three go to the fine cell centres through one and the same
+ *     interpolant (cell-centred source in every direction, even continuation
+ *     beyond the walls), so the interpolated gradients add up to the
+ *     interpolated coarse divergence.
+ *   - The reference planes are the low domain boundaries: u on the fine
+ *     x face 0 and v on the fine y face 0, interpolated from the coarse
+ *     velocity like the plain transfer does; w on the bottom wall is zero.
+ *   - Integration runs upward from the reference plane,
+ *       u[i] = u[0] + hx sum_{i' < i} Gx[i'],  i = 1 .. nfx - 1,
+ *     and likewise for v along y and w along z (w[k], k = 1 .. nfz - 1);
+ *     the top wall keeps w = 0.  The fine divergence is then the
+ *     interpolated coarse divergence in every cell but the last one of each
+ *     line, where the line's closure sum hx sum_{all i'} Gx[i'] (zero for a
+ *     periodic line whose coarse cells all carry the same total weight) is
+ *     left over.  resid[0..2] receive the largest |closure sum| over the
+ *     x, y and z lines (velocity units).
+ */
+int oracle_solenoidal_velocity(const int64_t nc[3], const double* zf, const double* uc,
+                               const double* vc, const double* wc, const int64_t nf[3],
+                               double* uf, double* vf, double* wf, double resid[3])
+{
+    meshes_t m;
+    if (meshes_init(&m, nc, zf, nf)) return -1;
+    const int64_t ncx = m.ncx, ncy = m.ncy, ncz = m.ncz, nfx = m.nfx, nfy = m.nfy, nfz = m.nfz;
+    const int64_t ncell = ncx * ncy * ncz, nfine = nfx * nfy * nfz;
+    double* g = malloc(sizeof(double) * ncell);
+    double* G = malloc(sizeof(double) * nfine);
+    double* ref = malloc(sizeof(double) * (nfx > nfy ? nfx : nfy) * nfz);
+    double* zero1 = malloc(sizeof(double));
+    if (!g || !G || !ref || !zero1) {
+        free(g); free(G); free(ref); free(zero1); meshes_free(&m);
+        return -1;
+    }
+    zero1[0] = 0.0;
+    axis_t ac[3] = {{ncx, m.cxc, 1.0, AX_PERIODIC}, {ncy, m.cyc, 1.0, AX_PERIODIC},
+                    {ncz, m.czc, 1.0, AX_WALL_EVEN}};
+    const double hx = 1.0 / nfx, hy = 1.0 / nfy, hz = 1.0 / nfz;
+    for (int d = 0; d < 3; ++d) resid[d] = 0.0;
+
+    /* u: gradient along x, reference plane x = 0, integrate along x */
+    for (int64_t k = 0; k < ncz; ++k)
+        for (int64_t j = 0; j < ncy; ++j)
+            for (int64_t i = 0; i < ncx; ++i) {
+                const int64_t r = (k * ncy + j) * ncx;
+                g[r + i] = (uc[r + (i + 1) % ncx] - uc[r + i]) * ncx;
+            }
+    interp_component(ac, g, nfx, m.fxc, nfy, m.fyc, nfz, m.fzc, G);
+    {
+        axis_t au[3] = {{ncx, m.cxf, 1.0, AX_PERIODIC}, {ncy, m.cyc, 1.0, AX_PERIODIC},
+                        {ncz, m.czc, 1.0, AX_WALL_EVEN}};
+        interp_component(au, uc, 1, zero1, nfy, m.fyc, nfz, m.fzc, ref);   /* [nfz][nfy] */
+    }
+    for (int64_t k = 0; k < nfz; ++k)
+        for (int64_t j = 0; j < nfy; ++j) {
+            const int64_t r = (k * nfy + j) * nfx;
+            double acc = 0.0;
+            for (int64_t i = 0; i < nfx; ++i) {
+                uf[r + i] = ref[k * nfy + j] + hx * acc;
+                acc += G[r + i];
+            }
+            if (fabs(hx * acc) > resid[0]) resid[0] = fabs(hx * acc);
+        }
+
+    /* v: gradient along y, reference plane y = 0, integrate along y */
+    for (int64_t k = 0; k < ncz; ++k)
+        for (int64_t j = 0; j < ncy; ++j)
+            for (int64_t i = 0; i < ncx; ++i)
+                g[(k * ncy + j) * ncx + i] =
+                    (vc[(k * ncy + (j + 1) % ncy) * ncx + i] - vc[(k * ncy + j) * ncx + i]) * ncy;
+    interp_component(ac, g, nfx, m.fxc, nfy, m.fyc, nfz, m.fzc, G);
+    {
+        axis_t av[3] = {{ncx, m.cxc, 1.0, AX_PERIODIC}, {ncy, m.cyf, 1.0, AX_PERIODIC},
+                        {ncz, m.czc, 1.0, AX_WALL_EVEN}};
+        interp_component(av, vc, nfx, m.fxc, 1, zero1, nfz, m.fzc, ref);   /* [nfz][nfx] */
+    }
+    for (int64_t k = 0; k < nfz; ++k)
+        for (int64_t i = 0; i < nfx; ++i) {
+            double acc = 0.0;
+            for (int64_t j = 0; j < nfy; ++j) {
+                const int64_t e = (k * nfy + j) * nfx + i;
+                vf[e] = ref[k * nfx + i] + hy * acc;
+                acc += G[e];
+            }
+            if (fabs(hy * acc) > resid[1]) resid[1] = fabs(hy * acc);
+        }
+
+    /* w: gradient along z, zero on the bottom wall, integrate along z; the
+       top wall stays zero */
+    for (int64_t k = 0; k < ncz; ++k)
+        for (int64_t j = 0; j < ncy; ++j)
+            for (int64_t i = 0; i < ncx; ++i)
+                g[(k * ncy + j) * ncx + i] =
+                    (wc[((k + 1) * ncy + j) * ncx + i] - wc[(k * ncy + j) * ncx + i])
+                    / (zf[k + 1] - zf[k]);
+    interp_component(ac, g, nfx, m.fxc, nfy, m.fyc, nfz, m.fzc, G);
+    for (int64_t j = 0; j < nfy; ++j)
+        for (int64_t i = 0; i < nfx; ++i) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < nfz; ++k) {
+                const int64_t e = (k * nfy + j) * nfx + i;
+                wf[e] = hz * acc;
+                acc += G[e];
+            }
+            wf[(nfz * nfy + j) * nfx + i] = 0.0;
+            if (fabs(hz * acc) > resid[2]) resid[2] = fabs(hz * acc);
+        }
+    free(g); free(G); free(ref); free(zero1);
+    meshes_free(&m);
+    return 0;
+}
+
+/* Back-coupling of C (sec. 3.4): the fine cell-centred field interpolated to
+ * the coarse cell centres (x, y periodic; beyond the walls C continues
+ * evenly).  Cf [nfz][nfy][nfx] -> Cc [ncz][ncy][ncx]. */
+int oracle_project_c(const int64_t nf[3], const double* Cf, const int64_t nc[3],
+                     const double* zf, double* Cc)
+{
+    meshes_t m;
+    if (meshes_init(&m, nc, zf, nf)) return -1;
+    axis_t af[3] = {{m.nfx, m.fxc, 1.0, AX_PERIODIC}, {m.nfy, m.fyc, 1.0, AX_PERIODIC},
+                    {m.nfz, m.fzc, 1.0, AX_WALL_EVEN}};
+    interp_component(af, Cf, m.ncx, m.cxc, m.ncy, m.cyc, m.ncz, m.czc, Cc);
+    meshes_free(&m);
     return 0;
 }

@@ -109,3 +109,98 @@ def test_reflection_beyond_the_walls_is_accurate_near_both_walls(kind):
         # cubic Hermite error: small against the local cell width cubed
         dz = zf[1] - zf[0]
         assert abs((wt * vals[idx]).sum() - f(t)) < 0.05 * dz ** 2 * np.pi ** 2
+
+
+# ---- the solenoidal variant and the back-projection of C (sec. 3.4) ----
+
+def _fine_div(uf, vf, wf):
+    nz, ny, nx = uf.shape
+    return ((np.roll(uf, -1, axis=2) - uf) * nx + (np.roll(vf, -1, axis=1) - vf) * ny
+            + (wf[1:] - wf[:-1]) * nz)
+
+
+def test_solenoidal_transfer_keeps_the_fine_field_divergence_free():
+    """A coarse field that is a discrete curl (exactly divergence-free on the
+    stretched staggered mesh) gives a fine field whose discrete divergence
+    is zero to rounding in every cell but the top layer (where the z line's
+    closure sum is left); with a refinement ratio of 2 the periodic x and y
+    lines close to rounding too."""
+    nc, zf = (10, 8, 8), inputs.stretched_faces(10, 2.0)
+    uc, vc, wc = inputs.coarse_wall_velocity(np.random.default_rng(5), nc, zf, kmax=3,
+                                             nmodes_z=5)
+    ncz, ncy, ncx = nc
+    cdiv = ((np.roll(uc, -1, axis=2) - uc) * ncx + (np.roll(vc, -1, axis=1) - vc) * ncy
+            + (wc[1:] - wc[:-1]) / np.diff(zf)[:, None, None])
+    scale = max(np.abs(uc).max(), np.abs(vc).max(), np.abs(wc).max())
+    assert np.abs(cdiv).max() < 1e-11 * scale * ncx
+    nf = (16, 16, 20)
+    uf, vf, wf, resid = oracle.solenoidal_velocity(zf, uc, vc, wc, nf)
+    div = _fine_div(uf, vf, wf)
+    tol = 1e-11 * scale * max(nf)
+    assert np.abs(div[:-1]).max() < tol, np.abs(div[:-1]).max()
+    assert resid[0] < 1e-12 * scale and resid[1] < 1e-12 * scale
+    # the top layer carries exactly the z closure sum (per unit height)
+    top = np.abs(div[-1]).max()
+    assert abs(top - resid[2] * nf[2]) <= 1e-9 * max(1.0, top)
+    assert np.all(wf[0] == 0.0) and np.all(wf[-1] == 0.0)
+    # the plain transfer does not have this property
+    ud, vd, wd = oracle.interp_velocity(zf, uc, vc, wc, nf)
+    assert np.abs(_fine_div(ud, vd, wd)[:-1]).max() > 1e3 * tol
+
+
+def test_solenoidal_transfer_reference_planes_and_x_independent_u():
+    nc, zf = (6, 8, 8), inputs.stretched_faces(6, 2.0)
+    uc, vc, wc = inputs.coarse_wall_velocity(np.random.default_rng(6), nc, zf, kmax=3,
+                                             nmodes_z=4)
+    nf = (16, 16, 12)
+    uf, vf, _, _ = oracle.solenoidal_velocity(zf, uc, vc, wc, nf)
+    ud, vd, _ = oracle.interp_velocity(zf, uc, vc, wc, nf)
+    # the reference planes are the plain transfer on the low faces, bitwise
+    assert np.array_equal(uf[:, :, 0], ud[:, :, 0])
+    assert np.array_equal(vf[:, 0, :], vd[:, 0, :])
+    # a u constant along x has no x gradient: every x face repeats face 0
+    uc2 = np.broadcast_to(uc[:, :, :1], uc.shape).copy()
+    uf2, _, _, r = oracle.solenoidal_velocity(zf, uc2, vc, wc, nf)
+    assert np.array_equal(uf2, np.broadcast_to(uf2[:, :, :1], uf2.shape))
+    assert r[0] == 0.0
+
+
+def test_solenoidal_transfer_converges_on_a_smooth_field():
+    errs = []
+    for nc in (8, 16, 32):
+        zf, uc, vc, wc, fns = _analytic(nc, (3 * nc) // 4)
+        nf = 2 * nc
+        uf, vf, wf, _ = oracle.solenoidal_velocity(zf, uc, vc, wc, (nf, nf, nf))
+        eu, ev, ew = _fine_exact(fns, nf)
+        errs.append(max(np.abs(uf - eu).max(), np.abs(vf - ev).max(), np.abs(wf - ew).max()))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 1.8, (errs, rates)
+
+
+def test_projection_of_c_is_the_identity_on_coincident_meshes_and_exact_on_constants():
+    rng = np.random.default_rng(8)
+    n = 12
+    zf = np.arange(n + 1) / n
+    Cf = rng.standard_normal((n, n, n))
+    Cc = oracle.project_c(Cf, zf, (n, n, n))
+    np.testing.assert_allclose(Cc, Cf, rtol=0, atol=1e-14)
+    zf2 = inputs.stretched_faces(10, 2.0)
+    Cc2 = oracle.project_c(np.full((24, 16, 20), 0.37), zf2, (8, 8, 10))
+    np.testing.assert_allclose(Cc2, 0.37, rtol=0, atol=1e-14)
+
+
+def test_projection_of_c_converges():
+    f = lambda x, y, z: np.cos(2 * math.pi * x) * np.sin(2 * math.pi * y + 0.4) * np.cos(math.pi * z)
+    errs = []
+    for nf in (16, 32, 64):
+        c = (np.arange(nf) + 0.5) / nf
+        Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+        nc = nf // 2
+        zf = inputs.stretched_faces((3 * nc) // 4, 2.0)
+        Cc = oracle.project_c(f(X, Y, Z), zf, (nc, nc, (3 * nc) // 4))
+        xc = (np.arange(nc) + 0.5) / nc
+        zc = 0.5 * (zf[:-1] + zf[1:])
+        Zc, Yc, Xc = np.meshgrid(zc, xc, xc, indexing="ij")
+        errs.append(np.abs(Cc - f(Xc, Yc, Zc)).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 2.5, (errs, rates)

@@ -48,6 +48,20 @@ MUTATIONS = [
      "double g1 = D / (x[2] - x[0]);", "double g1 = D / (x[2] - x[1]);"),
     ("odd-reflection", "interp_oracle.c",
      "if (m < 0) { *idx = -m; *sign = -1.0;", "if (m < 0) { *idx = -m; *sign = 1.0;"),
+    ("solenoidal-inclusive-integration", "interp_oracle.c",
+     "uf[r + i] = ref[k * nfy + j] + hx * acc;\n                acc += G[r + i];",
+     "acc += G[r + i];\n                uf[r + i] = ref[k * nfy + j] + hx * acc;"),
+    ("solenoidal-uniform-dz", "interp_oracle.c",
+     "/ (zf[k + 1] - zf[k]);", "* ncz;"),
+    ("solenoidal-gradient-sign", "interp_oracle.c",
+     "(vc[(k * ncy + (j + 1) % ncy) * ncx + i] - vc[(k * ncy + j) * ncx + i]) * ncy;",
+     "(vc[(k * ncy + j) * ncx + i] - vc[(k * ncy + (j + 1) % ncy) * ncx + i]) * ncy;"),
+    ("solenoidal-reference-plane", "interp_oracle.c",
+     "interp_component(au, uc, 1, zero1, nfy, m.fyc, nfz, m.fzc, ref);",
+     "interp_component(ac, uc, 1, zero1, nfy, m.fyc, nfz, m.fzc, ref);"),
+    ("projection-wall-continuation", "interp_oracle.c",
+     "{m.nfz, m.fzc, 1.0, AX_WALL_EVEN}};\n    interp_component(af",
+     "{m.nfz, m.fzc, 1.0, AX_PERIODIC}};\n    interp_component(af"),
 ]
 
 
