@@ -194,8 +194,8 @@ void ch_batch_destroy(ch_batch* b);
  * points per direction (slopes: chord through the two neighbours; beyond a
  * wall the tangential components continue evenly, the normal one oddly).
  * The 1-D stencils are built once at creation; the coarse mesh needs at
- * least 4 cells per axis and at most 8192 along x (CH_EINVAL /
- * CH_EUNSUPPORTED otherwise).  Coarse arrays: uc, vc
+ * least 4 cells per axis and at most 8192 along x in single precision,
+ * 4096 in double (CH_EINVAL / CH_EUNSUPPORTED otherwise).  Coarse arrays: uc, vc
  * [ncz][ncy][ncx], wc [ncz+1][ncy][ncx]; fine: u, v [nz][ny][nx],
  * w [nz+1][ny][nx]; all device memory in the given precision. */
 ch_status ch_interp_create(const ch_grid* fine, int64_t ncx, int64_t ncy, int64_t ncz,
@@ -204,6 +204,38 @@ ch_status ch_interp_set_stream(ch_interp* ip, void* stream);
 ch_status ch_interp_apply(ch_interp* ip, const void* uc, const void* vc, const void* wc,
                           void* u, void* v, void* w);
 void ch_interp_destroy(ch_interp* ip);
+
+/* Solenoidal mode of the transfer (sec. 3.4: the normal velocity gradients
+ * are interpolated instead of the velocity, then integrated from a 2-D
+ * reference plane).  With `on` set, ch_interp_apply and ch_step_multires
+ * form the coarse cell-centred gradients (u[i+1]-u[i]) ncx,
+ * (v[j+1]-v[j]) ncy and (w[k+1]-w[k]) / (zf[k+1]-zf[k]), take all three to
+ * the fine cell centres with one and the same interpolant (so that their
+ * sum is the interpolated coarse divergence), and integrate each component
+ * along its direction:  u[i] = u_ref + (1/nx) sum_{i'<i} G_x[i'] from the
+ * x = 0 face (u_ref: the plain transfer on that face), v likewise from the
+ * y = 0 face, w from 0 on the bottom wall; the top wall stays 0.  A coarse
+ * field that is discretely divergence-free then gives a fine field that is
+ * too in every cell but the last of each line, where the line's closure sum
+ * is left (see ch_interp_closure).  Switching allocates (on) or frees (off)
+ * one coarse field, one reference plane and small tables; it waits for the
+ * handle's stream.  Switching makes step graphs captured with the old mode
+ * stale (they are re-captured).  CH_ENOMEM if the buffers cannot be had. */
+ch_status ch_interp_set_solenoidal(ch_interp* ip, int on);
+
+/* Largest |closure sum| (velocity units) over the x, y and z lines of the
+ * last solenoidal transfer enqueued on the handle: out[d] = max over lines
+ * of |h sum G_d|, zero when the mode is off.  Waits for the stream. */
+ch_status ch_interp_closure(ch_interp* ip, double out[3]);
+
+/* Back-coupling of C (sec. 3.4): the fine cell-centred field Cf
+ * [nz][ny][nx] interpolated to the coarse cell centres, Cc [ncz][ncy][ncx]
+ * (the same interpolant; C continues evenly beyond the walls).  Device
+ * memory in the handle's precision, on the handle's stream.  CH_EUNSUPPORTED
+ * when the fine x extent is too long for the kernel's LDS rows (above 8192
+ * in single precision or 4096 in double, or fewer when the y ratio is
+ * large). */
+ch_status ch_interp_project_c(ch_interp* ip, const void* Cf, void* Cc);
 
 /* nsteps steps where every step first transfers the coarse velocity to the
  * fine faces (into buffers the state allocates on first use) and then

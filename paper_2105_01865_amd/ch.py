@@ -87,6 +87,9 @@ SIGNATURES = {
     "ch_interp_set_stream": (_I, [_VP, _VP]),
     "ch_interp_apply": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "ch_interp_destroy": (None, [_VP]),
+    "ch_interp_set_solenoidal": (_I, [_VP, _I]),
+    "ch_interp_closure": (_I, [_VP, ctypes.POINTER(_D)]),
+    "ch_interp_project_c": (_I, [_VP, _VP, _VP]),
     "ch_step_multires": (_I, [_VP, _VP, _VP, _VP, _VP, _D, _I]),
     "ch_profile_enable": (_I, [_VP, _I]),
     "ch_profile_read": (_I, [_VP, _I, _PD, _PI64]),
@@ -382,9 +385,13 @@ class Batch(_StreamMixin):
 
 
 class Interp:
-    """Coarse stretched-z velocity -> fine uniform faces (multiple resolution)."""
+    """Coarse stretched-z velocity -> fine uniform faces (multiple resolution),
+    and fine C -> coarse cell centres.  With solenoidal=True the velocity is
+    transferred through its normal gradients and integrated from reference
+    planes (ch_interp_set_solenoidal)."""
 
-    def __init__(self, fine_shape, h, coarse_shape, zf, precision="fp64", stream=None):
+    def __init__(self, fine_shape, h, coarse_shape, zf, precision="fp64", stream=None,
+                 solenoidal=False):
         nz, ny, nx = fine_shape
         ncz, ncy, ncx = coarse_shape
         self.fine_shape = tuple(fine_shape)
@@ -402,6 +409,18 @@ class Interp:
         self.stream = stream
         _check(lib().ch_interp_set_stream(self._h,
                                           ctypes.c_void_p(stream.cuda_stream if stream else 0)))
+        if solenoidal:
+            self.set_solenoidal(True)
+
+    def set_solenoidal(self, on):
+        _check(lib().ch_interp_set_solenoidal(self._h, 1 if on else 0))
+
+    def closure(self):
+        """Largest |closure sum| of the x, y and z lines of the last solenoidal
+        transfer (waits for the handle's stream)."""
+        out = (ctypes.c_double * 3)()
+        _check(lib().ch_interp_closure(self._h, out))
+        return tuple(out)
 
     def _coarse_ptrs(self, uc, vc, wc):
         ncz, ncy, ncx = self.coarse_shape
@@ -409,19 +428,36 @@ class Interp:
                 _dev_tensor(vc, self.dtype, (ncz, ncy, ncx), "vc"),
                 _dev_tensor(wc, self.dtype, (ncz + 1, ncy, ncx), "wc"))
 
-    def apply(self, uc, vc, wc):
+    def apply(self, uc, vc, wc, out=None):
+        """Fine (u, v, w); `out` may hold three preallocated tensors."""
         nz, ny, nx = self.fine_shape
-        u = torch.empty((nz, ny, nx), dtype=self.dtype, device="cuda")
-        v = torch.empty((nz, ny, nx), dtype=self.dtype, device="cuda")
-        w = torch.empty((nz + 1, ny, nx), dtype=self.dtype, device="cuda")
+        if out is None:
+            out = (torch.empty((nz, ny, nx), dtype=self.dtype, device="cuda"),
+                   torch.empty((nz, ny, nx), dtype=self.dtype, device="cuda"),
+                   torch.empty((nz + 1, ny, nx), dtype=self.dtype, device="cuda"))
+        u, v, w = out
+        ptrs = (_dev_tensor(u, self.dtype, (nz, ny, nx), "u"),
+                _dev_tensor(v, self.dtype, (nz, ny, nx), "v"),
+                _dev_tensor(w, self.dtype, (nz + 1, ny, nx), "w"))
         if self.stream is not None:
             self.stream.wait_stream(torch.cuda.current_stream())
-        _check(lib().ch_interp_apply(self._h, *self._coarse_ptrs(uc, vc, wc),
-                                     ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(v.data_ptr()),
-                                     ctypes.c_void_p(w.data_ptr())))
+        _check(lib().ch_interp_apply(self._h, *self._coarse_ptrs(uc, vc, wc), *ptrs))
         if self.stream is not None:
             torch.cuda.current_stream().wait_stream(self.stream)
         return u, v, w
+
+    def project_c(self, Cf, out=None):
+        """Fine cell-centred C (nz, ny, nx) -> coarse cell centres (ncz, ncy, ncx)."""
+        if out is None:
+            out = torch.empty(self.coarse_shape, dtype=self.dtype, device="cuda")
+        src = _dev_tensor(Cf, self.dtype, self.fine_shape, "Cf")
+        dst = _dev_tensor(out, self.dtype, self.coarse_shape, "Cc")
+        if self.stream is not None:
+            self.stream.wait_stream(torch.cuda.current_stream())
+        _check(lib().ch_interp_project_c(self._h, src, dst))
+        if self.stream is not None:
+            torch.cuda.current_stream().wait_stream(self.stream)
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

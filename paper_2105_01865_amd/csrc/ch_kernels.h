@@ -30,10 +30,63 @@ template <typename T>
 hipError_t launch_check_velocity(hipStream_t st, const chd::BoxDesc* boxes, int nbox,
                                  const void* U, const void* V, const void* W, int* flags);
 
+// One component of the coarse-to-fine transfer.  Target rows are grouped in
+// bands of `jb` (32, 16, 8, 4, 2 or 1) consecutive y-rows; band b reads the
+// coarse rows band[2b], band[2b] + 1, ... (band[2b + 1] of them, cyclic in
+// y), and no band spans more than `rmax` rows.  Target row j's y taps are
+// given as offsets (row within its band) x sx.  With `xwin` set, the x taps
+// of every 4 consecutive targets 4t .. 4t+3 lie within the 6 cyclically
+// consecutive coarse points starting at target 4t's first tap.  Weights of
+// the y and z stencils are in the working precision.
+struct InterpArgs {
+    const void* src;        // coarse component [.][sy][sx]
+    void* dst;              // target [tnz][tny][tnx]
+    int sx, sy;
+    int64_t plane;          // sx * sy
+    int tnx, tny, tnz;
+    int jb, rmax;
+    int xwin;
+    int nwg;                // work-groups (each takes a contiguous run of items)
+    size_t lds;             // bytes of LDS per work-group (interp_lds)
+    const int* ix;          // 4 taps per target, x
+    const double* wx;
+    const int* ly;          // 4 taps per target row, y (band-local offsets)
+    const void* wy;
+    const int* iz;          // 4 taps per target plane, z
+    const void* wz;
+    const int* band;
+};
+
+// LDS of one transfer work-group: rmax coarse rows and jb target rows
+constexpr size_t interp_lds(int rmax, int jb, int sx, size_t esize)
+{
+    return (size_t)(rmax + jb) * sx * esize;
+}
+
 template <typename T>
-hipError_t launch_interp(hipStream_t st, const void* src, int64_t sx, int64_t sy, int64_t tnx,
-                         int64_t tny, int64_t tnz, const int* ix, const double* wx,
-                         const int* iy, const double* wy, const int* iz, const double* wz,
-                         void* dst);
+hipError_t launch_interp(hipStream_t st, const InterpArgs& a);
+
+// Solenoidal transfer: the coarse normal gradient of component comp (0 u
+// along x, 1 v along y, 2 w along z) at the coarse cell centres, and the
+// in-place integration of a fine component along direction dir from its
+// reference plane ref (u: [nz][ny], v: [nz][nx]; w starts from 0 on the
+// bottom wall and the top wall plane is set to 0).  Each scan work-group
+// writes its largest |closure| to part[group]; scan_groups gives how many.
+constexpr int SCAN_WG = 1024;
+constexpr int scan_groups(int dir, int nx, int ny, int nz)
+{
+    const int64_t work = dir == 0 ? ((int64_t)ny * nz + 3) / 4
+                       : dir == 1 ? ((int64_t)nz * nx + 255) / 256
+                                  : ((int64_t)nx * ny + 255) / 256;
+    return (int)(work < SCAN_WG ? (work > 0 ? work : 1) : SCAN_WG);
+}
+
+template <typename T>
+hipError_t launch_grad(hipStream_t st, const void* src, int comp, int sx, int sy, int sz,
+                       const double* dzinv, void* out);
+
+template <typename T>
+hipError_t launch_scan(hipStream_t st, int dir, void* buf, const void* ref, int nx, int ny,
+                       int nz, double h, double* part);
 
 }  // namespace chk

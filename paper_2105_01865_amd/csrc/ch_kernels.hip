@@ -161,43 +161,305 @@ k_check_velocity(const chd::BoxDesc* __restrict__ boxes, int nbox, const T* __re
     }
 }
 
-// Coarse-to-fine velocity transfer, one target x-row per work-group and
-// iteration: the 4 x 4 source rows of the row's z and y stencils are first
-// combined into one coarse row in LDS (16 taps per coarse x point, coalesced
-// reads), then every target point takes its 4-point x stencil from LDS.
-// Exactly the separable tensor-product interpolation, summed z-y first.
-template <typename T>
+// Coarse-to-fine velocity transfer, the separable tensor-product
+// interpolation of sec. 3.4.  Work item = (target plane k, band of JB target
+// rows); each work-group takes a contiguous run of items (XCD-contiguous
+// runs, so that an L2 sees neighbouring planes):
+//   A. the band's coarse rows, each combined over the 4 source planes of k's
+//      z stencil, into LDS (coalesced along x; MA rows' loads in flight per
+//      thread, through buffer resources on the 4 planes);
+//   B. each target row of the band combines 4 of those rows (its y stencil)
+//      into a second LDS row;
+//   C. x stencil.  With the 6-point window property each thread owns 4
+//      consecutive targets: it reads the 6 window points once and applies a
+//      4 x 6 weight matrix built at start-up (4-wide stores); otherwise every
+//      target reads its 4 taps.
+// Band, z and y stencil entries are uniform per item and row, so they are
+// read into scalar registers.  Every target element is written once; the
+// coarse data is read through the caches about (rows per band / band height)
+// times per target plane.
+template <typename T, int JB, int MA>
 __global__ void __launch_bounds__(256)
-k_interp(const T* __restrict__ src, int64_t sx, int64_t sy, int64_t tnx, int64_t tny,
-         int64_t tnz, const int* __restrict__ ix, const double* __restrict__ wx,
-         const int* __restrict__ iy, const double* __restrict__ wy,
-         const int* __restrict__ iz, const double* __restrict__ wz, T* __restrict__ dst)
+k_interp(InterpArgs a, const T* __restrict__ src, T* __restrict__ dst,
+         const int* __restrict__ band, const int* __restrict__ izt, const T* __restrict__ wzt,
+         const int* __restrict__ lyt, const T* __restrict__ wyt, const int* __restrict__ ixt,
+         const double* __restrict__ wxt)
 {
+    typedef T T4 __attribute__((ext_vector_type(4)));
+    constexpr int XQ = 4, NW = 6;
     extern __shared__ __align__(16) unsigned char smem[];
-    T* row = reinterpret_cast<T*>(smem);
-    const int64_t nrows = tny * tnz;
-    for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
-        const int64_t j = r % tny, k = r / tny;
-        __syncthreads();   // the previous row's readers are done with `row`
-        for (int64_t cx = threadIdx.x; cx < sx; cx += blockDim.x) {
-            T acc = T(0);
-            for (int c = 0; c < 4; ++c) {
-                const T* plane = src + (int64_t)iz[4 * k + c] * sy * sx + cx;
-                T accy = T(0);
-                for (int b = 0; b < 4; ++b)
-                    accy += T(wy[4 * j + b]) * plane[(int64_t)iy[4 * j + b] * sx];
-                acc += T(wz[4 * k + c]) * accy;
+    const int sx = a.sx;
+    T* zr = reinterpret_cast<T*>(smem);           // rmax x sx
+    T* yr = zr + (size_t)a.rmax * sx;             // JB x sx
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int nb = (a.tny + JB - 1) / JB;
+    const int items = nb * a.tnz;
+    const uint32_t pbytes = (uint32_t)(a.plane * sizeof(T));
+
+    // x: thread -> targets xi0 .. xi0 + 3 of rows jj = rg0 (mod rgs)
+    const int tc = (a.tnx + XQ - 1) / XQ;
+    const bool win = a.xwin && tc <= nt;
+    const int rgs = win ? nt / tc : 1;
+    const int rg0 = win ? tid / tc : 0;
+    const int xi0 = win ? XQ * (tid - rg0 * tc) : 0;
+    const bool xact = win && rg0 < rgs;
+    const bool vec = (a.tnx % XQ) == 0 && (reinterpret_cast<uintptr_t>(dst) % sizeof(T4)) == 0;
+    int ws = 0;
+    if (xact) ws = ixt[4 * xi0];
+    int woff[NW];   // window points ws .. ws + NW - 1, cyclic in x
+#pragma unroll
+    for (int n = 0; n < NW; ++n) woff[n] = ws + n < sx ? ws + n : (ws + n) % sx;
+    T M[XQ][NW];
+#pragma unroll
+    for (int q = 0; q < XQ; ++q)
+#pragma unroll
+        for (int n = 0; n < NW; ++n) M[q][n] = T(0);
+    if (xact) {
+#pragma unroll
+        for (int q = 0; q < XQ; ++q)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bool ok = xi0 + q < a.tnx;
+                int d = ok ? ixt[4 * (xi0 + q) + t] - ws : 0;
+                if (d < 0) d += sx;
+                const T w = ok ? T(wxt[4 * (xi0 + q) + t]) : T(0);
+#pragma unroll
+                for (int n = 0; n < NW; ++n) M[q][n] += d == n ? w : T(0);
             }
-            row[cx] = acc;
+    }
+
+    const int per = (items + a.nwg - 1) / a.nwg;
+    const int it0 = xcd_task(blockIdx.x, a.nwg) * per;
+    const int it1 = it0 + per < items ? it0 + per : items;
+    for (int item = it0; item < it1; ++item) {
+        const int k = item / nb, b = item - k * nb;
+        const int j0 = b * JB;
+        const int nj = a.tny - j0 < JB ? a.tny - j0 : JB;
+        const int base = band[2 * b], span = band[2 * b + 1];
+        __syncthreads();   // the previous item's readers are done with the LDS
+        // A: coarse rows base .. base + span - 1 (cyclic), z stencil applied
+        {
+            const chd::PlaneRef<T> p0(src + (int64_t)izt[4 * k] * a.plane, pbytes);
+            const chd::PlaneRef<T> p1(src + (int64_t)izt[4 * k + 1] * a.plane, pbytes);
+            const chd::PlaneRef<T> p2(src + (int64_t)izt[4 * k + 2] * a.plane, pbytes);
+            const chd::PlaneRef<T> p3(src + (int64_t)izt[4 * k + 3] * a.plane, pbytes);
+            const T w0 = wzt[4 * k], w1 = wzt[4 * k + 1], w2 = wzt[4 * k + 2], w3 = wzt[4 * k + 3];
+            for (int r0 = 0; r0 < span; r0 += MA)
+                for (int cx = tid; cx < sx; cx += nt) {
+                    T v[MA][4];
+#pragma unroll
+                    for (int m = 0; m < MA; ++m) {
+                        int rr = base + r0 + m;
+                        if (rr >= a.sy) rr -= a.sy;
+                        const uint32_t boff =
+                            (uint32_t)((r0 + m < span ? rr * sx + cx : cx) * (int)sizeof(T));
+                        v[m][0] = p0(boff);
+                        v[m][1] = p1(boff);
+                        v[m][2] = p2(boff);
+                        v[m][3] = p3(boff);
+                    }
+#pragma unroll
+                    for (int m = 0; m < MA; ++m)
+                        if (r0 + m < span)
+                            zr[(r0 + m) * sx + cx] =
+                                ((w0 * v[m][0] + w1 * v[m][1]) + w2 * v[m][2]) + w3 * v[m][3];
+                }
         }
         __syncthreads();
-        T* out = dst + r * tnx;
-        for (int64_t i = threadIdx.x; i < tnx; i += blockDim.x) {
-            T acc = T(0);
-            for (int a = 0; a < 4; ++a) acc += T(wx[4 * i + a]) * row[ix[4 * i + a]];
-            out[i] = acc;
+        // B: the band's target rows, y stencil applied
+        for (int cx = tid; cx < sx; cx += nt) {
+#pragma unroll
+            for (int jj = 0; jj < JB; ++jj) {
+                if (jj < nj) {
+                    const int* l = lyt + 4 * (j0 + jj);
+                    const T* y = wyt + 4 * (j0 + jj);
+                    yr[jj * sx + cx] = ((y[0] * zr[l[0] + cx] + y[1] * zr[l[1] + cx])
+                                        + y[2] * zr[l[2] + cx]) + y[3] * zr[l[3] + cx];
+                }
+            }
+        }
+        __syncthreads();
+        // C: x stencil, every target point written once
+        T* out = dst + ((int64_t)k * a.tny + j0) * a.tnx;
+        if (win) {
+            if (xact)
+                for (int jj = rg0; jj < nj; jj += rgs) {
+                    const T* row = yr + jj * sx;
+                    T p[NW];
+#pragma unroll
+                    for (int n = 0; n < NW; ++n) p[n] = row[woff[n]];
+                    T y[XQ];
+#pragma unroll
+                    for (int q = 0; q < XQ; ++q) {
+                        T acc = M[q][0] * p[0];
+#pragma unroll
+                        for (int n = 1; n < NW; ++n) acc += M[q][n] * p[n];
+                        y[q] = acc;
+                    }
+                    T* o = out + (int64_t)jj * a.tnx + xi0;
+                    if (vec) {
+                        *reinterpret_cast<T4*>(o) = T4{y[0], y[1], y[2], y[3]};
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < XQ; ++q)
+                            if (xi0 + q < a.tnx) o[q] = y[q];
+                    }
+                }
+        } else {
+            for (int jj = 0; jj < nj; ++jj)
+                for (int i = tid; i < a.tnx; i += nt) {
+                    const T* row = yr + jj * sx;
+                    T acc = T(0);
+                    for (int t = 0; t < 4; ++t) acc += T(wxt[4 * i + t]) * row[ixt[4 * i + t]];
+                    out[(int64_t)jj * a.tnx + i] = acc;
+                }
         }
     }
+}
+
+// Solenoidal transfer, pieces other than the interpolation itself.
+//
+// Coarse normal gradient at the coarse cell centres, one row (k, j) per
+// work-group: comp 0 differences u along x, 1 differences v along y, 2
+// differences w along z (sz + 1 planes of w, cell heights 1 / dzinv[k]).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_grad(const T* __restrict__ src, int comp, int sx, int sy, int sz,
+       const double* __restrict__ dzinv, T* __restrict__ out)
+{
+    const int64_t plane = (int64_t)sx * sy;
+    for (int64_t row = blockIdx.x; row < (int64_t)sy * sz; row += gridDim.x) {
+        const int k = (int)(row / sy), j = (int)(row - (int64_t)k * sy);
+        const T* p = src + row * sx;
+        T* o = out + row * sx;
+        if (comp == 0) {
+            for (int i = threadIdx.x; i < sx; i += blockDim.x)
+                o[i] = (p[i + 1 < sx ? i + 1 : 0] - p[i]) * T(sx);
+        } else if (comp == 1) {
+            const T* q = src + ((int64_t)k * sy + (j + 1 < sy ? j + 1 : 0)) * sx;
+            for (int i = threadIdx.x; i < sx; i += blockDim.x) o[i] = (q[i] - p[i]) * T(sy);
+        } else {
+            const T s = T(dzinv[k]);
+            for (int i = threadIdx.x; i < sx; i += blockDim.x) o[i] = (p[i + plane] - p[i]) * s;
+        }
+    }
+}
+
+// Largest closure magnitude of a work-group into part[blockIdx.x].
+__device__ __forceinline__ void group_max(double v, double* __restrict__ part)
+{
+    __shared__ double red[4];
+    for (int d = 32; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+        part[blockIdx.x] = m;
+    }
+}
+
+// Integration along x, one wavefront per row (in place): the row holds the
+// interpolated gradient at the fine cell centres on entry and
+//   u[i] = ref[row] + h sum_{i' < i} G[i']
+// on exit (64 points per wave-wide scan).  The |h sum G| of the whole row is
+// the closure left at the periodic seam.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_scan_x(T* __restrict__ buf, const T* __restrict__ ref, int nx, int64_t nrows, T h,
+         double* __restrict__ part)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double mx = 0.0;
+    for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < nrows; row += (int64_t)gridDim.x * 4) {
+        T* p = buf + row * nx;
+        const T r = ref[row];
+        T acc = T(0);
+        for (int i0 = 0; i0 < nx; i0 += 64) {
+            const int i = i0 + lane;
+            const T g = i < nx ? p[i] : T(0);
+            T s = g;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const T t = __shfl_up(s, d);
+                if (lane >= d) s += t;
+            }
+            if (i < nx) p[i] = r + h * (acc + (s - g));
+            acc += __shfl(s, 63);
+        }
+        mx = fmax(mx, (double)fabs(h * acc));
+    }
+    group_max(mx, part);
+}
+
+// Integration along y (in place), one thread per (k, i) column:
+//   v[j] = ref[k][i] + h sum_{j' < j} G[j'].
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_scan_y(T* __restrict__ buf, const T* __restrict__ ref, int nx, int ny, int nz, T h,
+         double* __restrict__ part)
+{
+    double mx = 0.0;
+    const int64_t ncol = (int64_t)nz * nx;
+    for (int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; col < ncol;
+         col += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = col / nx, i = col - k * nx;
+        T* p = buf + k * ny * nx + i;
+        const T r = ref[col];
+        T acc = T(0);
+        int j = 0;
+        for (; j + 8 <= ny; j += 8) {
+            T g[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) g[q] = p[(int64_t)(j + q) * nx];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                p[(int64_t)(j + q) * nx] = r + h * acc;
+                acc += g[q];
+            }
+        }
+        for (; j < ny; ++j) {
+            const T g = p[(int64_t)j * nx];
+            p[(int64_t)j * nx] = r + h * acc;
+            acc += g;
+        }
+        mx = fmax(mx, (double)fabs(h * acc));
+    }
+    group_max(mx, part);
+}
+
+// Integration along z (in place), one thread per (j, i) column: planes
+// 0 .. nz-1 hold G on entry; w[k] = h sum_{k' < k} G[k'] (w = 0 on the
+// bottom wall) and the top wall plane nz is set to 0.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_scan_z(T* __restrict__ buf, int64_t plane, int nz, T h, double* __restrict__ part)
+{
+    double mx = 0.0;
+    for (int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; col < plane;
+         col += (int64_t)gridDim.x * blockDim.x) {
+        T* p = buf + col;
+        T acc = T(0);
+        int k = 0;
+        for (; k + 8 <= nz; k += 8) {
+            T g[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) g[q] = p[(int64_t)(k + q) * plane];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                p[(int64_t)(k + q) * plane] = h * acc;
+                acc += g[q];
+            }
+        }
+        for (; k < nz; ++k) {
+            const T g = p[(int64_t)k * plane];
+            p[(int64_t)k * plane] = h * acc;
+            acc += g;
+        }
+        p[(int64_t)nz * plane] = T(0);
+        mx = fmax(mx, (double)fabs(h * acc));
+    }
+    group_max(mx, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -292,16 +554,61 @@ hipError_t launch_check_velocity(hipStream_t st, const chd::BoxDesc* boxes, int 
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_interp(hipStream_t st, const void* src, int64_t sx, int64_t sy, int64_t tnx,
-                         int64_t tny, int64_t tnz, const int* ix, const double* wx,
-                         const int* iy, const double* wy, const int* iz, const double* wz,
-                         void* dst)
+template <typename T, int JB>
+static hipError_t launch_interp_jb(hipStream_t st, const InterpArgs& a)
 {
-    const int64_t rows = tny * tnz;
+    constexpr int MA = sizeof(T) == 4 ? 8 : 6;    // rows of loads in flight
+    if (a.lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)&k_interp<T, JB, MA>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)a.lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_interp<T, JB, MA>), dim3((unsigned)a.nwg), dim3(256), a.lds, st, a,
+                       (const T*)a.src, (T*)a.dst, a.band, a.iz, (const T*)a.wz, a.ly,
+                       (const T*)a.wy, a.ix, a.wx);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_interp(hipStream_t st, const InterpArgs& a)
+{
+    switch (a.jb) {
+    case 32: return launch_interp_jb<T, 32>(st, a);
+    case 16: return launch_interp_jb<T, 16>(st, a);
+    case 8: return launch_interp_jb<T, 8>(st, a);
+    case 4: return launch_interp_jb<T, 4>(st, a);
+    case 2: return launch_interp_jb<T, 2>(st, a);
+    case 1: return launch_interp_jb<T, 1>(st, a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_grad(hipStream_t st, const void* src, int comp, int sx, int sy, int sz,
+                       const double* dzinv, void* out)
+{
+    const int64_t rows = (int64_t)sy * sz;
     const int64_t nwg = rows < 262144 ? rows : 262144;
-    hipLaunchKernelGGL((k_interp<T>), dim3((unsigned)nwg), dim3(256), (size_t)sx * sizeof(T), st,
-                       (const T*)src, sx, sy, tnx, tny, tnz, ix, wx, iy, wy, iz, wz, (T*)dst);
+    hipLaunchKernelGGL((k_grad<T>), dim3((unsigned)nwg), dim3(256), 0, st, (const T*)src, comp,
+                       sx, sy, sz, dzinv, (T*)out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scan(hipStream_t st, int dir, void* buf, const void* ref, int nx, int ny,
+                       int nz, double h, double* part)
+{
+    const int nwg = scan_groups(dir, nx, ny, nz);
+    if (dir == 0)
+        hipLaunchKernelGGL((k_scan_x<T>), dim3(nwg), dim3(256), 0, st, (T*)buf, (const T*)ref,
+                           nx, (int64_t)ny * nz, T(h), part);
+    else if (dir == 1)
+        hipLaunchKernelGGL((k_scan_y<T>), dim3(nwg), dim3(256), 0, st, (T*)buf, (const T*)ref,
+                           nx, ny, nz, T(h), part);
+    else
+        hipLaunchKernelGGL((k_scan_z<T>), dim3(nwg), dim3(256), 0, st, (T*)buf,
+                           (int64_t)nx * ny, nz, T(h), part);
     return hipGetLastError();
 }
 
@@ -326,13 +633,15 @@ template hipError_t launch_check_velocity<double>(hipStream_t, const chd::BoxDes
                                                   const void*, const void*, const void*, int*);
 template hipError_t launch_check_velocity<float>(hipStream_t, const chd::BoxDesc*, int,
                                                  const void*, const void*, const void*, int*);
-template hipError_t launch_interp<double>(hipStream_t, const void*, int64_t, int64_t, int64_t,
-                                          int64_t, int64_t, const int*, const double*,
-                                          const int*, const double*, const int*, const double*,
-                                          void*);
-template hipError_t launch_interp<float>(hipStream_t, const void*, int64_t, int64_t, int64_t,
-                                         int64_t, int64_t, const int*, const double*,
-                                         const int*, const double*, const int*, const double*,
-                                         void*);
+template hipError_t launch_interp<double>(hipStream_t, const InterpArgs&);
+template hipError_t launch_interp<float>(hipStream_t, const InterpArgs&);
+template hipError_t launch_grad<double>(hipStream_t, const void*, int, int, int, int,
+                                        const double*, void*);
+template hipError_t launch_grad<float>(hipStream_t, const void*, int, int, int, int,
+                                       const double*, void*);
+template hipError_t launch_scan<double>(hipStream_t, int, void*, const void*, int, int, int,
+                                        double, double*);
+template hipError_t launch_scan<float>(hipStream_t, int, void*, const void*, int, int, int,
+                                       double, double*);
 
 }  // namespace chk

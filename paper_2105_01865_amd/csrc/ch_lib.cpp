@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
@@ -80,7 +81,8 @@ struct Engine {
     int device = 0;
     // graph of one step
     hipGraphExec_t gexec = nullptr;
-    const void* gkey[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // pointers and transfer handle (with its mode generation) of the captured step
+    const void* gkey[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -285,17 +287,199 @@ ch_status resolve_profile(Engine& e)
     return CH_OK;
 }
 
-// One multiple-resolution transfer descriptor.
+// One coarse-to-fine (or fine-to-coarse) tensor-product transfer: the
+// source is [.][sy][sx], the targets tn[0] x tn[1] x tn[2].
+struct Transfer {
+    int64_t sx = 0, sy = 0;
+    int64_t tn[3] = {};
+    // 1-D stencils per axis (x, y, z): 4 source indices and weights per target
+    int* idx[3] = {};
+    double* wt[3] = {};
+    // y bands: height, widest band, LDS bytes, (first row, row count) per
+    // band; y taps as band-local offsets x sx; y and z weights in the working
+    // precision; whether the x taps of targets 4t .. 4t+3 lie in 6 points
+    int jb = 0, rmax = 0, xwin = 0;
+    size_t lds = 0;
+    int* band = nullptr;
+    int* ly = nullptr;
+    void* wy = nullptr;
+    void* wz = nullptr;
+    bool ok = false;   // built (a source row too long for the LDS leaves it unbuilt)
+};
+
+// Transfers of one handle: the plain transfer of u, v, w; the fine cell
+// centres from coarse cell centres (the gradients of the solenoidal
+// transfer); its reference planes (u on x = 0, v on y = 0); C from the fine
+// to the coarse cell centres.
+enum { TR_U, TR_V, TR_W, TR_CENTRES, TR_UREF, TR_VREF, TR_C, TR_COUNT };
+
+// One multiple-resolution transfer handle.
 struct InterpData {
     int64_t nf[3];           // fine cells
     int64_t nc[3];           // coarse cells
     int prec = CH_FP64;
     hipStream_t stream = nullptr;
-    // 1-D stencils per component (u, v, w) and axis (x, y, z)
-    int* idx[3][3] = {};
-    double* wt[3][3] = {};
-    int64_t tn[3][3] = {};   // targets per component and axis
+    Transfer tr[TR_COUNT];
+    // solenoidal mode and its work buffers
+    int solenoidal = 0;
+    unsigned gen = 0;        // unique per handle and mode (graphs captured before are stale)
+    void* grad = nullptr;    // one coarse cell-centred gradient [ncz][ncy][ncx]
+    void* ref = nullptr;     // one reference plane (nz x max(nx, ny))
+    double* dzinv = nullptr; // 1 / coarse cell heights
+    double* part = nullptr;  // per-group closure maxima, 3 x chk::SCAN_WG
+    std::vector<double> zf;  // coarse z faces
 };
+
+// work-groups of one transfer launch at most (each takes a contiguous run of
+// work items)
+constexpr int64_t INTERP_MAX_WG = 2048;
+
+// source of InterpData::gen
+std::atomic<unsigned> g_interp_gen{1};
+
+void free_transfer(Transfer& t)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (t.idx[a]) (void)hipFree(t.idx[a]);
+        if (t.wt[a]) (void)hipFree(t.wt[a]);
+        t.idx[a] = nullptr;
+        t.wt[a] = nullptr;
+    }
+    void* p[4] = {t.band, t.ly, t.wy, t.wz};
+    for (void* q : p)
+        if (q) (void)hipFree(q);
+    t.band = t.ly = nullptr;
+    t.wy = t.wz = nullptr;
+    t.ok = false;
+}
+
+void free_solenoidal(InterpData& d)
+{
+    void* p[4] = {d.grad, d.ref, d.dzinv, d.part};
+    for (void* q : p)
+        if (q) (void)hipFree(q);
+    d.grad = d.ref = nullptr;
+    d.dzinv = d.part = nullptr;
+}
+
+// Device copy of a host table; false on failure.
+bool upload(void** dptr, const void* data, size_t bytes)
+{
+    if (hipMalloc(dptr, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *dptr = nullptr;
+        return false;
+    }
+    return hipMemcpy(*dptr, data, bytes, hipMemcpyHostToDevice) == hipSuccess;
+}
+
+// Device copy of stencil weights in the working precision; false on failure.
+bool upload_weights(void** dptr, const std::vector<double>& w, int precision)
+{
+    if (precision == CH_FP64) return upload(dptr, w.data(), sizeof(double) * w.size());
+    std::vector<float> f(w.begin(), w.end());
+    return upload(dptr, f.data(), sizeof(float) * f.size());
+}
+
+// LDS per work-group the band height is chosen for (three groups per CU in
+// single precision, two in double: what their registers allow), and the most
+// one group may take
+constexpr size_t interp_lds_target(size_t esize) { return esize == 4 ? 54528 : 81920; }
+constexpr size_t INTERP_LDS_MAX = 163840;
+
+// Band table for one y stencil (4 taps per target row, rows cyclic in sy):
+// band b starts at its first row's first tap and spans up to its farthest
+// tap.  The band height is the largest of 32, 16, ..., 1 (no larger than the
+// row count needs) whose LDS fits interp_lds_target, else 1; false when even
+// that exceeds INTERP_LDS_MAX.
+bool interp_bands(const std::vector<int>& iy, int64_t tny, int sx, int sy, size_t esize,
+                  int* jb_out, int* rmax_out, size_t* lds_out, std::vector<int>* band)
+{
+    int jb0 = 32;
+    while (jb0 > 1 && jb0 / 2 >= tny) jb0 /= 2;
+    for (int jb = jb0; jb >= 1; jb /= 2) {
+        const int64_t nb = (tny + jb - 1) / jb;
+        std::vector<int> t(2 * nb);
+        int rmax = 1;
+        for (int64_t b = 0; b < nb; ++b) {
+            const int base = iy[4 * b * jb];
+            int span = 1;
+            for (int64_t j = b * jb; j < std::min<int64_t>(tny, (b + 1) * jb); ++j)
+                for (int q = 0; q < 4; ++q) span = std::max(span, (iy[4 * j + q] - base + sy) % sy + 1);
+            t[2 * b] = base;
+            t[2 * b + 1] = span;
+            rmax = std::max(rmax, span);
+        }
+        const size_t lds = chk::interp_lds(rmax, jb, sx, esize);
+        if (lds > interp_lds_target(esize) && jb > 1) continue;
+        if (lds > INTERP_LDS_MAX) return false;
+        *band = std::move(t);
+        *jb_out = jb;
+        *rmax_out = rmax;
+        *lds_out = lds;
+        return true;
+    }
+    return false;
+}
+
+// Whether the x taps of every 4 consecutive targets 4t .. 4t+3 lie within
+// the 6 cyclically consecutive source points from target 4t's first tap.
+bool interp_xwin(const std::vector<int>& ix, int64_t tnx, int sx)
+{
+    for (int64_t i0 = 0; i0 < tnx; i0 += 4) {
+        const int ws = ix[4 * i0];
+        for (int64_t i = i0; i < std::min<int64_t>(tnx, i0 + 4); ++i)
+            for (int q = 0; q < 4; ++q)
+                if ((ix[4 * i + q] - ws + sx) % sx >= 6) return false;
+    }
+    return true;
+}
+
+template <typename T>
+hipError_t launch_transfer(const Transfer& t, hipStream_t st, const void* src, void* dst)
+{
+    if (!t.ok) return hipErrorInvalidValue;
+    chk::InterpArgs ia;
+    ia.src = src;
+    ia.dst = dst;
+    ia.sx = (int)t.sx;
+    ia.sy = (int)t.sy;
+    ia.plane = t.sx * t.sy;
+    ia.tnx = (int)t.tn[0];
+    ia.tny = (int)t.tn[1];
+    ia.tnz = (int)t.tn[2];
+    ia.jb = t.jb;
+    ia.rmax = t.rmax;
+    ia.xwin = t.xwin;
+    ia.nwg = (int)std::min<int64_t>((t.tn[1] + t.jb - 1) / t.jb * t.tn[2], INTERP_MAX_WG);
+    ia.lds = t.lds;
+    ia.ix = t.idx[0];
+    ia.wx = t.wt[0];
+    ia.ly = t.ly;
+    ia.wy = t.wy;
+    ia.iz = t.idx[2];
+    ia.wz = t.wz;
+    ia.band = t.band;
+    return chk::launch_interp<T>(st, ia);
+}
+
+// One component of the solenoidal transfer: its coarse normal gradient, that
+// gradient at the fine cell centres (written into the component's fine
+// array), then the integration from the reference plane in place.
+template <typename T>
+hipError_t solenoidal_component(InterpData* ip, hipStream_t st, int c, const void* src, void* dst)
+{
+    const int nx = (int)ip->nf[0], ny = (int)ip->nf[1], nz = (int)ip->nf[2];
+    hipError_t err = chk::launch_grad<T>(st, src, c, (int)ip->nc[0], (int)ip->nc[1],
+                                         (int)ip->nc[2], ip->dzinv, ip->grad);
+    if (err == hipSuccess) err = launch_transfer<T>(ip->tr[TR_CENTRES], st, ip->grad, dst);
+    if (err == hipSuccess && c < 2)
+        err = launch_transfer<T>(ip->tr[c == 0 ? TR_UREF : TR_VREF], st, src, ip->ref);
+    if (err == hipSuccess)
+        err = chk::launch_scan<T>(st, c, dst, ip->ref, nx, ny, nz, 1.0 / ip->nf[c],
+                                  ip->part + c * chk::SCAN_WG);
+    return err;
+}
 
 template <typename T>
 hipError_t interp_components(InterpData* ip, hipStream_t st, const void* uc, const void* vc,
@@ -310,11 +494,9 @@ hipError_t interp_components(InterpData* ip, hipStream_t st, const void* uc, con
             b = take_event(*prof_e);
             if (a) (void)hipEventRecord(a, st);
         }
-        const int64_t sx = ip->nc[0], sy = ip->nc[1];
-        hipError_t err = chk::launch_interp<T>(st, src[c], sx, sy, ip->tn[c][0], ip->tn[c][1],
-                                               ip->tn[c][2], ip->idx[c][0], ip->wt[c][0],
-                                               ip->idx[c][1], ip->wt[c][1], ip->idx[c][2],
-                                               ip->wt[c][2], dst[c]);
+        hipError_t err = ip->solenoidal
+            ? solenoidal_component<T>(ip, st, c, src[c], dst[c])
+            : launch_transfer<T>(ip->tr[c], st, src[c], dst[c]);
         if (prof_e && prof_e->prof && a && b) {
             (void)hipEventRecord(b, st);
             prof_e->ev_pending.push_back({3, {a, b}});
@@ -346,7 +528,8 @@ ch_status run_steps(Engine& e, const void* u, const void* v, const void* w, doub
         if (st != CH_OK) return st;
     }
     if (nsteps == 0) return CH_OK;
-    const void* key[6] = {u, v, w, uc, vc, wc};
+    const void* key[8] = {u, v, w, uc, vc, wc, ip,
+                          ip ? reinterpret_cast<const void*>((uintptr_t)ip->gen) : nullptr};
     const bool use_graph = e.P.opt.use_graph && e.stream != nullptr && !e.prof;
     auto body = [&]() -> hipError_t {
         if (ip) {
@@ -358,7 +541,7 @@ ch_status run_steps(Engine& e, const void* u, const void* v, const void* w, doub
     };
     if (use_graph) {
         bool same = e.gexec != nullptr;
-        for (int m = 0; m < 6 && same; ++m) same = key[m] == e.gkey[m];
+        for (int m = 0; m < 8 && same; ++m) same = key[m] == e.gkey[m];
         if (!same) {
             if (e.gexec) {
                 (void)hipGraphExecDestroy(e.gexec);
@@ -381,7 +564,7 @@ ch_status run_steps(Engine& e, const void* u, const void* v, const void* w, doub
                 e.gexec = nullptr;
                 return fail(CH_EHIP, "graph instantiate failed: %s", hipGetErrorString(err3));
             }
-            for (int m = 0; m < 6; ++m) e.gkey[m] = key[m];
+            for (int m = 0; m < 8; ++m) e.gkey[m] = key[m];
         }
         for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(e.gexec, e.stream));
     } else {
@@ -518,6 +701,49 @@ void hermite(const Src& src, double t, int idx[4], double w[4])
         idx[p] = (int)ii[p];
         w[p] = ww[p] * sgn[p];
     }
+}
+
+// Build one transfer: source axes src[3] (x, y, z) of a [.][sy][sx] array,
+// target coordinates tgt[3].  A y-row extent that does not fit the LDS
+// leaves it unbuilt (ok = false) with CH_OK; other failures return an error.
+ch_status build_transfer(Transfer& t, const Src* const src[3],
+                         const std::vector<double>* const tgt[3], int64_t sx, int64_t sy,
+                         int precision)
+{
+    t.sx = sx;
+    t.sy = sy;
+    std::vector<int> idx[3];
+    std::vector<double> wt[3];
+    for (int a = 0; a < 3; ++a) {
+        const std::vector<double>& q = *tgt[a];
+        idx[a].resize(4 * q.size());
+        wt[a].resize(4 * q.size());
+        for (size_t n = 0; n < q.size(); ++n) hermite(*src[a], q[n], &idx[a][4 * n], &wt[a][4 * n]);
+        t.tn[a] = (int64_t)q.size();
+    }
+    std::vector<int> band;
+    if (!interp_bands(idx[1], t.tn[1], (int)sx, (int)sy, precision == CH_FP64 ? 8 : 4, &t.jb,
+                      &t.rmax, &t.lds, &band))
+        return CH_OK;
+    std::vector<int> ly(idx[1].size());
+    for (size_t q = 0; q < ly.size(); ++q) {
+        const int base = band[2 * ((q / 4) / t.jb)];
+        ly[q] = (int)(((idx[1][q] - base + sy) % sy) * sx);
+    }
+    t.xwin = interp_xwin(idx[0], t.tn[0], (int)sx) ? 1 : 0;
+    bool good = true;
+    for (int a = 0; a < 3 && good; a += 2)
+        good = upload((void**)&t.idx[a], idx[a].data(), sizeof(int) * idx[a].size()) &&
+               upload((void**)&t.wt[a], wt[a].data(), sizeof(double) * wt[a].size());
+    good = good && upload((void**)&t.band, band.data(), sizeof(int) * band.size()) &&
+           upload((void**)&t.ly, ly.data(), sizeof(int) * ly.size()) &&
+           upload_weights(&t.wy, wt[1], precision) && upload_weights(&t.wz, wt[2], precision);
+    if (!good) {
+        free_transfer(t);
+        return fail(CH_ENOMEM, "cannot upload interpolation tables");
+    }
+    t.ok = true;
+    return CH_OK;
 }
 
 }  // namespace
@@ -753,81 +979,132 @@ ch_status ch_interp_create(const ch_grid* fine, int64_t ncx, int64_t ncy, int64_
         return fail(CH_EINVAL, "meshes too small");
     if ((double)ncx * ncy * (ncz + 1) >= 2147483647.0)
         return fail(CH_EINVAL, "coarse mesh too large");
-    if (ncx > 8192) return fail(CH_EUNSUPPORTED, "coarse x extent above 8192 (one row in LDS)");
+    if ((double)fine->nx * fine->ny * (fine->nz + 1) >= 2147483647.0 * 8.0 ||
+        (double)fine->ny * (fine->nz + 1) >= 2147483647.0 ||
+        (double)fine->nx * (fine->nz + 1) >= 2147483647.0)
+        return fail(CH_EINVAL, "fine mesh too large");
+    if (ncx > (precision == CH_FP64 ? 4096 : 8192))
+        return fail(CH_EUNSUPPORTED, "coarse x extent above %d (five rows in LDS)",
+                    precision == CH_FP64 ? 4096 : 8192);
     if (zf[0] != 0.0 || zf[ncz] != 1.0) return fail(CH_EINVAL, "zf must run from 0 to 1");
     for (int64_t k = 0; k < ncz; ++k)
         if (!(zf[k + 1] > zf[k])) return fail(CH_EINVAL, "zf must increase");
     ch_interp* ip = new (std::nothrow) ch_interp();
     if (!ip) return fail(CH_ENOMEM, "host allocation failed");
     InterpData& d = ip->d;
-    d.nf[0] = fine->nx;
-    d.nf[1] = fine->ny;
-    d.nf[2] = fine->nz;
+    const int64_t nx = fine->nx, ny = fine->ny, nz = fine->nz;
+    d.nf[0] = nx;
+    d.nf[1] = ny;
+    d.nf[2] = nz;
     d.nc[0] = ncx;
     d.nc[1] = ncy;
     d.nc[2] = ncz;
     d.prec = precision;
-    Src cxf{{}, SRC_PERIODIC}, cxc{{}, SRC_PERIODIC}, cyf{{}, SRC_PERIODIC},
-        cyc{{}, SRC_PERIODIC}, czc{{}, SRC_EVEN}, czf{{}, SRC_ODD};
-    for (int64_t i = 0; i < ncx; ++i) {
-        cxf.s.push_back((double)i / ncx);
-        cxc.s.push_back((i + 0.5) / ncx);
-    }
-    for (int64_t j = 0; j < ncy; ++j) {
-        cyf.s.push_back((double)j / ncy);
-        cyc.s.push_back((j + 0.5) / ncy);
-    }
+    d.gen = g_interp_gen.fetch_add(1);
+    d.zf.assign(zf, zf + ncz + 1);
+    auto pts = [](int64_t n, double off) {
+        std::vector<double> t(n);
+        for (int64_t i = 0; i < n; ++i) t[i] = (i + off) / n;
+        return t;
+    };
+    const Src cxf{pts(ncx, 0.0), SRC_PERIODIC}, cxc{pts(ncx, 0.5), SRC_PERIODIC},
+        cyf{pts(ncy, 0.0), SRC_PERIODIC}, cyc{pts(ncy, 0.5), SRC_PERIODIC};
+    Src czc{{}, SRC_EVEN}, czf{{}, SRC_ODD};
     for (int64_t k = 0; k < ncz; ++k) czc.s.push_back(0.5 * (zf[k] + zf[k + 1]));
     for (int64_t k = 0; k <= ncz; ++k) czf.s.push_back(zf[k]);
-    const int64_t nx = fine->nx, ny = fine->ny, nz = fine->nz;
-    auto faces = [](int64_t n) {
-        std::vector<double> t(n);
-        for (int64_t i = 0; i < n; ++i) t[i] = (double)i / n;
-        return t;
-    };
-    auto centres = [](int64_t n) {
-        std::vector<double> t(n);
-        for (int64_t i = 0; i < n; ++i) t[i] = (i + 0.5) / n;
-        return t;
-    };
-    std::vector<double> zfaces(nz + 1);
-    for (int64_t k = 0; k <= nz; ++k) zfaces[k] = (double)k / nz;
-    // component u: x faces, y centres, z centres; v: x centres, y faces, z
-    // centres; w: x centres, y centres, z faces
-    const Src* srcs[3][3] = {{&cxf, &cyc, &czc}, {&cxc, &cyf, &czc}, {&cxc, &cyc, &czf}};
-    const std::vector<double> tgts[3][3] = {{faces(nx), centres(ny), centres(nz)},
-                                            {centres(nx), faces(ny), centres(nz)},
-                                            {centres(nx), centres(ny), zfaces}};
+    const std::vector<double> fxf = pts(nx, 0.0), fxc = pts(nx, 0.5), fyf = pts(ny, 0.0),
+                              fyc = pts(ny, 0.5), fzc = pts(nz, 0.5), zero(1, 0.0);
+    std::vector<double> fzf(nz + 1);   // z faces including both walls
+    for (int64_t k = 0; k <= nz; ++k) fzf[k] = (double)k / nz;
+    const Src sfx{fxc, SRC_PERIODIC}, sfy{fyc, SRC_PERIODIC}, sfz{fzc, SRC_EVEN};
+    std::vector<double> ccx(cxc.s), ccy(cyc.s), ccz(czc.s);
+    // u: x faces, y and z centres; v: x centres, y faces, z centres; w: x
+    // and y centres, z faces; then the solenoidal transfer's pieces and the
+    // projection of C
+    const Src* srcs[TR_COUNT][3] = {{&cxf, &cyc, &czc}, {&cxc, &cyf, &czc}, {&cxc, &cyc, &czf},
+                                    {&cxc, &cyc, &czc}, {&cxf, &cyc, &czc}, {&cxc, &cyf, &czc},
+                                    {&sfx, &sfy, &sfz}};
+    const std::vector<double>* tgts[TR_COUNT][3] = {
+        {&fxf, &fyc, &fzc}, {&fxc, &fyf, &fzc}, {&fxc, &fyc, &fzf}, {&fxc, &fyc, &fzc},
+        {&zero, &fyc, &fzc}, {&fxc, &zero, &fzc}, {&ccx, &ccy, &ccz}};
     ch_status st = CH_OK;
-    for (int c = 0; c < 3 && st == CH_OK; ++c)
-        for (int a = 0; a < 3 && st == CH_OK; ++a) {
-            const std::vector<double>& t = tgts[c][a];
-            std::vector<int> idx(4 * t.size());
-            std::vector<double> wt(4 * t.size());
-            for (size_t q = 0; q < t.size(); ++q) hermite(*srcs[c][a], t[q], &idx[4 * q], &wt[4 * q]);
-            d.tn[c][a] = (int64_t)t.size();
-            if (hipMalloc(&d.idx[c][a], sizeof(int) * idx.size()) != hipSuccess ||
-                hipMalloc(&d.wt[c][a], sizeof(double) * wt.size()) != hipSuccess) {
-                st = fail(CH_ENOMEM, "cannot allocate interpolation tables");
-                break;
-            }
-            if (hipMemcpy(d.idx[c][a], idx.data(), sizeof(int) * idx.size(),
-                          hipMemcpyHostToDevice) != hipSuccess ||
-                hipMemcpy(d.wt[c][a], wt.data(), sizeof(double) * wt.size(),
-                          hipMemcpyHostToDevice) != hipSuccess)
-                st = fail(CH_EHIP, "cannot upload interpolation tables");
-        }
+    for (int c = 0; c < TR_COUNT && st == CH_OK; ++c) {
+        const bool fine_src = c == TR_C;
+        st = build_transfer(d.tr[c], srcs[c], tgts[c], fine_src ? nx : ncx, fine_src ? ny : ncy,
+                            precision);
+        if (st == CH_OK && !d.tr[c].ok && c != TR_C)
+            st = fail(CH_EUNSUPPORTED, "coarse x extent too long for the transfer's LDS rows");
+    }
     if (st != CH_OK) {
-        for (int c = 0; c < 3; ++c)
-            for (int a = 0; a < 3; ++a) {
-                if (d.idx[c][a]) (void)hipFree(d.idx[c][a]);
-                if (d.wt[c][a]) (void)hipFree(d.wt[c][a]);
-            }
+        for (int c = 0; c < TR_COUNT; ++c) free_transfer(d.tr[c]);
         delete ip;
         return st;
     }
     reg(ip);
     *out = ip;
+    return CH_OK;
+}
+
+ch_status ch_interp_set_solenoidal(ch_interp* ip, int on)
+{
+    CHECK_STATE(ip);
+    InterpData& d = ip->d;
+    if ((on != 0) == (d.solenoidal != 0)) return CH_OK;
+    if (d.stream) HIP_TRY(hipStreamSynchronize(d.stream));
+    else HIP_TRY(hipDeviceSynchronize());
+    d.gen = g_interp_gen.fetch_add(1);
+    if (!on) {
+        free_solenoidal(d);
+        d.solenoidal = 0;
+        return CH_OK;
+    }
+    const size_t es = d.prec == CH_FP64 ? 8 : 4;
+    const size_t ncell = (size_t)d.nc[0] * d.nc[1] * d.nc[2];
+    const size_t nref = (size_t)d.nf[2] * std::max(d.nf[0], d.nf[1]);
+    std::vector<double> dzinv(d.nc[2]);
+    for (int64_t k = 0; k < d.nc[2]; ++k) dzinv[k] = 1.0 / (d.zf[k + 1] - d.zf[k]);
+    const std::vector<double> zeros(3 * chk::SCAN_WG, 0.0);
+    const bool good = hipMalloc(&d.grad, ncell * es) == hipSuccess &&
+                      hipMalloc(&d.ref, nref * es) == hipSuccess &&
+                      upload((void**)&d.dzinv, dzinv.data(), sizeof(double) * dzinv.size()) &&
+                      upload((void**)&d.part, zeros.data(), sizeof(double) * zeros.size());
+    if (!good) {
+        (void)hipGetLastError();
+        free_solenoidal(d);
+        return fail(CH_ENOMEM, "cannot allocate the solenoidal transfer's buffers");
+    }
+    d.solenoidal = 1;
+    return CH_OK;
+}
+
+ch_status ch_interp_closure(ch_interp* ip, double out[3])
+{
+    CHECK_STATE(ip);
+    if (!out) return fail(CH_EINVAL, "null output");
+    InterpData& d = ip->d;
+    out[0] = out[1] = out[2] = 0.0;
+    if (!d.solenoidal) return CH_OK;
+    if (d.stream) HIP_TRY(hipStreamSynchronize(d.stream));
+    else HIP_TRY(hipDeviceSynchronize());
+    std::vector<double> part(3 * chk::SCAN_WG);
+    HIP_TRY(hipMemcpy(part.data(), d.part, sizeof(double) * part.size(), hipMemcpyDeviceToHost));
+    for (int c = 0; c < 3; ++c) {
+        const int g = chk::scan_groups(c, (int)d.nf[0], (int)d.nf[1], (int)d.nf[2]);
+        for (int q = 0; q < g; ++q) out[c] = std::max(out[c], part[c * chk::SCAN_WG + q]);
+    }
+    return CH_OK;
+}
+
+ch_status ch_interp_project_c(ch_interp* ip, const void* Cf, void* Cc)
+{
+    CHECK_STATE(ip);
+    if (!Cf || !Cc) return fail(CH_EINVAL, "null pointer");
+    InterpData& d = ip->d;
+    if (!d.tr[TR_C].ok)
+        return fail(CH_EUNSUPPORTED, "fine x extent too long for the projection's LDS rows");
+    hipError_t err = d.prec == CH_FP64 ? launch_transfer<double>(d.tr[TR_C], d.stream, Cf, Cc)
+                                       : launch_transfer<float>(d.tr[TR_C], d.stream, Cf, Cc);
+    if (err != hipSuccess) return fail(CH_EHIP, "projection failed: %s", hipGetErrorString(err));
     return CH_OK;
 }
 
@@ -856,11 +1133,8 @@ void ch_interp_destroy(ch_interp* ip)
     unreg(ip);
     if (ip->d.stream) (void)hipStreamSynchronize(ip->d.stream);
     else (void)hipDeviceSynchronize();
-    for (int c = 0; c < 3; ++c)
-        for (int a = 0; a < 3; ++a) {
-            if (ip->d.idx[c][a]) (void)hipFree(ip->d.idx[c][a]);
-            if (ip->d.wt[c][a]) (void)hipFree(ip->d.wt[c][a]);
-        }
+    for (int c = 0; c < TR_COUNT; ++c) free_transfer(ip->d.tr[c]);
+    free_solenoidal(ip->d);
     delete ip;
 }
 

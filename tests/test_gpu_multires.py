@@ -80,3 +80,110 @@ def test_multires_steps_match_oracle():
     print(f"  rel {e:.3e}, mass rel {abs(m - oracle.mass(ref, wl.h)) / abs(m):.2e}")
     assert e <= 1e-12 * nsteps
     assert abs(m - oracle.mass(wl.C, wl.h)) / abs(m) <= 1e-13
+
+
+# ---- the solenoidal transfer and the back-projection of C (sec. 3.4) ----
+
+def _fine_div(u, v, w):
+    nz, ny, nx = u.shape
+    return ((np.roll(u, -1, axis=2) - u) * nx + (np.roll(v, -1, axis=1) - v) * ny
+            + (w[1:] - w[:-1]) * nz)
+
+
+@pytest.mark.parametrize("fine,nc", [((32, 32, 32), (12, 16, 16)),
+                                     ((36, 40, 48), (10, 16, 20)),
+                                     ((24, 24, 24), (24, 24, 24))])
+def test_solenoidal_transfer_matches_oracle(fine, nc):
+    """Bars: FP64 1e-12 of the largest velocity (the integration sums in
+    another order than the oracle), FP32 2e-5 (single-precision gradients
+    summed over up to 48 cells); the closure sums agree likewise."""
+    nz, ny, nx = fine
+    zf, uc, vc, wc = _coarse(11, nc)
+    ref = oracle.solenoidal_velocity(zf, uc, vc, wc, (nx, ny, nz))
+    scale = max(np.abs(r).max() for r in ref[:3])
+    for prec, dt_, tol in (("fp64", torch.float64, 1e-12), ("fp32", torch.float32, 2e-5)):
+        print(f"[gpu] solenoidal transfer fine={fine} coarse={nc} {prec}", flush=True)
+        st = torch.cuda.Stream()
+        ip = ch.Interp(fine, 1.0 / nx, nc, zf, precision=prec, stream=st, solenoidal=True)
+        got = ip.apply(dev(uc, dt_), dev(vc, dt_), dev(wc, dt_))
+        clo = ip.closure()
+        for name, g, r in zip("uvw", got, ref[:3]):
+            e = float(np.abs(g.double().cpu().numpy() - r).max() / scale)
+            print(f"  {name}: rel {e:.2e}")
+            assert e <= tol
+        print(f"  closure gpu {clo}, oracle {tuple(ref[3])}")
+        for c, r in zip(clo, ref[3]):
+            assert abs(c - r) <= tol * scale
+        w = got[2].double().cpu().numpy()
+        assert np.all(w[0] == 0.0) and np.all(w[-1] == 0.0)
+        ip.close()
+
+
+def test_solenoidal_transfer_is_divergence_free_on_the_gpu():
+    """Property at a size beyond the oracle's small cases: a discrete-curl
+    coarse field (config 3's generator, 48 x 64 x 64) to a 128^3 fine mesh;
+    the FP64 fine divergence is zero to rounding in every cell but the top
+    layer, and the periodic closures vanish (ratio 2)."""
+    nc = (48, 64, 64)
+    zf, uc, vc, wc = _coarse(12, nc)
+    n = 128
+    st = torch.cuda.Stream()
+    ip = ch.Interp((n, n, n), 1.0 / n, nc, zf, precision="fp64", stream=st, solenoidal=True)
+    print(f"[gpu] solenoidal divergence {n}^3 from {nc}", flush=True)
+    u, v, w = (t.cpu().numpy() for t in ip.apply(dev(uc), dev(vc), dev(wc)))
+    clo = ip.closure()
+    ip.close()
+    scale = max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max())
+    div = _fine_div(u, v, w)
+    print(f"  max |div| below the top layer {np.abs(div[:-1]).max():.2e} (scale {scale:.2e}); "
+          f"closure {clo}")
+    assert np.abs(div[:-1]).max() <= 1e-10 * scale * n
+    assert clo[0] <= 1e-12 * scale and clo[1] <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("fine,nc", [((32, 32, 32), (12, 16, 16)), ((36, 40, 48), (10, 16, 20))])
+def test_projection_of_c_matches_oracle(fine, nc):
+    nz, ny, nx = fine
+    ncz, ncy, ncx = nc
+    rng = np.random.default_rng(13)
+    zf = inputs.stretched_faces(ncz, 2.0)
+    Cf = rng.random(fine)
+    ref = oracle.project_c(Cf, zf, (ncx, ncy, ncz))
+    for prec, dt_, tol in (("fp64", torch.float64, 1e-13), ("fp32", torch.float32, 2e-6)):
+        print(f"[gpu] project C fine={fine} coarse={nc} {prec}", flush=True)
+        st = torch.cuda.Stream()
+        ip = ch.Interp(fine, 1.0 / nx, nc, zf, precision=prec, stream=st)
+        got = ip.project_c(dev(Cf, dt_))
+        torch.cuda.synchronize()
+        e = rel(got.double().cpu().numpy(), ref)
+        print(f"  rel {e:.2e}")
+        assert e <= tol
+        ip.close()
+
+
+def test_multires_steps_with_the_solenoidal_transfer_match_oracle():
+    """Config 3 shrunk to 32^3: direct-transfer steps, then the same handle
+    switched to the solenoidal transfer (the captured step graph must be
+    replaced), against the oracle doing the same."""
+    wl = inputs.make_workload(3, n=32)
+    nz, ny, nx = wl.shape
+    zf, uc, vc, wc = (wl.coarse[k] for k in ("zf", "uc", "vc", "wc"))
+    ud = oracle.interp_velocity(zf, uc, vc, wc, (nx, ny, nz))
+    us = oracle.solenoidal_velocity(zf, uc, vc, wc, (nx, ny, nz))[:3]
+    ref = oracle.step(wl.C, *ud, wl.h, wl.Cn, wl.Pe, wl.dt, 2, bc=wl.bc)
+    ref = oracle.step(ref, *us, wl.h, wl.Cn, wl.Pe, wl.dt, 3, bc=wl.bc)
+    print(f"[gpu] multires direct x2 then solenoidal x3, {wl.shape}", flush=True)
+    st = torch.cuda.Stream()
+    s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, bc=wl.bc, stream=st)
+    ip = ch.Interp(wl.shape, wl.h, uc.shape, zf, precision="fp64", stream=st)
+    s.set_field(dev(wl.C))
+    UC, VC, WC = dev(uc), dev(vc), dev(wc)
+    s.step_multires(ip, UC, VC, WC, wl.dt, 2)
+    ip.set_solenoidal(True)
+    s.step_multires(ip, UC, VC, WC, wl.dt, 3)
+    got = s.get_field().cpu().numpy()
+    s.close()
+    ip.close()
+    e = rel(got, ref)
+    print(f"  rel {e:.3e}")
+    assert e <= 1e-12 * 5
