@@ -68,6 +68,8 @@ def lib():
         L.oracle_solenoidal_velocity.restype = ctypes.c_int
         L.oracle_solenoidal_velocity.argtypes = [_I64, _D, _D, _D, _D, _I64, _D, _D, _D, _D]
         L.oracle_project_c.restype = ctypes.c_int
+        L.oracle_label_drops.restype = ctypes.c_int64
+        L.oracle_label_drops.argtypes = [_I64, _INT, _D, ctypes.c_double, _I64]
         L.oracle_project_c.argtypes = [_I64, _D, _I64, _D, _D]
         _lib = L
     return _lib
@@ -270,3 +272,25 @@ def project_c(Cf, zf, nc):
     if rc:
         raise RuntimeError("oracle_project_c failed")
     return Cc
+
+
+def label_drops(C, thr=0.5, bc=(PERIODIC, PERIODIC, PERIODIC)):
+    """Drops of C (nz, ny, nx): face-connected cells with C >= thr, periodic
+    axes wrapping.  Returns (label, ndrops): label[p] is the smallest linear
+    index of p's drop, -1 below the threshold."""
+    C = _f64(C)
+    label = np.empty(C.shape, dtype=np.int64)
+    nd = lib().oracle_label_drops(_dims(C), _bc(bc), _dp(C), float(thr),
+                                  label.ctypes.data_as(_I64))
+    if nd < 0:
+        raise RuntimeError("oracle_label_drops failed")
+    return label, int(nd)
+
+
+def drop_volumes(label, h):
+    """(root, cells, V, D) of every drop, sorted by root (the smallest linear
+    index), with V = h^3 cells and D from (4 pi / 3)(D/2)^3 = V."""
+    roots, cells = np.unique(label[label >= 0], return_counts=True)
+    V = cells * h ** 3
+    D = np.cbrt(6.0 * V / np.pi)
+    return roots, cells, V, D

@@ -7,7 +7,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["ch_oracle.c", "interp_oracle.c"]
+SOURCES = ["ch_oracle.c", "interp_oracle.c", "drops_oracle.c"]
 TARGET = os.path.join(HERE, "liboracle.so")
 
 

@@ -13,7 +13,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
-PINS = ["tests/test_oracle_pins.py", "tests/test_interp_oracle.py"]
+PINS = ["tests/test_oracle_pins.py", "tests/test_interp_oracle.py", "tests/test_drops_oracle.py"]
+SOURCES = ["ch_oracle.c", "interp_oracle.c", "drops_oracle.c"]
 
 # (name, file, original text, planted mistake)
 MUTATIONS = [
@@ -59,6 +60,12 @@ MUTATIONS = [
     ("solenoidal-reference-plane", "interp_oracle.c",
      "interp_component(au, uc, 1, zero1, nfy, m.fyc, nfz, m.fzc, ref);",
      "interp_component(ac, uc, 1, zero1, nfy, m.fyc, nfz, m.fzc, ref);"),
+    ("drops-wall-wraps", "drops_oracle.c",
+     "if (bc[d] != 0) continue;", "if (bc[d] != 0 && d == 0) continue;"),
+    ("drops-threshold-strict", "drops_oracle.c",
+     "if (C[nb] >= thr) {", "if (C[nb] > thr) {"),
+    ("drops-one-direction", "drops_oracle.c",
+     "for (int s = -1; s <= 1; s += 2) {", "for (int s = 1; s <= 1; s += 2) {"),
     ("projection-wall-continuation", "interp_oracle.c",
      "{m.nfz, m.fzc, 1.0, AX_WALL_EVEN}};\n    interp_component(af",
      "{m.nfz, m.fzc, 1.0, AX_PERIODIC}};\n    interp_component(af"),
@@ -67,7 +74,7 @@ MUTATIONS = [
 
 def _build_and_run(tmp, edits):
     srcs = []
-    for name in ("ch_oracle.c", "interp_oracle.c"):
+    for name in SOURCES:
         text = open(os.path.join(ORACLE, name)).read()
         for fname, old, new in edits:
             if fname == name:
