@@ -153,10 +153,19 @@ def bench_ensemble(args, stream):
             "l2_rel_fp32_vs_fp64": float(np.linalg.norm(d) / np.linalg.norm(fields["fp64"]))}
 
 
+def transfer_bytes_per_component(nc, nf, es):
+    """Algorithmic HBM bytes of one component of the plain coarse-to-fine
+    transfer: every coarse value read once, every fine value written once."""
+    ncz, ncy, ncx = nc
+    nz, ny, nx = nf
+    return (ncx * ncy * ncz + nx * ny * nz) * es
+
+
 def bench_multires(args, stream):
     """The multiple-resolution workload: 512^3 fine mesh, periodic in x and y,
     no-flux walls in z, 1000 drops; the velocity lives on a 256 x 256 x 192
-    mesh stretched in z and is transferred to the fine faces every step."""
+    mesh stretched in z and is transferred to the fine faces every step,
+    by the plain transfer and by the solenoidal one."""
     import numpy as np
     import torch
     from paper_2105_01865_amd import ch, inputs
@@ -166,34 +175,64 @@ def bench_multires(args, stream):
     fields = {}
     for prec in ("fp32", "fp64"):
         dt_ = torch.float32 if prec == "fp32" else torch.float64
-        s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, bc=wl.bc, precision=prec, stream=stream)
-        ip = ch.Interp(wl.shape, wl.h, uc.shape, zf, precision=prec, stream=stream)
+        es = 4 if prec == "fp32" else 8
         UC, VC, WC = (torch.from_numpy(a).to("cuda", dt_) for a in (uc, vc, wc))
-        s.set_field(torch.from_numpy(wl.C).to("cuda", dt_))
-        m0 = s.mass()
-        s.step_multires(ip, UC, VC, WC, wl.dt, args.warmup)
-        ms = _timed_events(stream, lambda: s.step_multires(ip, UC, VC, WC, wl.dt,
-                                                           args.multires_steps))
-        m1 = s.mass()
-        fields[prec] = s.get_field().double().cpu().numpy()
-        s.profile(True)
-        s.step_multires(ip, UC, VC, WC, wl.dt, 5)
-        kern = {k: s.profile_read(k) for k in ("x", "y", "z", "interp")}
-        s.profile(False)
-        s.close()
-        ip.close()
-        res[prec] = {"value": round(wl.points * args.multires_steps / (ms * 1e-3) / 1e9, 4),
-                     "unit": "Gpts/s", "ms_per_step": round(ms / args.multires_steps, 4),
-                     "mass_drift": abs(m1 - m0) / abs(m0),
-                     "kernels_avg_us": {k: round(1e3 * v[0] / max(1, v[1]), 1)
-                                        for k, v in kern.items()}}
+        C0 = torch.from_numpy(wl.C).to("cuda", dt_)
+        for mode in ("plain", "solenoidal"):
+            s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, bc=wl.bc, precision=prec, stream=stream)
+            ip = ch.Interp(wl.shape, wl.h, uc.shape, zf, precision=prec, stream=stream,
+                           solenoidal=mode == "solenoidal")
+            s.set_field(C0)
+            m0 = s.mass()
+            s.step_multires(ip, UC, VC, WC, wl.dt, args.warmup)
+            ms = _timed_events(stream, lambda: s.step_multires(ip, UC, VC, WC, wl.dt,
+                                                               args.multires_steps))
+            m1 = s.mass()
+            if mode == "plain":
+                fields[prec] = s.get_field().double().cpu().numpy()
+            s.profile(True)
+            s.step_multires(ip, UC, VC, WC, wl.dt, 5)
+            kern = {k: s.profile_read(k) for k in ("x", "y", "z", "interp")}
+            s.profile(False)
+            clo = ip.closure()
+            s.close()
+            ip.close()
+            t_us = 1e3 * kern["interp"][0] / max(1, kern["interp"][1])
+            r = {"value": round(wl.points * args.multires_steps / (ms * 1e-3) / 1e9, 4),
+                 "unit": "Gpts/s", "ms_per_step": round(ms / args.multires_steps, 4),
+                 "mass_drift": abs(m1 - m0) / abs(m0),
+                 "kernels_avg_us": {k: round(1e3 * v[0] / max(1, v[1]), 1)
+                                    for k, v in kern.items()}}
+            nbytes = transfer_bytes_per_component(uc.shape, wl.shape, es)
+            if mode == "plain":
+                # the transfer of one component is one k_interp launch
+                r["transfer_roofline"] = {
+                    "bound": "hbm", "bytes_per_component": nbytes,
+                    "achieved_GBs": round(nbytes / (t_us * 1e-6) / 1e9, 1),
+                    "peak_GBs": HBM_PEAK_GBS,
+                    "frac": round(nbytes / (t_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 3)}
+            else:
+                # gradient, interpolation to the fine centres, reference plane
+                # and in-place integration: the fine array is written, read
+                # and written again
+                sb = nbytes + 2 * (wl.points * es) + 2 * (uc.size * es)
+                r["transfer_roofline"] = {
+                    "bound": "hbm", "bytes_per_component": sb,
+                    "achieved_GBs": round(sb / (t_us * 1e-6) / 1e9, 1),
+                    "peak_GBs": HBM_PEAK_GBS,
+                    "frac": round(sb / (t_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 3),
+                    "vs_plain_transfer_bytes": round(sb / nbytes, 2)}
+                r["closure_max"] = [float(c) for c in clo]
+            res.setdefault(prec, {})[mode] = r
+        del UC, VC, WC, C0
     d = fields["fp32"] - fields["fp64"]
     return {"workload": "512^3 fine mesh, periodic x,y, no-flux z, 1000 tanh drops R~U[4,12]h; "
                         "velocity on 256x256x192 (tanh-stretched z) transferred every step "
-                        "(transfer inside the step time)",
+                        "(transfer inside the step time), plain and solenoidal transfer",
             "points": wl.points, "steps": args.multires_steps, "dt": wl.dt,
-            "fp32": res["fp32"], "fp64": res["fp64"],
-            "fp32_over_fp64": round(res["fp32"]["value"] / res["fp64"]["value"], 3),
+            "fp32": res["fp32"]["plain"], "fp64": res["fp64"]["plain"],
+            "solenoidal": {"fp32": res["fp32"]["solenoidal"], "fp64": res["fp64"]["solenoidal"]},
+            "fp32_over_fp64": round(res["fp32"]["plain"]["value"] / res["fp64"]["plain"]["value"], 3),
             "l2_rel_fp32_vs_fp64": float(np.linalg.norm(d) / np.linalg.norm(fields["fp64"]))}
 
 
@@ -334,6 +373,11 @@ def main():
         m1 = s.mass()
         C = s.get_field().double().cpu().numpy()
         cfg = s.config()
+        # drops of the final field (the first call allocates the labels)
+        s.drops()
+        t0 = time.perf_counter()
+        roots, cells = s.drops()
+        label_ms = (time.perf_counter() - t0) * 1e3
         # every kernel, timed launch by launch with HIP events on the
         # library's stream over a profiled run of the same steps
         s.set_field(C0)
@@ -342,7 +386,8 @@ def main():
         prof = {k: s.profile_read(k) for k in ("x", "y", "z")}
         s.profile(False)
         s.close()
-        return dict(ms=ms, wall=wall, m0=m0, m1=m1, C=C, cfg=cfg, prof=prof)
+        return dict(ms=ms, wall=wall, m0=m0, m1=m1, C=C, cfg=cfg, prof=prof, roots=roots,
+                    cells=cells, label_ms=label_ms)
 
     r32 = timed("fp32")
     r64 = timed("fp64")
@@ -358,6 +403,22 @@ def main():
     v32vol = float((C32 >= 0.5).sum()) * h ** 3
     v64vol = float((C64 >= 0.5).sum()) * h ** 3
     vol_err = abs(v32vol - v64vol) / v64vol
+    # per-drop volumes (drops matched by their root, the smallest cell index)
+    c64 = dict(zip(r64["roots"].tolist(), r64["cells"].tolist()))
+    matched = [(c, c64[r]) for r, c in zip(r32["roots"].tolist(), r32["cells"].tolist()) if r in c64]
+    dh = np.cbrt(6.0 * r64["cells"] * h ** 3 / np.pi) / (wl.shape[0] * h)
+    drops = {"definition": "face-connected cells with C >= 1/2 (periodic), V = h^3 cells, "
+                           "(4 pi/3)(D/2)^3 = V, H = box height",
+             "count_fp32": int(len(r32["roots"])), "count_fp64": int(len(r64["roots"])),
+             "matched_by_root": len(matched),
+             "max_rel_volume_err_fp32_vs_fp64": max((abs(a - b) / b for a, b in matched),
+                                                    default=None),
+             "D_over_H_fp64": {"min": float(dh.min()), "median": float(np.median(dh)),
+                               "max": float(dh.max())} if len(dh) else None,
+             "label_ms_fp32": round(r32["label_ms"], 2), "label_ms_fp64": round(r64["label_ms"], 2),
+             "label_ms_note": "ch_drops wall time: labelling, counting, copy-out and sort",
+             "l_loss_fp32": (r32["m1"] - r32["m0"]) / r32["m0"],
+             "l_loss_fp64": (r64["m1"] - r64["m0"]) / r64["m0"]}
 
     def kern(r):
         return {k: dict(avg_us=round(1e3 * r["prof"][k][0] / max(1, r["prof"][k][1]), 2),
@@ -395,7 +456,7 @@ def main():
         "fp32_over_fp64": round(v32 / v64, 3),
         "accuracy_fp32_vs_fp64": {"steps": args.warmup + nstep, "l2_rel": l2,
                                   "mass_drift_fp32": drift32, "mass_drift_fp64": drift64,
-                                  "drop_volume_err": vol_err},
+                                  "drop_volume_err": vol_err, "drops": drops},
         "hbm_frac_step_model": round(step_bytes_per_point(4) * pts /
                                      (r32["ms"] / nstep * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "alu", "kernel": "k_pass_x (explicit terms + RHS + x solve), fp32",

@@ -243,6 +243,24 @@ ch_status ch_interp_project_c(ch_interp* ip, const void* Cf, void* Cc);
 ch_status ch_step_multires(ch_state* s, ch_interp* ip, const void* uc, const void* vc,
                            const void* wc, double dt, int nsteps);
 
+/* ---- drop diagnostics (sec. 4) -------------------------------------------
+ * The drops of a box for the drop-size statistics: cells with
+ * C >= threshold (the paper's mid-value 1/2; compared in the state's
+ * precision) joined through cell faces, across periodic boundaries but not
+ * across walls.  Each drop is named by its root, the smallest linear index
+ * (x fastest, [z][y][x]) of its cells, and `cells` counts its cells; its
+ * volume is V = h^3 cells and its effective diameter D follows from
+ * (4 pi / 3)(D/2)^3 = V.  The first min(cap, *ndrops) drops in increasing
+ * root order go to the host arrays root[] and cells[]; *ndrops receives
+ * the number of drops.  The labelling runs on the state's stream and the
+ * call waits for it.  The first call allocates two ints per cell of the box
+ * (kept until destroy).  Boxes of 2^31 cells or more: CH_EUNSUPPORTED.
+ * ch_batch_drops does the same for box `box` of an ensemble. */
+ch_status ch_drops(ch_state* s, double threshold, int64_t cap, int64_t* ndrops, int64_t* root,
+                   int64_t* cells);
+ch_status ch_batch_drops(ch_batch* b, int box, double threshold, int64_t cap, int64_t* ndrops,
+                         int64_t* root, int64_t* cells);
+
 /* ---- measurement ---------------------------------------------------------
  * With profiling on, ch_step / ch_batch_step launch kernels one by one
  * (no graph) and time each launch with HIP events on the state's stream.

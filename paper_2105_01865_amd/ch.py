@@ -87,6 +87,10 @@ SIGNATURES = {
     "ch_interp_set_stream": (_I, [_VP, _VP]),
     "ch_interp_apply": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "ch_interp_destroy": (None, [_VP]),
+    "ch_drops": (_I, [_VP, _D, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "ch_batch_drops": (_I, [_VP, _I, _D, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "ch_interp_set_solenoidal": (_I, [_VP, _I]),
     "ch_interp_closure": (_I, [_VP, ctypes.POINTER(_D)]),
     "ch_interp_project_c": (_I, [_VP, _VP, _VP]),
@@ -155,6 +159,21 @@ def _dev_tensor(t, dtype, shape, name):
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _drops_call(fn, args, cap):
+    """Run ch_drops / ch_batch_drops, growing the host arrays once if the
+    box has more than `cap` drops.  Returns (root, cells) int64 arrays."""
+    while True:
+        nd = ctypes.c_int64()
+        root = np.zeros(max(cap, 1), dtype=np.int64)
+        cells = np.zeros(max(cap, 1), dtype=np.int64)
+        P64 = ctypes.POINTER(ctypes.c_int64)
+        _check(fn(*args, cap, ctypes.byref(nd), root.ctypes.data_as(P64),
+                  cells.ctypes.data_as(P64)))
+        if nd.value <= cap:
+            return root[:nd.value], cells[:nd.value]
+        cap = nd.value
 
 
 class _StreamMixin:
@@ -247,6 +266,12 @@ class State(_StreamMixin):
         self._enter()
         _check(lib().ch_mass(self._h, ctypes.byref(out)))
         return out.value
+
+    def drops(self, threshold=0.5, cap=4096):
+        """(root, cells) of every drop (face-connected cells with
+        C >= threshold), sorted by root; V = h^3 cells."""
+        self._enter()
+        return _drops_call(lib().ch_drops, (self._h, float(threshold)), cap)
 
     def check_velocity(self, u, v, w):
         su, sv, sw = self.vel_shapes()
@@ -355,6 +380,11 @@ class Batch(_StreamMixin):
         self._enter()
         _check(lib().ch_batch_step(self._h, pu, pv, pw, float(dt), int(nsteps)))
         self._leave()
+
+    def drops(self, box, threshold=0.5, cap=4096):
+        """(root, cells) of the drops of box `box`, sorted by root."""
+        self._enter()
+        return _drops_call(lib().ch_batch_drops, (self._h, int(box), float(threshold)), cap)
 
     def mass(self):
         out = (ctypes.c_double * self.nbox)()

@@ -89,4 +89,16 @@ template <typename T>
 hipError_t launch_scan(hipStream_t st, int dir, void* buf, const void* ref, int nx, int ny,
                        int nz, double h, double* part);
 
+// Drops of one box (cells with C >= thr joined through faces, bc[d] == 0
+// wrapping): lab[i] = the smallest linear index of i's drop, or -1.  Then
+// the cells per drop into cnt (zeroed by the caller, one int per cell), and
+// the roots with their counts into oroot / ocnt (at most cap entries, in no
+// particular order) with the number of drops in *count (zeroed by the
+// caller).  Boxes of fewer than 2^31 cells.
+template <typename T>
+hipError_t launch_drops_label(hipStream_t st, const void* C, int nx, int ny, int nz,
+                              const int bc[3], double thr, int* lab);
+hipError_t launch_drops_count(hipStream_t st, const int* lab, int64_t n, int* cnt, int cap,
+                              int* oroot, int* ocnt, int* count);
+
 }  // namespace chk

@@ -362,29 +362,70 @@ __device__ __forceinline__ void group_max(double v, double* __restrict__ part)
 // Integration along x, one wavefront per row (in place): the row holds the
 // interpolated gradient at the fine cell centres on entry and
 //   u[i] = ref[row] + h sum_{i' < i} G[i']
-// on exit (64 points per wave-wide scan).  The |h sum G| of the whole row is
-// the closure left at the periodic seam.
+// on exit.  Each lane takes CH consecutive points (32 bytes, two 16-byte
+// vector accesses when the row allows), forms their prefix sums, and one
+// wave-wide scan of the lane totals joins them.  The |h sum G| of the whole
+// row is the closure left at the periodic seam.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_scan_x(T* __restrict__ buf, const T* __restrict__ ref, int nx, int64_t nrows, T h,
          double* __restrict__ part)
 {
+    constexpr int CH = 32 / sizeof(T);
+    typedef T TV __attribute__((ext_vector_type(CH / 2)));
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool vec = nx % (64 * CH) == 0 && reinterpret_cast<uintptr_t>(buf) % 16 == 0;
     double mx = 0.0;
     for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < nrows; row += (int64_t)gridDim.x * 4) {
         T* p = buf + row * nx;
         const T r = ref[row];
         T acc = T(0);
-        for (int i0 = 0; i0 < nx; i0 += 64) {
-            const int i = i0 + lane;
-            const T g = i < nx ? p[i] : T(0);
-            T s = g;
+        for (int i0 = 0; i0 < nx; i0 += 64 * CH) {
+            const int b0 = i0 + lane * CH;
+            T g[CH];
+            if (vec) {
+                const TV lo = *reinterpret_cast<const TV*>(p + b0);
+                const TV hi = *reinterpret_cast<const TV*>(p + b0 + CH / 2);
+#pragma unroll
+                for (int m = 0; m < CH / 2; ++m) {
+                    g[m] = lo[m];
+                    g[m + CH / 2] = hi[m];
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < CH; ++m) g[m] = b0 + m < nx ? p[b0 + m] : T(0);
+            }
+            T loc[CH];
+            T run = T(0);
+#pragma unroll
+            for (int m = 0; m < CH; ++m) {
+                loc[m] = run;
+                run += g[m];
+            }
+            T s = run;
 #pragma unroll
             for (int d = 1; d < 64; d <<= 1) {
                 const T t = __shfl_up(s, d);
                 if (lane >= d) s += t;
             }
-            if (i < nx) p[i] = r + h * (acc + (s - g));
+            const T ex = acc + (s - run);
+            T o[CH];
+#pragma unroll
+            for (int m = 0; m < CH; ++m) o[m] = r + h * (ex + loc[m]);
+            if (vec) {
+                TV lo, hi;
+#pragma unroll
+                for (int m = 0; m < CH / 2; ++m) {
+                    lo[m] = o[m];
+                    hi[m] = o[m + CH / 2];
+                }
+                *reinterpret_cast<TV*>(p + b0) = lo;
+                *reinterpret_cast<TV*>(p + b0 + CH / 2) = hi;
+            } else {
+#pragma unroll
+                for (int m = 0; m < CH; ++m)
+                    if (b0 + m < nx) p[b0 + m] = o[m];
+            }
             acc += __shfl(s, 63);
         }
         mx = fmax(mx, (double)fabs(h * acc));
@@ -460,6 +501,132 @@ k_scan_z(T* __restrict__ buf, int64_t plane, int nz, T h, double* __restrict__ p
         mx = fmax(mx, (double)fabs(h * acc));
     }
     group_max(mx, part);
+}
+
+// Drop labelling (the drop-size diagnostics of sec. 4): cells with
+// C >= threshold, joined through faces (periodic axes wrap), by union-find
+// on a label array.  A label points to a smaller linear index of the same
+// drop or to itself (a root); unions link the larger root under the smaller
+// with atomicMin, so every drop ends with its smallest index as its root.
+// Loads of labels other threads may be changing go to the coherent level.
+__device__ __forceinline__ int ccl_load(const int* lab, int a)
+{
+    return __hip_atomic_load(lab + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int ccl_find(const int* lab, int a)
+{
+    int b = ccl_load(lab, a);
+    while (b != a) {   // labels only decrease along the chain: it ends
+        a = b;
+        b = ccl_load(lab, a);
+    }
+    return a;
+}
+
+__device__ void ccl_union(int* lab, int a, int b)
+{
+    // each retry lowers max(a, b) strictly, so the loop ends
+    for (;;) {
+        a = ccl_find(lab, a);
+        b = ccl_find(lab, b);
+        if (a == b) return;
+        if (a > b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        const int old = atomicMin(lab + b, a);
+        if (old == b) return;
+        b = old;   // b had been linked meanwhile: join a with b's parent
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_ccl_init(const T* __restrict__ C, int64_t n, T thr, int* __restrict__ lab)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        lab[i] = C[i] >= thr ? (int)i : -1;
+}
+
+// One (z, y) row per work-group and iteration, threads along x: every drop
+// cell is joined with its -x, -y and -z neighbours (wrapping on periodic axes).
+__global__ void __launch_bounds__(256)
+k_ccl_union(int* lab, int nx, int ny, int nz, int px, int py, int pz)
+{
+    const int64_t plane = (int64_t)nx * ny;
+    for (int64_t row = blockIdx.x; row < (int64_t)ny * nz; row += gridDim.x) {
+        const int z = (int)(row / ny), y = (int)(row - (int64_t)z * ny);
+        const int64_t r0 = row * nx;
+        for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+            const int i = (int)(r0 + x);
+            if (lab[i] < 0) continue;   // background stays background
+            if (x > 0 || px) {
+                const int j = x > 0 ? i - 1 : (int)(r0 + nx - 1);
+                if (lab[j] >= 0) ccl_union(lab, i, j);
+            }
+            if (y > 0 || py) {
+                const int j = y > 0 ? i - nx : (int)(i + (int64_t)(ny - 1) * nx);
+                if (lab[j] >= 0) ccl_union(lab, i, j);
+            }
+            if (z > 0 || pz) {
+                const int j = z > 0 ? (int)(i - plane) : (int)(i + (int64_t)(nz - 1) * plane);
+                if (lab[j] >= 0) ccl_union(lab, i, j);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_ccl_flatten(int* lab, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (lab[i] >= 0) lab[i] = ccl_find(lab, (int)i);
+}
+
+// Cells per drop: each thread counts a run of CCL_RUN consecutive cells and
+// adds one count per stretch of equal labels to cnt[root].
+constexpr int CCL_RUN = 32;
+
+__global__ void __launch_bounds__(256)
+k_ccl_count(const int* __restrict__ lab, int64_t n, int* __restrict__ cnt)
+{
+    const int64_t nrun = (n + CCL_RUN - 1) / CCL_RUN;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrun;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i0 = r * CCL_RUN, i1 = i0 + CCL_RUN < n ? i0 + CCL_RUN : n;
+        int cur = -1, c = 0;
+        for (int64_t i = i0; i < i1; ++i) {
+            const int l = lab[i];
+            if (l != cur) {
+                if (cur >= 0) atomicAdd(cnt + cur, c);
+                cur = l;
+                c = 0;
+            }
+            ++c;
+        }
+        if (cur >= 0) atomicAdd(cnt + cur, c);
+    }
+}
+
+// Roots and their cell counts into a list of at most cap entries (in no
+// particular order); *count receives the number of drops.
+__global__ void __launch_bounds__(256)
+k_ccl_compact(const int* __restrict__ lab, const int* __restrict__ cnt, int64_t n, int cap,
+              int* __restrict__ oroot, int* __restrict__ ocnt, int* __restrict__ count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (lab[i] == (int)i) {
+            const int k = atomicAdd(count, 1);
+            if (k < cap) {
+                oroot[k] = (int)i;
+                ocnt[k] = cnt[i];
+            }
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -612,6 +779,42 @@ hipError_t launch_scan(hipStream_t st, int dir, void* buf, const void* ref, int 
     return hipGetLastError();
 }
 
+static unsigned grid_for(int64_t n)
+{
+    const int64_t g = (n + 255) / 256;
+    return (unsigned)(g < 65536 ? (g > 0 ? g : 1) : 65536);
+}
+
+template <typename T>
+hipError_t launch_drops_label(hipStream_t st, const void* C, int nx, int ny, int nz,
+                              const int bc[3], double thr, int* lab)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    hipLaunchKernelGGL((k_ccl_init<T>), dim3(grid_for(n)), dim3(256), 0, st, (const T*)C, n,
+                       T(thr), lab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t rows = (int64_t)ny * nz;
+    hipLaunchKernelGGL(k_ccl_union, dim3((unsigned)(rows < 262144 ? rows : 262144)), dim3(256), 0,
+                       st, lab, nx, ny, nz, bc[0] == 0, bc[1] == 0, bc[2] == 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ccl_flatten, dim3(grid_for(n)), dim3(256), 0, st, lab, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_drops_count(hipStream_t st, const int* lab, int64_t n, int* cnt, int cap,
+                              int* oroot, int* ocnt, int* count)
+{
+    hipLaunchKernelGGL(k_ccl_count, dim3(grid_for((n + CCL_RUN - 1) / CCL_RUN)), dim3(256), 0, st,
+                       lab, n, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ccl_compact, dim3(grid_for(n)), dim3(256), 0, st, lab, cnt, n, cap,
+                       oroot, ocnt, count);
+    return hipGetLastError();
+}
+
 #define CH_INSTANTIATE(T, A)                                                                    \
     template hipError_t launch_pass_x<T, A>(int, int, int, size_t, hipStream_t,                 \
                                             const chd::BoxDesc*, int,                           \
@@ -635,6 +838,10 @@ template hipError_t launch_check_velocity<float>(hipStream_t, const chd::BoxDesc
                                                  const void*, const void*, const void*, int*);
 template hipError_t launch_interp<double>(hipStream_t, const InterpArgs&);
 template hipError_t launch_interp<float>(hipStream_t, const InterpArgs&);
+template hipError_t launch_drops_label<double>(hipStream_t, const void*, int, int, int,
+                                               const int*, double, int*);
+template hipError_t launch_drops_label<float>(hipStream_t, const void*, int, int, int, const int*,
+                                              double, int*);
 template hipError_t launch_grad<double>(hipStream_t, const void*, int, int, int, int,
                                         const double*, void*);
 template hipError_t launch_grad<float>(hipStream_t, const void*, int, int, int, int,

@@ -93,6 +93,13 @@ struct Engine {
     void* fu = nullptr;
     void* fv = nullptr;
     void* fw = nullptr;
+    // drop labelling: labels and counts (one int per cell of the largest box
+    // labelled so far), the root list (cap entries each) and its length
+    int* d_lab = nullptr;
+    int* d_cnt = nullptr;
+    int64_t lab_n = 0;
+    int* d_list = nullptr;
+    int64_t list_cap = 0;
 };
 
 void free_engine(Engine& e)
@@ -104,7 +111,7 @@ void free_engine(Engine& e)
     }
     for (auto ev : e.ev_pool) (void)hipEventDestroy(ev);
     void* bufs[] = {e.C, e.E, e.qa, e.qb, e.d_partial, e.d_h3, e.d_mass, e.d_flags, e.d_boxes,
-                    e.fu, e.fv, e.fw};
+                    e.fu, e.fv, e.fw, e.d_lab, e.d_cnt, e.d_list};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
 }
@@ -575,6 +582,83 @@ ch_status run_steps(Engine& e, const void* u, const void* v, const void* w, doub
         }
     }
     return CH_OK;
+}
+
+// Drops of box `box`: labels, counts and the sorted (root, cells) list.
+ch_status drops(Engine& e, int box, double thr, int64_t cap, int64_t* ndrops, int64_t* root,
+                int64_t* cells)
+{
+    if (!ndrops || (cap > 0 && (!root || !cells))) return fail(CH_EINVAL, "null output");
+    if (cap < 0) return fail(CH_EINVAL, "negative capacity");
+    if (box < 0 || box >= e.P.nbox) return fail(CH_EINVAL, "box %d out of range", box);
+    if (!std::isfinite(thr)) return fail(CH_EINVAL, "threshold must be finite");
+    const chd::BoxDesc& d = e.P.boxes[box];
+    const int64_t n = (int64_t)d.n[0] * d.n[1] * d.n[2];
+    if (n >= 2147483647LL) return fail(CH_EUNSUPPORTED, "drop labelling needs fewer than 2^31 cells");
+    HIP_TRY(hipSetDevice(e.device));
+    if (n > e.lab_n) {
+        if (e.d_lab) (void)hipFree(e.d_lab);
+        if (e.d_cnt) (void)hipFree(e.d_cnt);
+        e.d_lab = e.d_cnt = nullptr;
+        e.lab_n = 0;
+        if (hipMalloc(&e.d_lab, sizeof(int) * n) != hipSuccess ||
+            hipMalloc(&e.d_cnt, sizeof(int) * n) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CH_ENOMEM, "cannot allocate the drop labels");
+        }
+        e.lab_n = n;
+    }
+    const size_t es = chp::esize(e.P.prec);
+    const void* C = (const char*)e.C + d.c_off * es;
+    const int bc[3] = {d.bc[0], d.bc[1], d.bc[2]};
+    hipError_t err = e.P.prec == CH_FP64
+        ? chk::launch_drops_label<double>(e.stream, C, d.n[0], d.n[1], d.n[2], bc, thr, e.d_lab)
+        : chk::launch_drops_label<float>(e.stream, C, d.n[0], d.n[1], d.n[2], bc, thr, e.d_lab);
+    if (err != hipSuccess) return fail(CH_EHIP, "drop labelling failed: %s", hipGetErrorString(err));
+    HIP_TRY(hipMemsetAsync(e.d_cnt, 0, sizeof(int) * n, e.stream));
+    // the root list: sized from a first pass if the cached one is too short
+    int64_t want = std::max<int64_t>(e.list_cap, 1024);
+    for (int pass = 0; pass < 2; ++pass) {
+        if (want > e.list_cap) {
+            if (e.d_list) (void)hipFree(e.d_list);
+            e.d_list = nullptr;
+            e.list_cap = 0;
+            if (hipMalloc(&e.d_list, sizeof(int) * (2 * want + 1)) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(CH_ENOMEM, "cannot allocate the drop list");
+            }
+            e.list_cap = want;
+        }
+        int* count = e.d_list + 2 * e.list_cap;
+        HIP_TRY(hipMemsetAsync(count, 0, sizeof(int), e.stream));
+        if (pass == 1) HIP_TRY(hipMemsetAsync(e.d_cnt, 0, sizeof(int) * n, e.stream));
+        err = chk::launch_drops_count(e.stream, e.d_lab, n, e.d_cnt, (int)e.list_cap, e.d_list,
+                                      e.d_list + e.list_cap, count);
+        if (err != hipSuccess)
+            return fail(CH_EHIP, "drop counting failed: %s", hipGetErrorString(err));
+        int found = 0;
+        HIP_TRY(hipMemcpyAsync(&found, count, sizeof(int), hipMemcpyDeviceToHost, e.stream));
+        HIP_TRY(hipStreamSynchronize(e.stream));
+        if (found <= e.list_cap) {
+            std::vector<int> r(found), c(found);
+            if (found > 0) {
+                HIP_TRY(hipMemcpy(r.data(), e.d_list, sizeof(int) * found, hipMemcpyDeviceToHost));
+                HIP_TRY(hipMemcpy(c.data(), e.d_list + e.list_cap, sizeof(int) * found,
+                                  hipMemcpyDeviceToHost));
+            }
+            std::vector<int> order(found);
+            for (int q = 0; q < found; ++q) order[q] = q;
+            std::sort(order.begin(), order.end(), [&](int a, int b) { return r[a] < r[b]; });
+            for (int64_t q = 0; q < std::min<int64_t>(cap, found); ++q) {
+                root[q] = r[order[q]];
+                cells[q] = c[order[q]];
+            }
+            *ndrops = found;
+            return CH_OK;
+        }
+        want = found;
+    }
+    return fail(CH_EHIP, "drop list did not settle");
 }
 
 ch_status mass(Engine& e, double* out)
@@ -1136,6 +1220,20 @@ void ch_interp_destroy(ch_interp* ip)
     for (int c = 0; c < TR_COUNT; ++c) free_transfer(ip->d.tr[c]);
     free_solenoidal(ip->d);
     delete ip;
+}
+
+ch_status ch_drops(ch_state* s, double threshold, int64_t cap, int64_t* ndrops, int64_t* root,
+                   int64_t* cells)
+{
+    CHECK_STATE(s);
+    return drops(s->e, 0, threshold, cap, ndrops, root, cells);
+}
+
+ch_status ch_batch_drops(ch_batch* b, int box, double threshold, int64_t cap, int64_t* ndrops,
+                         int64_t* root, int64_t* cells)
+{
+    CHECK_STATE(b);
+    return drops(b->e, box, threshold, cap, ndrops, root, cells);
 }
 
 ch_status ch_step_multires(ch_state* s, ch_interp* ip, const void* uc, const void* vc,

@@ -92,7 +92,8 @@ def _fine_div(u, v, w):
 
 @pytest.mark.parametrize("fine,nc", [((32, 32, 32), (12, 16, 16)),
                                      ((36, 40, 48), (10, 16, 20)),
-                                     ((24, 24, 24), (24, 24, 24))])
+                                     ((24, 24, 24), (24, 24, 24)),
+                                     ((16, 8, 512), (8, 8, 256))])   # 512-point x rows
 def test_solenoidal_transfer_matches_oracle(fine, nc):
     """Bars: FP64 1e-12 of the largest velocity (the integration sums in
     another order than the oracle), FP32 2e-5 (single-precision gradients
