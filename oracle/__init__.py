@@ -17,6 +17,7 @@ import os
 import numpy as np
 
 from . import build as _build
+from . import pressure   # noqa: F401  (split-density pressure step, numpy)
 
 PERIODIC = 0
 NOFLUX = 1

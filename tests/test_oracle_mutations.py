@@ -101,3 +101,42 @@ def test_unmodified_copy_passes():
 def test_planted_mistake_is_caught(name, fname, old, new):
     with tempfile.TemporaryDirectory() as tmp:
         assert _build_and_run(tmp, [(fname, old, new)]) != 0, name
+
+
+# mistakes planted in the numpy pressure oracle (oracle/pressure.py): the
+# module is re-executed from the mutated source before its pins run
+PY_MUTATIONS = [
+    ("pressure-extrapolation", "Phat = 2.0 * P - Pold", "Phat = 2.0 * P + Pold"),
+    ("pressure-face-pair", "return 0.5 * (a + np.roll(a, 1, axis=axis))",
+     "return 0.5 * (a + np.roll(a, -1, axis=axis))"),
+    ("pressure-split-coefficient", "(1.0 - rho2 / r) * g", "(1.0 - r / rho2) * g"),
+    ("pressure-update-coefficient", "(1.0 / r - 1.0 / rho2) * gp", "(1.0 / rho2 - 1.0 / r) * gp"),
+    ("pressure-neumann-ends", "T[0, 0] = T[-1, -1] = -1.0 / h ** 2",
+     "T[0, 0] = T[-1, -1] = -2.0 / h ** 2"),
+    ("pressure-no-clip", "np.clip(C, 0.0, 1.0)", "C"),
+]
+
+_PY_RUNNER = """
+import sys
+sys.path.insert(0, {root!r})
+import oracle.pressure as m
+path = m.__file__
+src = open(path).read()
+assert src.count({old!r}) >= 1
+exec(compile(src.replace({old!r}, {new!r}, 1), path, "exec"), m.__dict__)
+import pytest
+sys.exit(pytest.main(["-x", "-q", "-p", "no:cacheprovider", "tests/test_pressure_oracle.py"]))
+"""
+
+
+@pytest.mark.parametrize("name,old,new", PY_MUTATIONS, ids=[m[0] for m in PY_MUTATIONS])
+def test_planted_mistake_in_the_pressure_oracle_is_caught(name, old, new):
+    code = _PY_RUNNER.format(root=ROOT, old=old, new=new)
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True)
+    assert r.returncode == 1, (name, r.stdout[-2000:], r.stderr[-2000:])
+
+
+def test_unmodified_pressure_oracle_passes_through_the_runner():
+    code = _PY_RUNNER.format(root=ROOT, old="import numpy as np", new="import numpy as np")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout[-2000:]
