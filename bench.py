@@ -36,6 +36,14 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_x_256cube_fp32_traffic.md"
 X_SOURCES = ("ch_device.h", "ch_kernels.hip", "ch_plan.h")
 
 
+def progress(msg):
+    """One line per finished section on stderr (long runs stay visibly alive)."""
+    print(f"[bench] {msg} ({time.perf_counter() - _T0:.0f} s)", file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
+
+
 def x_pass_flops_per_point():
     """Algorithmic flops of one x-pass launch per grid point (fused
     multiply-add = 2, add / multiply / reciprocal = 1):
@@ -236,6 +244,68 @@ def bench_multires(args, stream):
             "l2_rel_fp32_vs_fp64": float(np.linalg.norm(d) / np.linalg.norm(fields["fp64"]))}
 
 
+def pressure_bytes_per_step(n, es):
+    """Algorithmic HBM bytes of one pressure step on n cells: element accesses
+    prep 4 (P, Pold in; Phat, Pold out), right-hand side 6 (C, Phat, u, v, w
+    in; rhs out), forward transform 2, mode solves 3 (spectrum in and out,
+    half a field of Thomas scratch written and read), inverse transform 2,
+    update 9 (C, P, Phat, u, v, w in; u, v, w out): 26 n elements."""
+    return 26 * n * es
+
+
+def bench_pressure(args, stream):
+    """The split-density pressure step on the 512^3 multiple-resolution box
+    (walls in z): C and u* from that workload (u* = the plain transfer of
+    its coarse velocity), density ratio 1000, P and P^{l-1} from the steps
+    before."""
+    import torch
+    from paper_2105_01865_amd import ch, inputs
+    wl = inputs.make_workload(3)
+    zf, uc, vc, wc = (wl.coarse[k] for k in ("zf", "uc", "vc", "wc"))
+    res = {}
+    for prec in ("fp32", "fp64"):
+        dt_ = torch.float32 if prec == "fp32" else torch.float64
+        es = 4 if prec == "fp32" else 8
+        ip = ch.Interp(wl.shape, wl.h, uc.shape, zf, precision=prec, stream=stream)
+        u0, v0, w0 = ip.apply(*(torch.from_numpy(a).to("cuda", dt_) for a in (uc, vc, wc)))
+        ip.close()
+        C = torch.from_numpy(wl.C).to("cuda", dt_)
+        P = torch.zeros(wl.shape, dtype=dt_, device="cuda")
+        Pold = torch.zeros_like(P)
+        p = ch.Poisson(wl.shape, wl.h, z_walls=True, precision=prec, stream=stream)
+        u, v, w = u0.clone(), v0.clone(), w0.clone()
+        for _ in range(args.warmup):
+            u.copy_(u0), v.copy_(v0), w.copy_(w0)
+            p.step(C, u, v, w, P, Pold, 1000.0, 1.0, wl.dt)
+        torch.cuda.synchronize()
+        n = args.pressure_steps
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * n)]
+        for k in range(n):
+            u.copy_(u0), v.copy_(v0), w.copy_(w0)
+            ev[2 * k].record(stream)
+            p.step(C, u, v, w, P, Pold, 1000.0, 1.0, wl.dt)
+            ev[2 * k + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(n)) / n
+        h = wl.h
+        div = ((torch.roll(u, -1, 2) - u) + (torch.roll(v, -1, 1) - v) + (w[1:] - w[:-1])) / h
+        div0 = ((torch.roll(u0, -1, 2) - u0) + (torch.roll(v0, -1, 1) - v0) + (w0[1:] - w0[:-1])) / h
+        nbytes = pressure_bytes_per_step(wl.points, es)
+        res[prec] = {"ms_per_step": round(ms, 4),
+                     "Gpts_per_s": round(wl.points / (ms * 1e-3) / 1e9, 3),
+                     "max_div_after_over_before": float(div.abs().max() / div0.abs().max()),
+                     "roofline": {"bound": "hbm", "bytes_per_step": nbytes,
+                                  "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                                  "peak_GBs": HBM_PEAK_GBS,
+                                  "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}}
+        p.close()
+        del u, v, w, u0, v0, w0, C, P, Pold
+    return {"workload": "512^3 cells, periodic x,y, walls in z; C of the 1000-drop workload, "
+                        "u* its transferred velocity, rho1/rho2 = 1000, dt = 1e-4",
+            "points": wl.points, "steps": args.pressure_steps,
+            "fp32": res["fp32"], "fp64": res["fp64"]}
+
+
 def bench_large(args, stream):
     """The 1536^3 periodic box in single precision (inputs built on the GPU):
     FP32 throughput over a few steps, and the whole box's mass drift."""
@@ -329,6 +399,7 @@ def main():
     ap.add_argument("--multires-steps", type=int, default=100)
     ap.add_argument("--large-steps", type=int, default=10)
     ap.add_argument("--explicit-steps", type=int, default=200)
+    ap.add_argument("--pressure-steps", type=int, default=20)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-ensemble and multiple-resolution lines")
     ap.add_argument("--counter-probe", action="store_true")
@@ -390,7 +461,9 @@ def main():
                     cells=cells, label_ms=label_ms)
 
     r32 = timed("fp32")
+    progress("256^3 fp32 done")
     r64 = timed("fp64")
+    progress("256^3 fp64 done")
     nstep = args.steps
     v32 = pts * nstep / (r32["ms"] * 1e-3) / 1e9
     v64 = pts * nstep / (r64["ms"] * 1e-3) / 1e9
@@ -476,9 +549,15 @@ def main():
 
     if not args.no_extra:
         line["batched"] = bench_ensemble(args, stream)
+        progress("ensemble done")
         line["multires"] = bench_multires(args, stream)
+        progress("multiple resolution done")
+        line["pressure"] = bench_pressure(args, stream)
+        progress("pressure step done")
         line["large"] = bench_large(args, stream)
+        progress("1536^3 done")
         line["explicit25"] = bench_explicit25(args, stream, line)
+        progress("explicit 25-point done")
 
     if not args.no_cpu_baseline:
         # the FP64 oracle on the same workload, whole RK3 steps until about
@@ -497,6 +576,7 @@ def main():
                                 "cores": oracle.threads(), "kind": "oracle",
                                 "sample": f"{steps} RK3 step(s) of the same {wl.shape[2]}^3 "
                                           f"workload in FP64, {el:.1f} s"}
+        progress("cpu baseline done")
     print(json.dumps(line), flush=True)
 
 

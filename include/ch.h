@@ -106,6 +106,7 @@ typedef struct {
 typedef struct ch_state ch_state;
 typedef struct ch_batch ch_batch;
 typedef struct ch_interp ch_interp;
+typedef struct ch_poisson ch_poisson;
 
 /* Fill *opt with the defaults above. */
 void ch_default_opts(ch_opts* opt);
@@ -242,6 +243,39 @@ ch_status ch_interp_project_c(ch_interp* ip, const void* Cf, void* Cc);
  * advances C by one RK3 step. */
 ch_status ch_step_multires(ch_state* s, ch_interp* ip, const void* uc, const void* vc,
                            const void* wc, double dt, int nsteps);
+
+/* ---- split-density pressure step (sec. 3.2: eq-poi, eq-split, eq-newpoi,
+ * eq-u) --------------------------------------------------------------------
+ * The pressure projection of the coupled solver on the uniform staggered
+ * mesh of the CH field: P and C at the nx x ny x nz cell centres (spacing
+ * h, x fastest), u / v / w on the low faces of the cells, periodic in x and
+ * y; z periodic (z_walls = 0: w has nz planes) or between two walls
+ * (z_walls = 1: w has nz + 1 planes, zero on both walls, dP/dz = 0 there).
+ * The density is rho = rho2 + (rho1 - rho2) clamp(C, 0, 1) (rho2 <= rho1),
+ * taken on a face as the mean of its two cells.  Creation makes the hipFFT
+ * plans and the work arrays (three fields and a spectrum); nx, ny, nz >= 2
+ * (CH_EINVAL), fewer than 2^31 cells (CH_EUNSUPPORTED).  Device memory in
+ * the given precision; work is enqueued on the handle's stream.
+ *
+ * ch_poisson_solve: P with lap P = rhs - mean(rhs) and zero mean, for the
+ * 7-point Laplacian of these face differences (transforms in x and y; along
+ * z a tridiagonal solve per mode between walls, the 3-D transform when
+ * periodic).  rhs is not modified.
+ *
+ * ch_pressure_step: with P = P^l, Pold = P^{l-1} and u, v, w = u*:
+ *   Phat = 2 P^l - P^{l-1};
+ *   lap P^{l+1} = div[(1 - rho2/rho) grad Phat] + (rho2/dt) div u*;
+ *   u^{l+1} = u* - dt [grad P^{l+1} / rho2 + (1/rho - 1/rho2) grad Phat];
+ * on return P = P^{l+1}, Pold = P^l and u, v, w = u^{l+1} (the wall planes of
+ * w are not written).  The new velocity is discretely divergence-free for
+ * any density and pressure history.  CH_EINVAL unless 0 < rho2 <= rho1 and
+ * dt > 0. */
+ch_status ch_poisson_create(const ch_grid* g, int z_walls, int precision, ch_poisson** out);
+ch_status ch_poisson_set_stream(ch_poisson* p, void* stream);
+ch_status ch_poisson_solve(ch_poisson* p, const void* rhs, void* P);
+ch_status ch_pressure_step(ch_poisson* p, const void* C, double rho1, double rho2, double dt,
+                           void* u, void* v, void* w, void* P, void* Pold);
+void ch_poisson_destroy(ch_poisson* p);
 
 /* ---- drop diagnostics (sec. 4) -------------------------------------------
  * The drops of a box for the drop-size statistics: cells with

@@ -91,6 +91,11 @@ SIGNATURES = {
                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "ch_batch_drops": (_I, [_VP, _I, _D, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "ch_poisson_create": (_I, [ctypes.POINTER(Grid), _I, _I, ctypes.POINTER(_VP)]),
+    "ch_poisson_set_stream": (_I, [_VP, _VP]),
+    "ch_poisson_solve": (_I, [_VP, _VP, _VP]),
+    "ch_pressure_step": (_I, [_VP, _VP, _D, _D, _D, _VP, _VP, _VP, _VP, _VP]),
+    "ch_poisson_destroy": (None, [_VP]),
     "ch_interp_set_solenoidal": (_I, [_VP, _I]),
     "ch_interp_closure": (_I, [_VP, ctypes.POINTER(_D)]),
     "ch_interp_project_c": (_I, [_VP, _VP, _VP]),
@@ -492,6 +497,64 @@ class Interp:
     def close(self):
         if getattr(self, "_h", None):
             lib().ch_interp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Poisson(_StreamMixin):
+    """Split-density pressure step on an (nz, ny, nx) cell mesh of spacing h,
+    periodic in x and y, z periodic or between walls (z_walls)."""
+
+    def __init__(self, shape, h, z_walls=False, precision="fp64", stream=None):
+        nz, ny, nx = shape
+        self.shape = tuple(shape)
+        self.z_walls = bool(z_walls)
+        self.dtype = _dtype(_prec(precision))
+        g = Grid(nx, ny, nz, h)
+        handle = ctypes.c_void_p()
+        _check(lib().ch_poisson_create(ctypes.byref(g), 1 if z_walls else 0, _prec(precision),
+                                       ctypes.byref(handle)))
+        self._h = handle
+        self.stream = stream
+        _check(lib().ch_poisson_set_stream(self._h,
+                                           ctypes.c_void_p(stream.cuda_stream if stream else 0)))
+
+    def w_shape(self):
+        nz, ny, nx = self.shape
+        return (nz + 1, ny, nx) if self.z_walls else self.shape
+
+    def solve(self, rhs, out=None):
+        """Zero-mean P with lap P = rhs - mean(rhs)."""
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, device="cuda")
+        a = _dev_tensor(rhs, self.dtype, self.shape, "rhs")
+        b = _dev_tensor(out, self.dtype, self.shape, "P")
+        self._enter()
+        _check(lib().ch_poisson_solve(self._h, a, b))
+        self._leave()
+        return out
+
+    def step(self, C, u, v, w, P, Pold, rho1, rho2, dt):
+        """In place: u, v, w <- u^{l+1}; P <- P^{l+1}; Pold <- P^l."""
+        ptrs = [_dev_tensor(C, self.dtype, self.shape, "C"),
+                _dev_tensor(u, self.dtype, self.shape, "u"),
+                _dev_tensor(v, self.dtype, self.shape, "v"),
+                _dev_tensor(w, self.dtype, self.w_shape(), "w"),
+                _dev_tensor(P, self.dtype, self.shape, "P"),
+                _dev_tensor(Pold, self.dtype, self.shape, "Pold")]
+        self._enter()
+        _check(lib().ch_pressure_step(self._h, ptrs[0], float(rho1), float(rho2), float(dt),
+                                      *ptrs[1:]))
+        self._leave()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ch_poisson_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -101,4 +101,26 @@ hipError_t launch_drops_label(hipStream_t st, const void* C, int nx, int ny, int
 hipError_t launch_drops_count(hipStream_t st, const int* lab, int64_t n, int* cnt, int cap,
                               int* oroot, int* ocnt, int* count);
 
+// Split-density pressure step: mesh, densities of the two phases, time step.
+struct PressArgs {
+    int nx, ny, nz, zwalls;
+    double h, rho1, rho2, dt;
+};
+
+// Phat = 2 P - Pold and Pold <- P; the eq-newpoi right-hand side; the solve
+// in spectral space (z walls: per-mode Thomas along z after 2-D transforms;
+// periodic z: division by the eigenvalues of the 3-D transform), scaled for
+// the unnormalised inverse transform; the eq-u velocity update.
+template <typename T>
+hipError_t launch_press_prep(hipStream_t st, const void* P, void* Pold, void* phat, int64_t n);
+template <typename T>
+hipError_t launch_press_rhs(hipStream_t st, const PressArgs& a, const void* C, const void* phat,
+                            const void* u, const void* v, const void* w, void* rhs);
+template <typename T>
+hipError_t launch_press_solve(hipStream_t st, int zwalls, void* spec, void* cp, int nx, int ny,
+                              int nz, double h);
+template <typename T>
+hipError_t launch_press_update(hipStream_t st, const PressArgs& a, const void* C, const void* P,
+                               const void* phat, void* u, void* v, void* w);
+
 }  // namespace chk

@@ -629,6 +629,229 @@ k_ccl_compact(const int* __restrict__ lab, const int* __restrict__ cnt, int64_t 
         }
 }
 
+// Split-density pressure step (sec. 3.2: eq-split, eq-newpoi, eq-u) on the
+// staggered mesh: P and C at the cells, u / v / w on the low faces of the
+// cells (w has nz + 1 planes between walls, zero on both).  The density is
+// rho2 + (rho1 - rho2) clamp(C, 0, 1); a face takes the mean of its two
+// cells.
+template <typename T>
+__device__ __forceinline__ T press_rho(const PressArgs& a, T c)
+{
+    const T cc = c < T(0) ? T(0) : (c > T(1) ? T(1) : c);
+    return T(a.rho2) + T(a.rho1 - a.rho2) * cc;
+}
+
+// Phat = 2 P - Pold, then Pold <- P (the next step's history).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_press_prep(const T* __restrict__ P, T* __restrict__ Pold, T* __restrict__ phat, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T p = P[i];
+        phat[i] = T(2) * p - Pold[i];
+        Pold[i] = p;
+    }
+}
+
+// Right-hand side of eq-newpoi at every cell, one (z, y) row per work-group:
+// div[(1 - rho2/rho_f) grad Phat] + (rho2/dt) div u*.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_press_rhs(PressArgs a, const T* __restrict__ C, const T* __restrict__ ph,
+            const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
+            T* __restrict__ rhs)
+{
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int64_t plane = (int64_t)nx * ny;
+    const T ih = T(1.0 / a.h), r2 = T(a.rho2), sdiv = T(a.rho2 / a.dt);
+    for (int64_t row = blockIdx.x; row < (int64_t)ny * nz; row += gridDim.x) {
+        const int z = (int)(row / ny), y = (int)(row - (int64_t)z * ny);
+        const int ym = y > 0 ? y - 1 : ny - 1, yp = y + 1 < ny ? y + 1 : 0;
+        const int zm = z > 0 ? z - 1 : nz - 1, zp = z + 1 < nz ? z + 1 : 0;
+        for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+            const int xm = x > 0 ? x - 1 : nx - 1, xp = x + 1 < nx ? x + 1 : 0;
+            const int64_t c = row * nx + x;
+            const T rc = press_rho(a, C[c]), pc = ph[c];
+            // flux through the face between cells c and nb (nb on the + side
+            // when s = 1): (1 - rho2/rho_f) (ph[hi] - ph[lo]) / h
+            auto flux = [&](int64_t nb, int s) {
+                const T rf = T(0.5) * (rc + press_rho(a, C[nb]));
+                const T g = s > 0 ? ph[nb] - pc : pc - ph[nb];
+                return (T(1) - r2 / rf) * g * ih;
+            };
+            T d = flux(row * nx + xp, 1) - flux(row * nx + xm, -1)
+                + flux(((int64_t)z * ny + yp) * nx + x, 1) - flux(((int64_t)z * ny + ym) * nx + x, -1);
+            if (!a.zwalls || z + 1 < nz) d += flux(c - (int64_t)z * plane + (int64_t)zp * plane, 1);
+            if (!a.zwalls || z > 0) d -= flux(c - (int64_t)z * plane + (int64_t)zm * plane, -1);
+            const T du = u[row * nx + xp] - u[c];
+            const T dv = v[((int64_t)z * ny + yp) * nx + x] - v[c];
+            const T dw = a.zwalls ? w[c + plane] - w[c]
+                                  : w[(int64_t)zp * plane + (int64_t)y * nx + x] - w[c];
+            rhs[c] = d * ih + sdiv * (du + dv + dw) * ih;
+        }
+    }
+}
+
+// Solve along z per (ky, kx) mode after the 2-D transforms in x and y
+// (between walls): (1/h^2)(p[k+1] - 2 p[k] + p[k-1]) + lxy p[k] = f[k] with
+// p[-1] = p[0], p[nz] = p[nz-1] (dP/dz = 0), by the Thomas algorithm (the
+// rows are diagonally dominant for lxy < 0).  The mean mode (lxy = 0) is
+// singular: its mean over z is removed from f, then p[0] = 0 and the rows
+// 0 .. nz-2 give p[1 .. nz-1] by p[k+1] = 2 p[k] - p[k-1] + h^2 f[k]
+// (p[-1] = p[0]), and the mean of p is removed.  Spectra are [nz][ny][nxh]
+// complex (re, im interleaved); cp holds nz x nmodes reals of scratch.  The
+// result is scaled by `scale` (the inverse transform's 1 / (nx ny)).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_press_tri(T* __restrict__ spec, T* __restrict__ cp, int nx, int ny, int nz, double h,
+            double scale)
+{
+    const int nxh = nx / 2 + 1;
+    const int64_t nm = (int64_t)ny * nxh;
+    const double PI = 3.14159265358979323846;
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nm;
+         m += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(m / nxh), i = (int)(m - (int64_t)j * nxh);
+        const double sx = sin(PI * i / nx), sy = sin(PI * j / ny);
+        const T ih2 = T(1.0 / (h * h));
+        const T lxy = T(-4.0 / (h * h) * (sx * sx + sy * sy));
+        T* f = spec + 2 * m;            // f[k] at f + 2 k nm
+        const int64_t st = 2 * nm;
+        const T sc = T(scale);
+        if (i == 0 && j == 0) {
+            T mr = T(0), mi = T(0);
+            for (int k = 0; k < nz; ++k) {
+                mr += f[k * st];
+                mi += f[k * st + 1];
+            }
+            mr /= T(nz);
+            mi /= T(nz);
+            const T h2 = T(h * h);
+            T pr = T(0), pi = T(0), qr = T(0), qi = T(0);   // p[k-1], p[k]
+            T sr = T(0), si = T(0);
+            for (int k = 0; k < nz; ++k) {
+                const T fr = f[k * st] - mr, fi = f[k * st + 1] - mi;
+                f[k * st] = qr;         // p[k]
+                f[k * st + 1] = qi;
+                sr += qr;
+                si += qi;
+                const T lr = k == 0 ? qr : pr, li = k == 0 ? qi : pi;
+                const T nr = T(2) * qr - lr + h2 * fr, ni = T(2) * qi - li + h2 * fi;
+                pr = qr;
+                pi = qi;
+                qr = nr;
+                qi = ni;
+            }
+            sr /= T(nz);
+            si /= T(nz);
+            for (int k = 0; k < nz; ++k) {
+                f[k * st] = (f[k * st] - sr) * sc;
+                f[k * st + 1] = (f[k * st + 1] - si) * sc;
+            }
+            continue;
+        }
+        // forward sweep: c'_k into cp, d'_k into f; the right-hand sides of
+        // PK planes are loaded before they are used
+        constexpr int PK = sizeof(T) == 4 ? 8 : 4;
+        T cprev = T(0), dr = T(0), di = T(0);
+        for (int k0 = 0; k0 < nz; k0 += PK) {
+            T fr[PK], fi[PK];
+#pragma unroll
+            for (int q = 0; q < PK; ++q) {
+                const int k = k0 + q < nz ? k0 + q : nz - 1;
+                fr[q] = f[k * st];
+                fi[q] = f[k * st + 1];
+            }
+#pragma unroll
+            for (int q = 0; q < PK; ++q) {
+                const int k = k0 + q;
+                if (k >= nz) break;
+                const T b = lxy - (k == 0 || k == nz - 1 ? ih2 : T(2) * ih2);
+                const T den = b - (k > 0 ? ih2 * cprev : T(0));
+                const T c = k + 1 < nz ? ih2 / den : T(0);
+                dr = (fr[q] - (k > 0 ? ih2 * dr : T(0))) / den;
+                di = (fi[q] - (k > 0 ? ih2 * di : T(0))) / den;
+                f[k * st] = dr;
+                f[k * st + 1] = di;
+                cp[k * nm + m] = c;
+                cprev = c;
+            }
+        }
+        // back substitution, PK planes loaded at a time
+        T xr = T(0), xi = T(0);
+        for (int k1 = nz - 1; k1 >= 0; k1 -= PK) {
+            T fr[PK], fi[PK], cc[PK];
+#pragma unroll
+            for (int q = 0; q < PK; ++q) {
+                const int k = k1 - q >= 0 ? k1 - q : 0;
+                fr[q] = f[k * st];
+                fi[q] = f[k * st + 1];
+                cc[q] = cp[k * nm + m];
+            }
+#pragma unroll
+            for (int q = 0; q < PK; ++q) {
+                const int k = k1 - q;
+                if (k < 0) break;
+                xr = fr[q] - (k + 1 < nz ? cc[q] * xr : T(0));
+                xi = fi[q] - (k + 1 < nz ? cc[q] * xi : T(0));
+                f[k * st] = xr * sc;
+                f[k * st + 1] = xi * sc;
+            }
+        }
+    }
+}
+
+// Periodic z: divide the 3-D spectrum [nz][ny][nxh] by the eigenvalue of the
+// 7-point Laplacian, zero mode to 0, scaled by 1 / (nx ny nz).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_press_div(T* __restrict__ spec, int nx, int ny, int nz, double h, double scale)
+{
+    const int nxh = nx / 2 + 1;
+    const int64_t n = (int64_t)nz * ny * nxh;
+    const double PI = 3.14159265358979323846;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e % nxh);
+        const int64_t r = e / nxh;
+        const int j = (int)(r % ny), k = (int)(r / ny);
+        const double sx = sin(PI * i / nx), sy = sin(PI * j / ny), sz = sin(PI * k / nz);
+        const double lam = -4.0 / (h * h) * (sx * sx + sy * sy + sz * sz);
+        const T f = (e == 0) ? T(0) : T(scale / lam);
+        spec[2 * e] *= f;
+        spec[2 * e + 1] *= f;
+    }
+}
+
+// eq-u on the low faces of every cell (the wall faces of z stay as they are).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_press_update(PressArgs a, const T* __restrict__ C, const T* __restrict__ P,
+               const T* __restrict__ ph, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w)
+{
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int64_t plane = (int64_t)nx * ny;
+    const T ih = T(1.0 / a.h), ir2 = T(1.0 / a.rho2), dt = T(a.dt);
+    for (int64_t row = blockIdx.x; row < (int64_t)ny * nz; row += gridDim.x) {
+        const int z = (int)(row / ny), y = (int)(row - (int64_t)z * ny);
+        const int ym = y > 0 ? y - 1 : ny - 1, zm = z > 0 ? z - 1 : nz - 1;
+        for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+            const int xm = x > 0 ? x - 1 : nx - 1;
+            const int64_t c = row * nx + x;
+            const T rc = press_rho(a, C[c]), pc = P[c], hc = ph[c];
+            auto corr = [&](int64_t nb) {   // face between nb (low side) and c
+                const T rf = T(0.5) * (rc + press_rho(a, C[nb]));
+                return dt * ((pc - P[nb]) * ih * ir2 + (T(1) / rf - ir2) * (hc - ph[nb]) * ih);
+            };
+            u[c] -= corr(row * nx + xm);
+            v[c] -= corr(((int64_t)z * ny + ym) * nx + x);
+            if (!a.zwalls) w[c] -= corr((int64_t)zm * plane + (int64_t)y * nx + x);
+            else if (z > 0) w[c] -= corr(c - plane);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers (declared in ch_kernels.h)
 // ---------------------------------------------------------------------------
@@ -815,6 +1038,52 @@ hipError_t launch_drops_count(hipStream_t st, const int* lab, int64_t n, int* cn
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_press_prep(hipStream_t st, const void* P, void* Pold, void* phat, int64_t n)
+{
+    hipLaunchKernelGGL((k_press_prep<T>), dim3(grid_for(n)), dim3(256), 0, st, (const T*)P,
+                       (T*)Pold, (T*)phat, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_press_rhs(hipStream_t st, const PressArgs& a, const void* C, const void* phat,
+                            const void* u, const void* v, const void* w, void* rhs)
+{
+    const int64_t rows = (int64_t)a.ny * a.nz;
+    hipLaunchKernelGGL((k_press_rhs<T>), dim3((unsigned)(rows < 262144 ? rows : 262144)),
+                       dim3(256), 0, st, a, (const T*)C, (const T*)phat, (const T*)u,
+                       (const T*)v, (const T*)w, (T*)rhs);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_press_solve(hipStream_t st, int zwalls, void* spec, void* cp, int nx, int ny,
+                              int nz, double h)
+{
+    if (zwalls) {
+        const int64_t nm = (int64_t)ny * (nx / 2 + 1);
+        hipLaunchKernelGGL((k_press_tri<T>), dim3(grid_for(nm)), dim3(256), 0, st, (T*)spec,
+                           (T*)cp, nx, ny, nz, h, 1.0 / ((double)nx * ny));
+    } else {
+        const int64_t n = (int64_t)nz * ny * (nx / 2 + 1);
+        hipLaunchKernelGGL((k_press_div<T>), dim3(grid_for(n)), dim3(256), 0, st, (T*)spec, nx,
+                           ny, nz, h, 1.0 / ((double)nx * ny * nz));
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_press_update(hipStream_t st, const PressArgs& a, const void* C, const void* P,
+                               const void* phat, void* u, void* v, void* w)
+{
+    const int64_t rows = (int64_t)a.ny * a.nz;
+    hipLaunchKernelGGL((k_press_update<T>), dim3((unsigned)(rows < 262144 ? rows : 262144)),
+                       dim3(256), 0, st, a, (const T*)C, (const T*)P, (const T*)phat, (T*)u,
+                       (T*)v, (T*)w);
+    return hipGetLastError();
+}
+
 #define CH_INSTANTIATE(T, A)                                                                    \
     template hipError_t launch_pass_x<T, A>(int, int, int, size_t, hipStream_t,                 \
                                             const chd::BoxDesc*, int,                           \
@@ -850,5 +1119,18 @@ template hipError_t launch_scan<double>(hipStream_t, int, void*, const void*, in
                                         double, double*);
 template hipError_t launch_scan<float>(hipStream_t, int, void*, const void*, int, int, int,
                                        double, double*);
+
+template hipError_t launch_press_prep<double>(hipStream_t, const void*, void*, void*, int64_t);
+template hipError_t launch_press_rhs<double>(hipStream_t, const PressArgs&, const void*, const void*,
+                                          const void*, const void*, const void*, void*);
+template hipError_t launch_press_solve<double>(hipStream_t, int, void*, void*, int, int, int, double);
+template hipError_t launch_press_update<double>(hipStream_t, const PressArgs&, const void*,
+                                             const void*, const void*, void*, void*, void*);
+template hipError_t launch_press_prep<float>(hipStream_t, const void*, void*, void*, int64_t);
+template hipError_t launch_press_rhs<float>(hipStream_t, const PressArgs&, const void*, const void*,
+                                          const void*, const void*, const void*, void*);
+template hipError_t launch_press_solve<float>(hipStream_t, int, void*, void*, int, int, int, double);
+template hipError_t launch_press_update<float>(hipStream_t, const PressArgs&, const void*,
+                                             const void*, const void*, void*, void*, void*);
 
 }  // namespace chk

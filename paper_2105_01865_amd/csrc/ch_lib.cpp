@@ -6,6 +6,7 @@
 // (x: explicit terms + RHS + x solve, y solve, z solve + update); with a
 // non-null stream a whole step is captured once as a HIP graph and replayed.
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <atomic>
@@ -841,6 +842,18 @@ struct ch_batch {
 struct ch_interp {
     InterpData d;
 };
+// Split-density pressure step: mesh, transforms and work arrays.
+struct ch_poisson {
+    int nx = 0, ny = 0, nz = 0, zwalls = 0, prec = CH_FP64;
+    double h = 0.0;
+    hipStream_t stream = nullptr;
+    hipfftHandle fwd = 0, inv = 0;
+    bool have_fwd = false, have_inv = false;
+    void* phat = nullptr;   // 2 P^l - P^{l-1}
+    void* rhs = nullptr;    // eq-newpoi right-hand side
+    void* spec = nullptr;   // its transform, nz x ny x (nx/2 + 1) complex
+    void* cp = nullptr;     // Thomas scratch, nz x ny x (nx/2 + 1) reals
+};
 
 extern "C" {
 
@@ -1234,6 +1247,146 @@ ch_status ch_batch_drops(ch_batch* b, int box, double threshold, int64_t cap, in
 {
     CHECK_STATE(b);
     return drops(b->e, box, threshold, cap, ndrops, root, cells);
+}
+
+static void poisson_free(ch_poisson* p)
+{
+    if (p->have_fwd) (void)hipfftDestroy(p->fwd);
+    if (p->have_inv) (void)hipfftDestroy(p->inv);
+    void* bufs[4] = {p->phat, p->rhs, p->spec, p->cp};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    delete p;
+}
+
+ch_status ch_poisson_create(const ch_grid* g, int z_walls, int precision, ch_poisson** out)
+{
+    if (!g || !out) return fail(CH_EINVAL, "null argument");
+    *out = nullptr;
+    if (precision != CH_FP64 && precision != CH_FP32)
+        return fail(CH_EINVAL, "unknown precision %d", precision);
+    if (g->nx < 2 || g->ny < 2 || g->nz < 2 || !(g->h > 0.0))
+        return fail(CH_EINVAL, "the pressure mesh needs at least 2 cells per axis and h > 0");
+    if ((double)g->nx * g->ny * (g->nz + 1) >= 2147483647.0)
+        return fail(CH_EUNSUPPORTED, "pressure mesh of 2^31 cells or more");
+    ch_poisson* p = new (std::nothrow) ch_poisson();
+    if (!p) return fail(CH_ENOMEM, "host allocation failed");
+    p->nx = (int)g->nx;
+    p->ny = (int)g->ny;
+    p->nz = (int)g->nz;
+    p->h = g->h;
+    p->zwalls = z_walls ? 1 : 0;
+    p->prec = precision;
+    const size_t es = precision == CH_FP64 ? 8 : 4;
+    const size_t n = (size_t)p->nx * p->ny * p->nz;
+    const size_t nm = (size_t)p->ny * (p->nx / 2 + 1);
+    const hipfftType tf = precision == CH_FP64 ? HIPFFT_D2Z : HIPFFT_R2C;
+    const hipfftType ti = precision == CH_FP64 ? HIPFFT_Z2D : HIPFFT_C2R;
+    hipfftResult r1, r2;
+    if (p->zwalls) {
+        int dims[2] = {p->ny, p->nx};
+        r1 = hipfftPlanMany(&p->fwd, 2, dims, nullptr, 1, 0, nullptr, 1, 0, tf, p->nz);
+        p->have_fwd = r1 == HIPFFT_SUCCESS;
+        r2 = hipfftPlanMany(&p->inv, 2, dims, nullptr, 1, 0, nullptr, 1, 0, ti, p->nz);
+        p->have_inv = r2 == HIPFFT_SUCCESS;
+    } else {
+        r1 = hipfftPlan3d(&p->fwd, p->nz, p->ny, p->nx, tf);
+        p->have_fwd = r1 == HIPFFT_SUCCESS;
+        r2 = hipfftPlan3d(&p->inv, p->nz, p->ny, p->nx, ti);
+        p->have_inv = r2 == HIPFFT_SUCCESS;
+    }
+    if (!p->have_fwd || !p->have_inv) {
+        poisson_free(p);
+        return fail(CH_EHIP, "hipFFT plan creation failed (%d, %d)", (int)r1, (int)r2);
+    }
+    if (hipMalloc(&p->phat, n * es) != hipSuccess || hipMalloc(&p->rhs, n * es) != hipSuccess ||
+        hipMalloc(&p->spec, 2 * nm * p->nz * es) != hipSuccess ||
+        (p->zwalls && hipMalloc(&p->cp, nm * p->nz * es) != hipSuccess)) {
+        (void)hipGetLastError();
+        poisson_free(p);
+        return fail(CH_ENOMEM, "cannot allocate the pressure work arrays");
+    }
+    reg(p);
+    *out = p;
+    return CH_OK;
+}
+
+ch_status ch_poisson_set_stream(ch_poisson* p, void* stream)
+{
+    CHECK_STATE(p);
+    p->stream = (hipStream_t)stream;
+    return CH_OK;
+}
+
+static hipError_t poisson_enqueue(ch_poisson* p, const void* rhs, void* P)
+{
+    if (hipfftSetStream(p->fwd, p->stream) != HIPFFT_SUCCESS ||
+        hipfftSetStream(p->inv, p->stream) != HIPFFT_SUCCESS)
+        return hipErrorLaunchFailure;
+    hipfftResult r;
+    if (p->prec == CH_FP64)
+        r = hipfftExecD2Z(p->fwd, (hipfftDoubleReal*)const_cast<void*>(rhs),
+                          (hipfftDoubleComplex*)p->spec);
+    else
+        r = hipfftExecR2C(p->fwd, (hipfftReal*)const_cast<void*>(rhs), (hipfftComplex*)p->spec);
+    if (r != HIPFFT_SUCCESS) return hipErrorLaunchFailure;
+    hipError_t err = p->prec == CH_FP64
+        ? chk::launch_press_solve<double>(p->stream, p->zwalls, p->spec, p->cp, p->nx, p->ny,
+                                          p->nz, p->h)
+        : chk::launch_press_solve<float>(p->stream, p->zwalls, p->spec, p->cp, p->nx, p->ny,
+                                         p->nz, p->h);
+    if (err != hipSuccess) return err;
+    if (p->prec == CH_FP64)
+        r = hipfftExecZ2D(p->inv, (hipfftDoubleComplex*)p->spec, (hipfftDoubleReal*)P);
+    else
+        r = hipfftExecC2R(p->inv, (hipfftComplex*)p->spec, (hipfftReal*)P);
+    return r == HIPFFT_SUCCESS ? hipSuccess : hipErrorLaunchFailure;
+}
+
+ch_status ch_poisson_solve(ch_poisson* p, const void* rhs, void* P)
+{
+    CHECK_STATE(p);
+    if (!rhs || !P) return fail(CH_EINVAL, "null pointer");
+    hipError_t err = poisson_enqueue(p, rhs, P);
+    if (err != hipSuccess) return fail(CH_EHIP, "Poisson solve failed: %s", hipGetErrorString(err));
+    return CH_OK;
+}
+
+ch_status ch_pressure_step(ch_poisson* p, const void* C, double rho1, double rho2, double dt,
+                           void* u, void* v, void* w, void* P, void* Pold)
+{
+    CHECK_STATE(p);
+    if (!C || !u || !v || !w || !P || !Pold) return fail(CH_EINVAL, "null pointer");
+    if (!(rho2 > 0.0) || !(rho1 >= rho2) || !(dt > 0.0) || !std::isfinite(rho1))
+        return fail(CH_EINVAL, "need 0 < rho2 <= rho1 (finite) and dt > 0");
+    const chk::PressArgs a{p->nx, p->ny, p->nz, p->zwalls, p->h, rho1, rho2, dt};
+    const int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    hipError_t err;
+    if (p->prec == CH_FP64) {
+        err = chk::launch_press_prep<double>(p->stream, P, Pold, p->phat, n);
+        if (err == hipSuccess)
+            err = chk::launch_press_rhs<double>(p->stream, a, C, p->phat, u, v, w, p->rhs);
+    } else {
+        err = chk::launch_press_prep<float>(p->stream, P, Pold, p->phat, n);
+        if (err == hipSuccess)
+            err = chk::launch_press_rhs<float>(p->stream, a, C, p->phat, u, v, w, p->rhs);
+    }
+    if (err == hipSuccess) err = poisson_enqueue(p, p->rhs, P);
+    if (err == hipSuccess)
+        err = p->prec == CH_FP64
+            ? chk::launch_press_update<double>(p->stream, a, C, P, p->phat, u, v, w)
+            : chk::launch_press_update<float>(p->stream, a, C, P, p->phat, u, v, w);
+    if (err != hipSuccess) return fail(CH_EHIP, "pressure step failed: %s", hipGetErrorString(err));
+    return CH_OK;
+}
+
+void ch_poisson_destroy(ch_poisson* p)
+{
+    if (!p || !live(p)) return;
+    unreg(p);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    else (void)hipDeviceSynchronize();
+    poisson_free(p);
 }
 
 ch_status ch_step_multires(ch_state* s, ch_interp* ip, const void* uc, const void* vc,
