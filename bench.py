@@ -541,7 +541,13 @@ def main():
                      "avg_launch_us": round(x_avg_s * 1e6, 2),
                      "hbm_view": {"bytes_per_point": x_pass_bytes_per_point(4),
                                   "achieved_gbs": round(x_gbs, 1),
-                                  "frac_of_8000": round(x_gbs / HBM_PEAK_GBS, 4)},
+                                  "frac_of_8000": round(x_gbs / HBM_PEAK_GBS, 4),
+                                  # measured bytes (counters) over the same launch time
+                                  "measured_gbs": (round(traffic / x_avg_s / 1e9, 1)
+                                                   if traffic else None),
+                                  "measured_frac_of_8000": (round(traffic / x_avg_s / 1e9
+                                                                  / HBM_PEAK_GBS, 4)
+                                                            if traffic else None)},
                      "window": f"{args.profile_steps} profiled steps, HIP events per launch"},
         "kernels_fp32": kern(r32),
         "kernels_fp64": kern(r64),

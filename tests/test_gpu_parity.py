@@ -315,3 +315,28 @@ def test_explicit_and_implicit_steps_interleave():
     got = s.get_field().cpu().numpy()
     s.close()
     assert rel(got, ref) <= 5 * TOL64
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+@pytest.mark.parametrize("kappa", [4.0, 3.0])
+def test_flat_interface_equilibrium_stays_on_the_gpu(axis, kappa):
+    """The scheme's discrete flat-interface equilibrium (a slab, Newton-solved
+    on one periodic line) extruded along the other two axes, u = 0: 20 steps
+    at dt = 1e-3 leave it in place to 1e-12 (FP64); FP32 storage keeps it to
+    within its own rounding (1e-6)."""
+    from tests.test_oracle_pins import _flat_equilibrium
+    n = 64
+    h = 1.0 / n
+    prof = _flat_equilibrium(n, h, h, kappa)
+    shape = (n, 16, 24) if axis == 0 else (16, 24, n)
+    C = np.broadcast_to(prof[:, None, None] if axis == 0 else prof[None, None, :],
+                        shape).copy()
+    zero = np.zeros_like(C)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        print(f"[gpu] flat interface along axis {axis}, kappa {kappa}, {prec}", flush=True)
+        got, _ = run_gpu(C, zero, zero, zero, h, h, 0.9 / h, 1e-3, 20, precision=prec,
+                         kappa=kappa)
+        ref = C if prec == "fp64" else C.astype(np.float32).astype(np.float64)
+        d = float(np.abs(got - ref).max())
+        print(f"  max |dC| {d:.2e}")
+        assert d <= tol
