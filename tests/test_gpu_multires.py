@@ -36,7 +36,9 @@ def _coarse(seed, nc, alpha=2.0):
 
 @pytest.mark.parametrize("fine,nc", [((32, 32, 32), (12, 16, 16)),       # config 3, shrunk
                                      ((36, 40, 48), (10, 16, 20)),       # uneven ratios
-                                     ((24, 24, 24), (24, 24, 24))])      # same counts
+                                     ((24, 24, 24), (24, 24, 24)),       # same counts
+                                     ((20, 18, 30), (8, 12, 16)),        # x targets not 4k
+                                     ((16, 12, 9), (6, 8, 12))])         # fewer fine than coarse
 def test_transfer_matches_oracle(fine, nc):
     nz, ny, nx = fine
     zf, uc, vc, wc = _coarse(7, nc)
@@ -142,7 +144,8 @@ def test_solenoidal_transfer_is_divergence_free_on_the_gpu():
     assert clo[0] <= 1e-12 * scale and clo[1] <= 1e-12 * scale
 
 
-@pytest.mark.parametrize("fine,nc", [((32, 32, 32), (12, 16, 16)), ((36, 40, 48), (10, 16, 20))])
+@pytest.mark.parametrize("fine,nc", [((32, 32, 32), (12, 16, 16)), ((36, 40, 48), (10, 16, 20)),
+                                     ((20, 18, 30), (8, 12, 16))])
 def test_projection_of_c_matches_oracle(fine, nc):
     nz, ny, nx = fine
     ncz, ncy, ncx = nc

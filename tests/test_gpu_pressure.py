@@ -36,7 +36,8 @@ def _inputs(shape, zwalls, seed):
     return C, u, v, w, rng.standard_normal(shape), rng.standard_normal(shape)
 
 
-@pytest.mark.parametrize("shape", [(8, 12, 10), (9, 8, 16), (12, 6, 8), (32, 64, 48)])
+@pytest.mark.parametrize("shape", [(8, 12, 10), (9, 8, 16), (12, 6, 8), (32, 64, 48),
+                                   (10, 7, 15)])   # odd y and x extents
 @pytest.mark.parametrize("zwalls", [False, True])
 def test_poisson_solve_matches_oracle(shape, zwalls):
     from paper_2105_01865_amd import ch
@@ -55,7 +56,7 @@ def test_poisson_solve_matches_oracle(shape, zwalls):
         assert e <= tol
 
 
-@pytest.mark.parametrize("shape", [(8, 12, 10), (16, 16, 16), (9, 10, 24)])
+@pytest.mark.parametrize("shape", [(8, 12, 10), (16, 16, 16), (9, 10, 24), (11, 9, 13)])
 @pytest.mark.parametrize("zwalls", [False, True])
 def test_pressure_step_matches_oracle(shape, zwalls):
     from paper_2105_01865_amd import ch
