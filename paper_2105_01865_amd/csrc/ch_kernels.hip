@@ -633,7 +633,7 @@ k_ccl_compact(const int* __restrict__ lab, const int* __restrict__ cnt, int64_t 
 // staggered mesh: P and C at the cells, u / v / w on the low faces of the
 // cells (w has nz + 1 planes between walls, zero on both).  The density is
 // rho2 + (rho1 - rho2) clamp(C, 0, 1); a face takes the mean of its two
-// cells.
+// cells, and 1/rho on a face is the refined hardware reciprocal (fast_rcp).
 template <typename T>
 __device__ __forceinline__ T press_rho(const PressArgs& a, T c)
 {
@@ -678,7 +678,7 @@ k_press_rhs(PressArgs a, const T* __restrict__ C, const T* __restrict__ ph,
             auto flux = [&](int64_t nb, int s) {
                 const T rf = T(0.5) * (rc + press_rho(a, C[nb]));
                 const T g = s > 0 ? ph[nb] - pc : pc - ph[nb];
-                return (T(1) - r2 / rf) * g * ih;
+                return (T(1) - r2 * chd::fast_rcp(rf)) * g * ih;
             };
             T d = flux(row * nx + xp, 1) - flux(row * nx + xm, -1)
                 + flux(((int64_t)z * ny + yp) * nx + x, 1) - flux(((int64_t)z * ny + ym) * nx + x, -1);
@@ -842,7 +842,8 @@ k_press_update(PressArgs a, const T* __restrict__ C, const T* __restrict__ P,
             const T rc = press_rho(a, C[c]), pc = P[c], hc = ph[c];
             auto corr = [&](int64_t nb) {   // face between nb (low side) and c
                 const T rf = T(0.5) * (rc + press_rho(a, C[nb]));
-                return dt * ((pc - P[nb]) * ih * ir2 + (T(1) / rf - ir2) * (hc - ph[nb]) * ih);
+                return dt * ((pc - P[nb]) * ih * ir2
+                             + (chd::fast_rcp(rf) - ir2) * (hc - ph[nb]) * ih);
             };
             u[c] -= corr(row * nx + xm);
             v[c] -= corr(((int64_t)z * ny + ym) * nx + x);
