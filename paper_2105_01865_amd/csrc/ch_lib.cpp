@@ -1076,8 +1076,9 @@ ch_status ch_interp_create(const ch_grid* fine, int64_t ncx, int64_t ncy, int64_
         return fail(CH_EINVAL, "meshes too small");
     if ((double)ncx * ncy * (ncz + 1) >= 2147483647.0)
         return fail(CH_EINVAL, "coarse mesh too large");
-    if ((double)fine->nx * fine->ny * (fine->nz + 1) >= 2147483647.0 * 8.0 ||
-        (double)fine->ny * (fine->nz + 1) >= 2147483647.0 ||
+    // the kernels count (row, plane) work items and reference-plane points in
+    // 32 bits (element addresses are 64-bit)
+    if ((double)fine->ny * (fine->nz + 1) >= 2147483647.0 ||
         (double)fine->nx * (fine->nz + 1) >= 2147483647.0)
         return fail(CH_EINVAL, "fine mesh too large");
     if (ncx > (precision == CH_FP64 ? 4096 : 8192))
