@@ -587,28 +587,27 @@ k_ccl_flatten(int* lab, int64_t n)
         if (lab[i] >= 0) lab[i] = ccl_find(lab, (int)i);
 }
 
-// Cells per drop: each thread counts a run of CCL_RUN consecutive cells and
-// adds one count per stretch of equal labels to cnt[root].
-constexpr int CCL_RUN = 32;
-
+// Cells per drop: each wavefront reads windows of 64 consecutive labels
+// (coalesced); the lanes that start a run of equal labels within a window
+// (found with a ballot) add the run's length to cnt[root].
 __global__ void __launch_bounds__(256)
 k_ccl_count(const int* __restrict__ lab, int64_t n, int* __restrict__ cnt)
 {
-    const int64_t nrun = (n + CCL_RUN - 1) / CCL_RUN;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrun;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i0 = r * CCL_RUN, i1 = i0 + CCL_RUN < n ? i0 + CCL_RUN : n;
-        int cur = -1, c = 0;
-        for (int64_t i = i0; i < i1; ++i) {
-            const int l = lab[i];
-            if (l != cur) {
-                if (cur >= 0) atomicAdd(cnt + cur, c);
-                cur = l;
-                c = 0;
-            }
-            ++c;
+    const int lane = threadIdx.x & 63;
+    const int64_t nwave = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
+         base < n; base += nwave * 64) {
+        const int64_t i = base + lane;
+        const int l = i < n ? lab[i] : -1;
+        const int prev = __shfl_up(l, 1);
+        const bool start = lane == 0 || l != prev;
+        const unsigned long long runs = __ballot(start);
+        if (start && l >= 0) {
+            // next run start above this lane, or the window's end
+            const unsigned long long above = lane == 63 ? 0ull : runs & (~0ull << (lane + 1));
+            const int64_t end = above ? base + __ffsll((long long)above) - 1 : base + 64;
+            atomicAdd(cnt + l, (int)((end < n ? end : n) - i));
         }
-        if (cur >= 0) atomicAdd(cnt + cur, c);
     }
 }
 
@@ -1030,8 +1029,7 @@ hipError_t launch_drops_label(hipStream_t st, const void* C, int nx, int ny, int
 hipError_t launch_drops_count(hipStream_t st, const int* lab, int64_t n, int* cnt, int cap,
                               int* oroot, int* ocnt, int* count)
 {
-    hipLaunchKernelGGL(k_ccl_count, dim3(grid_for((n + CCL_RUN - 1) / CCL_RUN)), dim3(256), 0, st,
-                       lab, n, cnt);
+    hipLaunchKernelGGL(k_ccl_count, dim3(grid_for(n)), dim3(256), 0, st, lab, n, cnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ccl_compact, dim3(grid_for(n)), dim3(256), 0, st, lab, cnt, n, cap,
