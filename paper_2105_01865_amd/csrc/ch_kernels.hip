@@ -947,7 +947,7 @@ hipError_t launch_check_velocity(hipStream_t st, const chd::BoxDesc* boxes, int 
 template <typename T, int JB>
 static hipError_t launch_interp_jb(hipStream_t st, const InterpArgs& a)
 {
-    constexpr int MA = sizeof(T) == 4 ? 8 : 6;    // rows of loads in flight
+    constexpr int MA = sizeof(T) == 4 ? 20 : 12;  // rows of loads in flight
     if (a.lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)&k_interp<T, JB, MA>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
