@@ -138,6 +138,7 @@ def bench_ensemble(args, stream):
                      [w.Pe for w in E], stream=stream, precision=prec)
         U, V, W = (b.pack([getattr(w, f) for w in E], f) for f in "uvw")
         b.set_field(b.pack([w.C for w in E], "c"))
+        tune = b.autotune(U, V, W, 1e-4, steps=5) if not args.no_autotune else None
         m0 = np.array(b.mass())
         b.step(U, V, W, 1e-4, args.warmup)
         ms = _timed_events(stream, lambda: b.step(U, V, W, 1e-4, args.ensemble_steps))
@@ -151,6 +152,7 @@ def bench_ensemble(args, stream):
         res[prec] = {"value": round(pts * args.ensemble_steps / (ms * 1e-3) / 1e9, 4),
                      "unit": "Gpts/s", "ms_per_step": round(ms / args.ensemble_steps, 4),
                      "max_box_mass_drift": float(np.max(np.abs(m1 - m0) / np.abs(m0))),
+                     "autotune": tune,
                      "kernels_avg_us": {k: round(1e3 * v[0] / max(1, v[1]), 1)
                                         for k, v in kern.items()}}
     d = fields["fp32"] - fields["fp64"]
@@ -400,6 +402,8 @@ def main():
     ap.add_argument("--large-steps", type=int, default=10)
     ap.add_argument("--explicit-steps", type=int, default=200)
     ap.add_argument("--pressure-steps", type=int, default=20)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the planner's automatic tiles (no launch-plan autotuning)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-ensemble and multiple-resolution lines")
     ap.add_argument("--counter-probe", action="store_true")
@@ -429,6 +433,8 @@ def main():
         C0 = torch.from_numpy(wl.C).to(device="cuda", dtype=dt_)
         U, V, W = (torch.from_numpy(a).to(device="cuda", dtype=dt_) for a in (wl.u, wl.v, wl.w))
         s.set_field(C0)
+        # launch-plan autotuning (before the timed region; C is restored)
+        tune = s.autotune(U, V, W, wl.dt, steps=10) if not args.no_autotune else None
         m0 = s.mass()
         s.step(U, V, W, wl.dt, args.warmup)
         torch.cuda.synchronize()
@@ -458,7 +464,7 @@ def main():
         s.profile(False)
         s.close()
         return dict(ms=ms, wall=wall, m0=m0, m1=m1, C=C, cfg=cfg, prof=prof, roots=roots,
-                    cells=cells, label_ms=label_ms)
+                    cells=cells, label_ms=label_ms, tune=tune)
 
     r32 = timed("fp32")
     progress("256^3 fp32 done")
@@ -523,9 +529,10 @@ def main():
                                "R~U[6,16]h, frozen k^-5/3 field 1<=k<=16 rms 1, Cn=h, "
                                "Pe=0.9/Cn, dt=1e-4, kappa=4",
                    "points": pts, "precision": "fp32 storage+stencils, fp64 mass",
-                   "plan": r32["cfg"]},
+                   "plan": r32["cfg"], "autotune": r32["tune"]},
         "fp64": {"value": round(v64, 4), "unit": "Gpts/s",
-                 "ms_per_step": round(r64["ms"] / nstep, 5), "plan": r64["cfg"]},
+                 "ms_per_step": round(r64["ms"] / nstep, 5), "plan": r64["cfg"],
+                 "autotune": r64["tune"]},
         "fp32_over_fp64": round(v32 / v64, 3),
         "accuracy_fp32_vs_fp64": {"steps": args.warmup + nstep, "l2_rel": l2,
                                   "mass_drift_fp32": drift32, "mass_drift_fp64": drift64,

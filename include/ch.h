@@ -277,6 +277,30 @@ ch_status ch_pressure_step(ch_poisson* p, const void* C, double rho1, double rho
                            void* u, void* v, void* w, void* P, void* Pold);
 void ch_poisson_destroy(ch_poisson* p);
 
+/* ---- launch-plan autotuning ----------------------------------------------
+ * The tiles of the x pass (rows per task, planes per task) are chosen by a
+ * heuristic at creation.  ch_autotune / ch_batch_autotune time `steps` RK3
+ * steps (1 .. 1000, after one untimed step) of every plan in the candidate
+ * set  x_rows in {auto, 1, 2, 4} x z_chunk in {auto, 4, 6, ..., 16}  that
+ * the planner admits for dt, each from the same C with the given velocity
+ * (borrowed device pointers, as for ch_step), and keep the fastest as the
+ * state's launch options.  C is restored before returning; the call waits
+ * for the stream and allocates one copy of C for its duration.  The tuned
+ * options stay fixed: a later dt for which they are not admitted fails in
+ * ch_step (tune again).  out receives the chosen plan, its ms per step, the
+ * automatic plan's ms per step and the number of candidates timed (the
+ * automatic plan is also run once first, untimed for the choice, to warm the
+ * device up). */
+typedef struct {
+    int x_rows, z_chunk;
+    double ms_per_step, auto_ms_per_step;
+    int candidates;
+} ch_tune;
+ch_status ch_autotune(ch_state* s, const void* u, const void* v, const void* w, double dt,
+                      int steps, ch_tune* out);
+ch_status ch_batch_autotune(ch_batch* b, const void* u, const void* v, const void* w, double dt,
+                            int steps, ch_tune* out);
+
 /* ---- drop diagnostics (sec. 4) -------------------------------------------
  * The drops of a box for the drop-size statistics: cells with
  * C >= threshold (the paper's mid-value 1/2; compared in the state's

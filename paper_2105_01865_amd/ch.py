@@ -60,6 +60,17 @@ _PD = ctypes.POINTER(ctypes.c_double)
 _PI64 = ctypes.POINTER(ctypes.c_int64)
 
 # name -> (restype, argtypes); kept in the order of include/ch.h
+class Tune(ctypes.Structure):
+    _fields_ = [("x_rows", ctypes.c_int), ("z_chunk", ctypes.c_int),
+                ("ms_per_step", ctypes.c_double), ("auto_ms_per_step", ctypes.c_double),
+                ("candidates", ctypes.c_int)]
+
+
+def _tune_dict(t):
+    return {"x_rows": t.x_rows, "z_chunk": t.z_chunk, "ms_per_step": t.ms_per_step,
+            "auto_ms_per_step": t.auto_ms_per_step, "candidates": t.candidates}
+
+
 SIGNATURES = {
     "ch_default_opts": (None, [ctypes.POINTER(Opts)]),
     "ch_create": (_I, [ctypes.POINTER(Grid), _D, _D, ctypes.POINTER(Psi), ctypes.POINTER(BC),
@@ -87,6 +98,8 @@ SIGNATURES = {
     "ch_interp_set_stream": (_I, [_VP, _VP]),
     "ch_interp_apply": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "ch_interp_destroy": (None, [_VP]),
+    "ch_autotune": (_I, [_VP, _VP, _VP, _VP, _D, _I, ctypes.POINTER(Tune)]),
+    "ch_batch_autotune": (_I, [_VP, _VP, _VP, _VP, _D, _I, ctypes.POINTER(Tune)]),
     "ch_drops": (_I, [_VP, _D, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "ch_batch_drops": (_I, [_VP, _I, _D, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
@@ -272,6 +285,17 @@ class State(_StreamMixin):
         _check(lib().ch_mass(self._h, ctypes.byref(out)))
         return out.value
 
+    def autotune(self, u, v, w, dt, steps=5):
+        """Time the candidate launch plans, keep the fastest (C is restored)."""
+        su, sv, sw = self.vel_shapes()
+        t = Tune()
+        self._enter()
+        _check(lib().ch_autotune(self._h, _dev_tensor(u, self.dtype, su, "u"),
+                                 _dev_tensor(v, self.dtype, sv, "v"),
+                                 _dev_tensor(w, self.dtype, sw, "w"), float(dt), int(steps),
+                                 ctypes.byref(t)))
+        return _tune_dict(t)
+
     def drops(self, threshold=0.5, cap=4096):
         """(root, cells) of every drop (face-connected cells with
         C >= threshold), sorted by root; V = h^3 cells."""
@@ -385,6 +409,17 @@ class Batch(_StreamMixin):
         self._enter()
         _check(lib().ch_batch_step(self._h, pu, pv, pw, float(dt), int(nsteps)))
         self._leave()
+
+    def autotune(self, u, v, w, dt, steps=5):
+        """Time the candidate launch plans on the packed velocity, keep the
+        fastest (C is restored)."""
+        t = Tune()
+        self._enter()
+        _check(lib().ch_batch_autotune(self._h, _dev_tensor(u, self.dtype, (self.totals[1],), "u"),
+                                       _dev_tensor(v, self.dtype, (self.totals[2],), "v"),
+                                       _dev_tensor(w, self.dtype, (self.totals[3],), "w"),
+                                       float(dt), int(steps), ctypes.byref(t)))
+        return _tune_dict(t)
 
     def drops(self, box, threshold=0.5, cap=4096):
         """(root, cells) of the drops of box `box`, sorted by root."""

@@ -664,6 +664,84 @@ ch_status drops(Engine& e, int box, double thr, int64_t cap, int64_t* ndrops, in
     return fail(CH_EHIP, "drop list did not settle");
 }
 
+// Launch-plan autotuning: every candidate (x rows per task, planes per task)
+// that the plan admits for dt is timed over `steps` steps (after one untimed
+// step) with the given velocity, from the same C each time; the fastest
+// stays as the engine's options.  C is restored; E and q are scratch.
+ch_status autotune(Engine& e, const void* u, const void* v, const void* w, double dt, int steps,
+                   ch_tune* out)
+{
+    if (!u || !v || !w || !out) return fail(CH_EINVAL, "null argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CH_EINVAL, "dt must be > 0");
+    steps = std::max(1, std::min(steps, 1000));
+    HIP_TRY(hipSetDevice(e.device));
+    HIP_TRY(hipStreamSynchronize(e.stream));
+    const size_t bytes = (size_t)e.P.tot[0] * chp::esize(e.P.prec);
+    void* save = nullptr;
+    if (hipMalloc(&save, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CH_ENOMEM, "cannot allocate the copy of C for autotuning");
+    }
+    HIP_TRY(hipMemcpy(save, e.C, bytes, hipMemcpyDeviceToDevice));
+    const bool prof = e.prof;
+    e.prof = false;
+    const int keep_rows = e.P.opt.x_rows, keep_zc = e.P.opt.z_chunk;
+    // the automatic plan first (its timing also warms the device up) and
+    // again last, where its time is taken
+    std::vector<std::pair<int, int>> cand = {{0, 0}};
+    for (int r : {1, 2, 4})
+        for (int z : {0, 4, 6, 8, 10, 12, 14, 16}) cand.push_back({r, z});
+    cand.push_back({0, 0});
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    ch_status st = CH_OK;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
+        st = fail(CH_EHIP, "cannot create events");
+    int best_r = keep_rows, best_z = keep_zc, tried = 0;
+    double best_ms = INFINITY, auto_ms = NAN;
+    for (size_t c = 0; c < cand.size() && st == CH_OK; ++c) {
+        e.P.opt.x_rows = cand[c].first;
+        e.P.opt.z_chunk = cand[c].second;
+        if (set_dt(e, dt) != CH_OK) continue;   // not admitted for this dt
+        hipError_t err = hipMemcpyAsync(e.C, save, bytes, hipMemcpyDeviceToDevice, e.stream);
+        if (err == hipSuccess) err = enqueue_step(e, u, v, w);
+        if (err == hipSuccess) err = hipEventRecord(t0, e.stream);
+        for (int k = 0; k < steps && err == hipSuccess; ++k) err = enqueue_step(e, u, v, w);
+        if (err == hipSuccess) err = hipEventRecord(t1, e.stream);
+        if (err == hipSuccess) err = hipEventSynchronize(t1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, t0, t1);
+        if (err != hipSuccess) {
+            st = fail(CH_EHIP, "autotuning step failed: %s", hipGetErrorString(err));
+            break;
+        }
+        if (c > 0) ++tried;
+        const double per = ms / steps;
+        if (c + 1 == cand.size()) auto_ms = per;
+        if (c > 0 && per < best_ms) {
+            best_ms = per;
+            best_r = cand[c].first;
+            best_z = cand[c].second;
+        }
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    e.prof = prof;
+    e.P.opt.x_rows = st == CH_OK ? best_r : keep_rows;
+    e.P.opt.z_chunk = st == CH_OK ? best_z : keep_zc;
+    ch_status st2 = set_dt(e, dt);
+    hipError_t err = hipMemcpy(e.C, save, bytes, hipMemcpyDeviceToDevice);
+    (void)hipFree(save);
+    if (st != CH_OK) return st;
+    if (st2 != CH_OK) return st2;
+    if (err != hipSuccess) return fail(CH_EHIP, "cannot restore C: %s", hipGetErrorString(err));
+    out->x_rows = e.P.x_rows;
+    out->z_chunk = e.P.zc;
+    out->ms_per_step = best_ms;
+    out->auto_ms_per_step = auto_ms;
+    out->candidates = tried;
+    return CH_OK;
+}
+
 ch_status mass(Engine& e, double* out)
 {
     if (!out) return fail(CH_EINVAL, "null output");
@@ -1236,6 +1314,20 @@ void ch_interp_destroy(ch_interp* ip)
     for (int c = 0; c < TR_COUNT; ++c) free_transfer(ip->d.tr[c]);
     free_solenoidal(ip->d);
     delete ip;
+}
+
+ch_status ch_autotune(ch_state* s, const void* u, const void* v, const void* w, double dt,
+                      int steps, ch_tune* out)
+{
+    CHECK_STATE(s);
+    return autotune(s->e, u, v, w, dt, steps, out);
+}
+
+ch_status ch_batch_autotune(ch_batch* b, const void* u, const void* v, const void* w, double dt,
+                            int steps, ch_tune* out)
+{
+    CHECK_STATE(b);
+    return autotune(b->e, u, v, w, dt, steps, out);
 }
 
 ch_status ch_drops(ch_state* s, double threshold, int64_t cap, int64_t* ndrops, int64_t* root,

@@ -340,3 +340,46 @@ def test_flat_interface_equilibrium_stays_on_the_gpu(axis, kappa):
         d = float(np.abs(got - ref).max())
         print(f"  max |dC| {d:.2e}")
         assert d <= tol
+
+
+def test_autotune_restores_c_and_the_tuned_plan_matches_the_oracle():
+    C, u, v, w, h = _case((32, 40, 48), seed=21)
+    st = torch.cuda.Stream()
+    s = ch.State(C.shape, h, h, 0.9 / h, stream=st)
+    s.set_field(dev(C))
+    U, V, W = dev(u), dev(v), dev(w)
+    print("[gpu] autotune (32, 40, 48)", flush=True)
+    t = s.autotune(U, V, W, 1e-4, steps=2)
+    print(f"  {t}")
+    assert t["candidates"] >= 2 and 0.0 < t["ms_per_step"] <= t["auto_ms_per_step"]
+    assert np.array_equal(s.get_field().cpu().numpy(), C)
+    cfg = s.config()
+    assert (cfg["x_rows"], cfg["z_chunk"]) == (t["x_rows"], t["z_chunk"])
+    s.step(U, V, W, 1e-4, 3)
+    got = s.get_field().cpu().numpy()
+    s.close()
+    ref = oracle.step(C, u, v, w, h, h, 0.9 / h, 1e-4, 3)
+    assert rel(got, ref) <= 3e-12
+    same, _ = run_gpu(C, u, v, w, h, h, 0.9 / h, 1e-4, 3, x_rows=t["x_rows"],
+                      z_chunk=t["z_chunk"])
+    assert np.array_equal(got, same)
+
+
+def test_batch_autotune_restores_c_and_steps_like_the_oracle():
+    cases = [_case((32, 32, 32), seed=22), _case((24, 16, 48), seed=23)]
+    shapes = [c[0].shape for c in cases]
+    hs = [c[4] for c in cases]
+    st = torch.cuda.Stream()
+    b = ch.Batch(shapes, hs, hs, [0.9 / h for h in hs], stream=st)
+    C0 = b.pack([c[0] for c in cases], "c")
+    b.set_field(C0)
+    U, V, W = (b.pack([c[i] for c in cases], f) for i, f in ((1, "u"), (2, "v"), (3, "w")))
+    print("[gpu] batch autotune", flush=True)
+    t = b.autotune(U, V, W, 1e-4, steps=2)
+    print(f"  {t}")
+    assert torch.equal(b.get_field(), C0)
+    b.step(U, V, W, 1e-4, 2)
+    outs = [o.cpu().numpy() for o in b.unpack(b.get_field())]
+    b.close()
+    for (C, u, v, w, h), got in zip(cases, outs):
+        assert rel(got, oracle.step(C, u, v, w, h, h, 0.9 / h, 1e-4, 2)) <= 2e-12
