@@ -193,6 +193,10 @@ def bench_multires(args, stream):
             ip = ch.Interp(wl.shape, wl.h, uc.shape, zf, precision=prec, stream=stream,
                            solenoidal=mode == "solenoidal")
             s.set_field(C0)
+            tune = None
+            if not args.no_autotune:
+                # the step's tiles, tuned on the transferred velocity
+                tune = s.autotune(*ip.apply(UC, VC, WC), wl.dt, steps=3)
             m0 = s.mass()
             s.step_multires(ip, UC, VC, WC, wl.dt, args.warmup)
             ms = _timed_events(stream, lambda: s.step_multires(ip, UC, VC, WC, wl.dt,
@@ -210,7 +214,7 @@ def bench_multires(args, stream):
             t_us = 1e3 * kern["interp"][0] / max(1, kern["interp"][1])
             r = {"value": round(wl.points * args.multires_steps / (ms * 1e-3) / 1e9, 4),
                  "unit": "Gpts/s", "ms_per_step": round(ms / args.multires_steps, 4),
-                 "mass_drift": abs(m1 - m0) / abs(m0),
+                 "mass_drift": abs(m1 - m0) / abs(m0), "autotune": tune,
                  "kernels_avg_us": {k: round(1e3 * v[0] / max(1, v[1]), 1)
                                     for k, v in kern.items()}}
             nbytes = transfer_bytes_per_component(uc.shape, wl.shape, es)
@@ -318,6 +322,7 @@ def bench_large(args, stream):
     s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, precision="fp32", stream=stream)
     s.set_field(wl.C)
     del wl.C
+    tune = s.autotune(wl.u, wl.v, wl.w, wl.dt, steps=2) if not args.no_autotune else None
     m0 = s.mass()
     s.step(wl.u, wl.v, wl.w, wl.dt, 1)
     ms = _timed_events(stream, lambda: s.step(wl.u, wl.v, wl.w, wl.dt, args.large_steps))
@@ -340,7 +345,7 @@ def bench_large(args, stream):
                      "mass_drift": abs(m1 - m0) / abs(m0),
                      "kernels_avg_us": {k: round(1e3 * v[0] / max(1, v[1]), 1)
                                         for k, v in kern.items()}},
-            "plan": cfg}
+            "plan": cfg, "autotune": tune}
 
 
 def bench_explicit25(args, stream, line):
