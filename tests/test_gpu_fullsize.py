@@ -1,0 +1,98 @@
+"""The 512^3 multiple-resolution workload at full size, in the launch
+configuration the benchmark times (autotuned tiles):
+
+* one FP64 step with the plain transfer against the oracle's transfer and
+  step over the whole field (1e-12 relative, the per-step bar);
+* the solenoidal transfer's fine divergence (zero to rounding below the top
+  layer, the property that holds at any size);
+* the split-density pressure step's divergence-free velocity (the oracle's
+  dense per-mode solves do not reach this size; the property does).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2105_01865_amd import ch, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wl3():
+    return inputs.make_workload(3)
+
+
+def _dev(a, dt_=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt_)
+
+
+def test_config3_full_size_one_step_against_oracle(wl3):
+    wl = wl3
+    nz, ny, nx = wl.shape
+    zf, uc, vc, wc = (wl.coarse[k] for k in ("zf", "uc", "vc", "wc"))
+    print(f"[gpu] config 3 at {wl.shape}: oracle transfer + step", flush=True)
+    uf, vf, wf = oracle.interp_velocity(zf, uc, vc, wc, (nx, ny, nz))
+    ref = oracle.step(wl.C, uf, vf, wf, wl.h, wl.Cn, wl.Pe, wl.dt, 1, bc=wl.bc)
+    del uf, vf, wf
+    print("[gpu] GPU step (autotuned plan)", flush=True)
+    st = torch.cuda.Stream()
+    s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, bc=wl.bc, stream=st)
+    ip = ch.Interp(wl.shape, wl.h, uc.shape, zf, precision="fp64", stream=st)
+    UC, VC, WC = _dev(uc), _dev(vc), _dev(wc)
+    s.set_field(_dev(wl.C))
+    t = s.autotune(*ip.apply(UC, VC, WC), wl.dt, steps=1)
+    s.step_multires(ip, UC, VC, WC, wl.dt, 1)
+    got = s.get_field().cpu().numpy()
+    s.close()
+    ip.close()
+    e = float(np.abs(got - ref).max() / np.abs(ref).max())
+    print(f"  plan {t['x_rows']} rows x {t['z_chunk']} planes; rel {e:.2e}")
+    assert e <= 1e-12
+
+
+def _div(u, v, w, h):
+    return ((torch.roll(u, -1, 2) - u) + (torch.roll(v, -1, 1) - v) + (w[1:] - w[:-1])) / h
+
+
+def test_solenoidal_transfer_full_size_is_divergence_free(wl3):
+    wl = wl3
+    zf, uc, vc, wc = (wl.coarse[k] for k in ("zf", "uc", "vc", "wc"))
+    print(f"[gpu] solenoidal transfer at {wl.shape}", flush=True)
+    st = torch.cuda.Stream()
+    ip = ch.Interp(wl.shape, wl.h, uc.shape, zf, precision="fp64", stream=st, solenoidal=True)
+    u, v, w = ip.apply(_dev(uc), _dev(vc), _dev(wc))
+    clo = ip.closure()
+    ip.close()
+    torch.cuda.synchronize()
+    d = _div(u, v, w, wl.h)
+    scale = max(float(x.abs().max()) for x in (u, v, w))
+    below = float(d[:-1].abs().max())
+    print(f"  max |div| below the top layer {below:.2e} (velocity scale {scale:.2e}, "
+          f"1/h {1 / wl.h:.0f}); closures {clo}")
+    assert below <= 1e-11 * scale / wl.h
+    assert clo[0] <= 1e-12 * scale and clo[1] <= 1e-12 * scale
+    assert float(w[0].abs().max()) == 0.0 and float(w[-1].abs().max()) == 0.0
+
+
+def test_pressure_step_full_size_is_divergence_free(wl3):
+    wl = wl3
+    zf, uc, vc, wc = (wl.coarse[k] for k in ("zf", "uc", "vc", "wc"))
+    print(f"[gpu] pressure step at {wl.shape}", flush=True)
+    st = torch.cuda.Stream()
+    ip = ch.Interp(wl.shape, wl.h, uc.shape, zf, precision="fp64", stream=st)
+    u, v, w = ip.apply(_dev(uc), _dev(vc), _dev(wc))
+    ip.close()
+    C = _dev(wl.C)
+    rng = np.random.default_rng(71)
+    P = _dev(rng.standard_normal(wl.shape))
+    Pold = _dev(rng.standard_normal(wl.shape))
+    d0 = float(_div(u, v, w, wl.h).abs().max())
+    p = ch.Poisson(wl.shape, wl.h, z_walls=True, stream=st)
+    p.step(C, u, v, w, P, Pold, 1000.0, 1.0, wl.dt)
+    torch.cuda.synchronize()
+    p.close()
+    d1 = float(_div(u, v, w, wl.h).abs().max())
+    print(f"  max |div| before {d0:.2e}, after {d1:.2e}")
+    assert d1 <= 1e-10 * d0
+    assert float(w[0].abs().max()) == 0.0 and float(w[-1].abs().max()) == 0.0
