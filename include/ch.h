@@ -282,7 +282,8 @@ void ch_poisson_destroy(ch_poisson* p);
  * heuristic at creation.  ch_autotune / ch_batch_autotune time `steps` RK3
  * steps (1 .. 1000, after one untimed step) of every plan in the candidate
  * set  x_rows in {auto, 1, 2, 4} x z_chunk in {auto, 4, 6, ..., 16}  that
- * the planner admits for dt, each from the same C with the given velocity
+ * the planner admits for dt, then the y / z segment lengths {auto, 128, 64}
+ * with the fastest of those, each from the same C with the given velocity
  * (borrowed device pointers, as for ch_step), and keep the fastest as the
  * state's launch options.  C is restored before returning; the call waits
  * for the stream and allocates one copy of C for its duration.  The tuned
@@ -295,6 +296,7 @@ typedef struct {
     int x_rows, z_chunk;
     double ms_per_step, auto_ms_per_step;
     int candidates;
+    int seg_len;   /* segment length of the y and z line passes */
 } ch_tune;
 ch_status ch_autotune(ch_state* s, const void* u, const void* v, const void* w, double dt,
                       int steps, ch_tune* out);

@@ -63,12 +63,13 @@ _PI64 = ctypes.POINTER(ctypes.c_int64)
 class Tune(ctypes.Structure):
     _fields_ = [("x_rows", ctypes.c_int), ("z_chunk", ctypes.c_int),
                 ("ms_per_step", ctypes.c_double), ("auto_ms_per_step", ctypes.c_double),
-                ("candidates", ctypes.c_int)]
+                ("candidates", ctypes.c_int), ("seg_len", ctypes.c_int)]
 
 
 def _tune_dict(t):
     return {"x_rows": t.x_rows, "z_chunk": t.z_chunk, "ms_per_step": t.ms_per_step,
-            "auto_ms_per_step": t.auto_ms_per_step, "candidates": t.candidates}
+            "auto_ms_per_step": t.auto_ms_per_step, "candidates": t.candidates,
+            "seg_len": t.seg_len}
 
 
 SIGNATURES = {

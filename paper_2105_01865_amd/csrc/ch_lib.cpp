@@ -666,7 +666,8 @@ ch_status drops(Engine& e, int box, double thr, int64_t cap, int64_t* ndrops, in
 
 // Launch-plan autotuning: every candidate (x rows per task, planes per task)
 // that the plan admits for dt is timed over `steps` steps (after one untimed
-// step) with the given velocity, from the same C each time; the fastest
+// step) with the given velocity, from the same C each time; then, with the
+// fastest of those, the y / z segment lengths 128 and 64.  The fastest plan
 // stays as the engine's options.  C is restored; E and q are scratch.
 ch_status autotune(Engine& e, const void* u, const void* v, const void* w, double dt, int steps,
                    ch_tune* out)
@@ -723,9 +724,37 @@ ch_status autotune(Engine& e, const void* u, const void* v, const void* w, doubl
             best_z = cand[c].second;
         }
     }
+    // then the segment length of the y and z passes, with the chosen x plan
+    const int keep_seg = e.P.opt.seg_len;
+    int best_seg = keep_seg;
+    for (int seg : {128, 64}) {
+        if (st != CH_OK) break;
+        e.P.opt.x_rows = best_r;
+        e.P.opt.z_chunk = best_z;
+        e.P.opt.seg_len = seg;
+        if (set_dt(e, dt) != CH_OK) continue;
+        hipError_t err = hipMemcpyAsync(e.C, save, bytes, hipMemcpyDeviceToDevice, e.stream);
+        if (err == hipSuccess) err = enqueue_step(e, u, v, w);
+        if (err == hipSuccess) err = hipEventRecord(t0, e.stream);
+        for (int k = 0; k < steps && err == hipSuccess; ++k) err = enqueue_step(e, u, v, w);
+        if (err == hipSuccess) err = hipEventRecord(t1, e.stream);
+        if (err == hipSuccess) err = hipEventSynchronize(t1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, t0, t1);
+        if (err != hipSuccess) {
+            st = fail(CH_EHIP, "autotuning step failed: %s", hipGetErrorString(err));
+            break;
+        }
+        ++tried;
+        if (ms / steps < best_ms) {
+            best_ms = ms / steps;
+            best_seg = seg;
+        }
+    }
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
     e.prof = prof;
+    e.P.opt.seg_len = st == CH_OK ? best_seg : keep_seg;
     e.P.opt.x_rows = st == CH_OK ? best_r : keep_rows;
     e.P.opt.z_chunk = st == CH_OK ? best_z : keep_zc;
     ch_status st2 = set_dt(e, dt);
@@ -736,6 +765,7 @@ ch_status autotune(Engine& e, const void* u, const void* v, const void* w, doubl
     if (err != hipSuccess) return fail(CH_EHIP, "cannot restore C: %s", hipGetErrorString(err));
     out->x_rows = e.P.x_rows;
     out->z_chunk = e.P.zc;
+    out->seg_len = e.P.seg_cap;
     out->ms_per_step = best_ms;
     out->auto_ms_per_step = auto_ms;
     out->candidates = tried;

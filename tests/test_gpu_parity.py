@@ -343,25 +343,27 @@ def test_flat_interface_equilibrium_stays_on_the_gpu(axis, kappa):
 
 
 def test_autotune_restores_c_and_the_tuned_plan_matches_the_oracle():
-    C, u, v, w, h = _case((32, 40, 48), seed=21)
+    # 136 rows in y: the segment candidates 128 and 64 split the y lines
+    # (with ragged last segments), so the tuned plan may be a segmented one
+    C, u, v, w, h = _case((32, 136, 48), seed=21)
     st = torch.cuda.Stream()
     s = ch.State(C.shape, h, h, 0.9 / h, stream=st)
     s.set_field(dev(C))
     U, V, W = dev(u), dev(v), dev(w)
-    print("[gpu] autotune (32, 40, 48)", flush=True)
+    print("[gpu] autotune (32, 136, 48)", flush=True)
     t = s.autotune(U, V, W, 1e-4, steps=2)
     print(f"  {t}")
     assert t["candidates"] >= 2 and 0.0 < t["ms_per_step"] <= t["auto_ms_per_step"]
     assert np.array_equal(s.get_field().cpu().numpy(), C)
     cfg = s.config()
-    assert (cfg["x_rows"], cfg["z_chunk"]) == (t["x_rows"], t["z_chunk"])
+    assert (cfg["x_rows"], cfg["z_chunk"], cfg["seg"]) == (t["x_rows"], t["z_chunk"], t["seg_len"])
     s.step(U, V, W, 1e-4, 3)
     got = s.get_field().cpu().numpy()
     s.close()
     ref = oracle.step(C, u, v, w, h, h, 0.9 / h, 1e-4, 3)
     assert rel(got, ref) <= 3e-12
     same, _ = run_gpu(C, u, v, w, h, h, 0.9 / h, 1e-4, 3, x_rows=t["x_rows"],
-                      z_chunk=t["z_chunk"])
+                      z_chunk=t["z_chunk"], seg_len=t["seg_len"])
     assert np.array_equal(got, same)
 
 
