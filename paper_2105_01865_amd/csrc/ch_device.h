@@ -26,6 +26,7 @@
 // independent chunks that many threads march at once.
 #pragma once
 
+#include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -156,6 +157,16 @@ struct PlaneRef {
             return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, boff, 0, 0));
         }
     }
+    // element at lane offset voff plus the wave-uniform offset soff (which
+    // takes the load's scalar offset field: no lane register for the sum)
+    __device__ T operator()(uint32_t voff, uint32_t soff) const
+    {
+        if constexpr (sizeof(T) == 4) {
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+        } else {
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+        }
+    }
     __device__ void store(uint32_t boff, T v) const
     {
         if constexpr (sizeof(T) == 4) {
@@ -180,6 +191,7 @@ struct PlaneRef {
         return *reinterpret_cast<const T*>(p + boff);
 #endif
     }
+    CH_HD T operator()(uint32_t voff, uint32_t soff) const { return (*this)(voff + soff); }
     CH_HD void store(uint32_t boff, T v) const
     {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -226,13 +238,14 @@ CH_HD void wait_loads()
 //    weights do not change): eps + beta is t^2 + (3/13) u^2 + (12/13) eps;
 //  - the weights g_k / (eps + beta_k)^2 (g = 1/10, 6/10, 3/10) are formed
 //    over the common denominator prod_k (eps + beta_k)^2, which leaves one
-//    reciprocal; the factor 10 g_k is folded into the q_k - c coefficients.
-// `epsw` is (12/13) eps.
+//    reciprocal; the factor 10 g_k is folded into the q_k - c coefficients,
+//    which in the differences are (5 d2 - 2 d1)/6, d2 + 2 d3 and
+//    2 d3 - d4/2.
+// `epsw` is (12/13) eps.  weno5_inc returns the value minus c.
 template <typename T>
-CH_HD T weno5(T a, T b, T c, T d, T e, T epsw)
+CH_HD T weno5_inc(T d1, T d2, T d3, T d4, T epsw)
 {
     const T k3 = T(3) / T(13);
-    const T d1 = b - a, d2 = c - b, d3 = d - c, d4 = e - d;
     const T t0 = d2 - d1, t1 = d3 - d2, t2 = d4 - d3;
     const T u0 = T(3) * d2 - d1, u1 = d2 + d3, u2 = d4 - T(3) * d3;
     const T e0 = t0 * t0 + ((k3 * u0) * u0 + epsw);
@@ -241,12 +254,18 @@ CH_HD T weno5(T a, T b, T c, T d, T e, T epsw)
     const T p0 = e0 * e0, p1 = e1 * e1, p2 = e2 * e2;
     const T p12 = p1 * p2, p02 = p0 * p2, p01 = p0 * p1;
     // 10 g_k (q_k - c)
-    const T r0 = T(1) / T(12) * t0 + T(0.25) * u0;
-    const T r1 = T(0.5) * t1 + T(1.5) * u1;
-    const T r2 = T(0.25) * t2 - T(0.75) * u2;
+    const T r0 = T(5) / T(6) * d2 - T(1) / T(3) * d1;
+    const T r1 = d2 + T(2) * d3;
+    const T r2 = T(2) * d3 - T(0.5) * d4;
     const T num = p12 * r0 + (p02 * r1 + p01 * r2);
     const T den = p12 + (T(6) * p02 + T(3) * p01);
-    return c + num * fast_rcp(den);
+    return num * fast_rcp(den);
+}
+
+template <typename T>
+CH_HD T weno5(T a, T b, T c, T d, T e, T epsw)
+{
+    return c + weno5_inc<T>(b - a, c - b, d - c, e - d, epsw);
 }
 
 template <typename T>
@@ -259,15 +278,6 @@ template <typename T>
 CH_HD Cubic<T> cubic(const double* p)
 {
     return Cubic<T>{T(p[0]), T(p[1]), T(p[2]), T(p[3])};
-}
-
-// Fourth difference (1,-4,6,-4,1) from the differences to the centre value,
-// which keeps single precision accurate on smooth data.
-template <typename T>
-CH_HD T d4(T m2, T m1, T c0, T p1, T p2)
-{
-    const T s2 = (m2 - c0) + (p2 - c0), s1 = (m1 - c0) + (p1 - c0);
-    return s2 - T(4) * s1;
 }
 
 // compile-time integer tag
@@ -326,6 +336,30 @@ CH_HD T face_weno(T vel, T c0, T c1, T c2, T c3, T c4, T c5, T eps)
 {
     const bool p = vel >= T(0);
     return weno5<T>(p ? c0 : c5, p ? c1 : c4, p ? c2 : c3, p ? c3 : c2, p ? c4 : c1, eps);
+}
+
+// The flux vel * value through the same face, from the five first
+// differences D_j = c[j] - c[j-1] of the six cells and the two cells c2, c3
+// next to the face.  Read from the downwind side the stencil's differences
+// are the negated D in reverse order, and the increment is odd in the
+// differences (exactly so in rounded arithmetic too), so
+//   value = c2 + inc(D1, D2, D3, D4)  (vel >= 0),  c3 - inc(D5, D4, D3, D2),
+// and vel * value = vel * centre + |vel| * inc.  One set of D serves both
+// directions, neighbouring faces and the fourth differences.
+template <typename T>
+CH_HD T flux_weno_d(T vel, T D1, T D2, T D3, T D4, T D5, T c2, T c3, T eps)
+{
+    const bool p = vel >= T(0);
+    const T inc = weno5_inc<T>(p ? D1 : D5, p ? D2 : D4, D3, p ? D4 : D2, eps);
+    return vel * (p ? c2 : c3) + fabs(vel) * inc;
+}
+
+// Fourth difference (1,-4,6,-4,1) at the cell between D2 and D3 from the first
+// differences D1 .. D4 of its five cells.
+template <typename T>
+CH_HD T d4_d(T D1, T D2, T D3, T D4)
+{
+    return (D4 - D1) + T(3) * (D2 - D3);
 }
 
 // ---------------------------------------------------------------------------
@@ -607,7 +641,6 @@ struct XState {
     int rx[MI];      // (row << 16) | x of each owned cell, -1 if none
     uint32_t col[MI];   // byte offset of the cell in a plane of C, E, v, w
     uint32_t colu[MI];  // byte offset of its low x face in a plane of u
-    uint32_t colvh[MI]; // byte offset of its high y face in a plane of v
     int cxp[MI];     // halo column (-3 .. nx+2) that copies the owned column in
                      // the C tile, or the column itself if none (nx >= 6)
     int cxm[MI];     // the same for the psi'(C) tile (-1 .. nx)
@@ -672,6 +705,10 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
         hoffb[hr] = (uint32_t)(map_idx(t.y0 - 3 + prow, ny, bd.bc[1]) * nx) * sT;
     }
     const bool one_copy = nx >= 6;   // every column feeds at most one halo column
+    // byte offset, in a plane of v, of the row of the task's top y face (the
+    // high face of the last row: periodic wrap, or the wall face ny)
+    const int ytop = t.y0 + rows;
+    const uint32_t vtopb = (uint32_t)((ytop == ny && bd.bc[1] == 0 ? 0 : ytop) * nx) * sT;
 
     // all global loads of plane z for the owned cells, into prefetch set b
     // (uniform plane bases, 32-bit offsets within a plane)
@@ -692,13 +729,13 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 s.nvel[b][m][0] = Uz(s.colu[m]);
                 s.nvel[b][m][1] = (x == nx - 1 && bcx != 0) ? Uz(s.colu[m] + sT) : T(0);
                 s.nvel[b][m][2] = Vz(s.col[m]);
-                s.nvel[b][m][3] = r == rows - 1 ? Vz(s.colvh[m]) : T(0);
+                s.nvel[b][m][3] = r == rows - 1 ? Vz((uint32_t)x * sT, vtopb) : T(0);
                 s.nwh[b][m] = Wh(s.col[m]);
                 s.neold[b][m] = pa.e_mode != 0 ? Ez(s.col[m]) : T(0);
                 const uint32_t xb = (uint32_t)x * sT;
 #pragma unroll
                 for (int hr = 0; hr < 6; ++hr)
-                    if (hown[hr] == r) s.nhalo[b][m][hr] = Cz(hoffb[hr] + xb);
+                    if (hown[hr] == r) s.nhalo[b][m][hr] = Cz(xb, hoffb[hr]);
             }
         }
     };
@@ -762,10 +799,8 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
             if (s.rx[m] >= 0) {
                 const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
                 const int y = t.y0 + r;
-                const int yh = (y + 1 == ny && bd.bc[1] == 0) ? 0 : y + 1;
                 s.col[m] = (uint32_t)(y * nx + x) * sT;
                 s.colu[m] = (uint32_t)(y * fx + x) * sT;
-                s.colvh[m] = (uint32_t)(yh * nx + x) * sT;
                 s.cxp[m] = x;
                 s.cxm[m] = x;
                 for (int q = 0; q < 6; ++q)
@@ -787,8 +822,8 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                                          pbytes);
                     const uint32_t xb = (uint32_t)x * sT;
                     s.hq[m][0][0] = s.hq[m][1][0] = T(0);
-                    s.hq[m][0][1] = Cm(hoffb[2] + xb);
-                    s.hq[m][1][1] = Cm(hoffb[3] + xb);
+                    s.hq[m][0][1] = Cm(xb, hoffb[2]);
+                    s.hq[m][1][1] = Cm(xb, hoffb[3]);
                 }
             }
             s.xmask[m] = mask;
@@ -893,32 +928,52 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 const T* mrow = mb + (r + 1) * L.mbp + x + 1;  // mrow[o] = psi'(C)(x + o)
                 const int p = L.pbp, mp = L.mbp;
                 const T* vl = s.vel[m];
-                // x: the low face of the cell, and the wall face nx
-                fxb[r * L.fxp + x] =
-                    vl[0] * face_weno<T>(vl[0], row[-3], row[-2], row[-1], row[0], row[1], row[2], epsw);
-                if (x == nx - 1 && bcx != 0)
-                    fxb[r * L.fxp + nx] = vl[1] * face_weno<T>(vl[1], row[-2], row[-1], row[0],
-                                                                 row[1], row[2], row[3], epsw);
-                // y: the low face, and the top face for the last row
-                fyb[r * L.fyp + x] = vl[2] * face_weno<T>(vl[2], colm[0], colm[p], colm[2 * p],
-                                                          colm[3 * p], colm[4 * p], colm[5 * p], epsw);
-                if (r == rows - 1)
-                    fyb[(r + 1) * L.fyp + x] =
-                        vl[3] * face_weno<T>(vl[3], colm[p], colm[2 * p], colm[3 * p], colm[4 * p],
-                                             colm[5 * p], colm[6 * p], epsw);
-                // z: the high face (the low one carries over from the plane below)
+                // Each direction's first differences (D_j = C_j - C_{j-1}) serve its
+                // faces and its fourth difference; the directions are taken one
+                // after the other so that only one set is live at a time.
+                // x: C(x-2..x+2) minus the cell before; the low face of the cell,
+                // and the wall face nx
+                {
+                    const T dX[5] = {row[-2] - row[-3], row[-1] - row[-2], row[0] - row[-1],
+                                     row[1] - row[0], row[2] - row[1]};
+                    fxb[r * L.fxp + x] = flux_weno_d<T>(vl[0], dX[0], dX[1], dX[2], dX[3], dX[4],
+                                                        row[-1], row[0], epsw);
+                    if (x == nx - 1 && bcx != 0)
+                        fxb[r * L.fxp + nx] = vl[1] * face_weno<T>(vl[1], row[-2], row[-1], row[0],
+                                                                     row[1], row[2], row[3], epsw);
+                    s.pb4[m] = d4_d<T>(dX[1], dX[2], dX[3], dX[4]);
+                }
+                // y: rows y-2 .. y+2; the low face, and the top face for the last row
+                {
+                    T dY[5];
+#pragma unroll
+                    for (int j = 0; j < 5; ++j) dY[j] = colm[(j + 1) * p] - colm[j * p];
+                    fyb[r * L.fyp + x] = flux_weno_d<T>(vl[2], dY[0], dY[1], dY[2], dY[3], dY[4],
+                                                        colm[2 * p], colm[3 * p], epsw);
+                    if (r == rows - 1)
+                        fyb[(r + 1) * L.fyp + x] =
+                            flux_weno_d<T>(vl[3], dY[1], dY[2], dY[3], dY[4], colm[6 * p] - colm[5 * p],
+                                           colm[3 * p], colm[4 * p], epsw);
+                    s.pb4[m] += d4_d<T>(dY[1], dY[2], dY[3], dY[4]);
+                }
+                // z: planes z-1 .. z+3; the high face (the low one carries over
+                // from the plane below)
                 const T* c = s.cz[m];
-                if (zs == 0)
-                    s.fzl[m] = vl[4] * face_weno<T>(vl[4], c[0], c[1], c[2], c[3], c[4], c[5], epsw);
-                const T fzh = vl[5] * face_weno<T>(vl[5], c[1], c[2], c[3], c[4], c[5], c[6], epsw);
-                s.pz[m] = fzh - s.fzl[m];
-                s.fzl[m] = fzh;
+                {
+                    T dZ[5];
+#pragma unroll
+                    for (int j = 0; j < 5; ++j) dZ[j] = c[j + 2] - c[j + 1];
+                    if (zs == 0)
+                        s.fzl[m] = vl[4] * face_weno<T>(vl[4], c[0], c[1], c[2], c[3], c[4], c[5], epsw);
+                    const T fzh =
+                        flux_weno_d<T>(vl[5], dZ[0], dZ[1], dZ[2], dZ[3], dZ[4], c[3], c[4], epsw);
+                    s.pz[m] = fzh - s.fzl[m];
+                    s.fzl[m] = fzh;
+                    s.pb4[m] += d4_d<T>(dZ[0], dZ[1], dZ[2], dZ[3]);
+                }
                 const T mu0 = s.mq[m][1];
                 s.plap[m] = ((mrow[1] + mrow[-1]) + (mrow[mp] + mrow[-mp]))
                           + (s.mq[m][2] + s.mq[m][0]) - T(6) * mu0;
-                s.pb4[m] = d4<T>(row[-2], row[-1], row[0], row[1], row[2])
-                         + d4<T>(colm[p], colm[2 * p], colm[3 * p], colm[4 * p], colm[5 * p])
-                         + d4<T>(c[1], c[2], c[3], c[4], c[5]);
                 if constexpr (E25) {
                     // mixed second differences xy (rows y -+ 1 of this plane) and xz
                     // (the owned row at z -+ 1)
@@ -951,9 +1006,9 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 const T* c = s.cz[m];
                 const T* hm = s.hq[m][0];
                 const T* hp = s.hq[m][1];
-                const T lo = (hm[0] - hm[1]) + (Cn1(hoffb[2] + xb) - hm[1]);
+                const T lo = (hm[0] - hm[1]) + (Cn1(xb, hoffb[2]) - hm[1]);
                 const T mid = (c[2] - c[3]) + (c[4] - c[3]);
-                const T hi = (hp[0] - hp[1]) + (Cn1(hoffb[3] + xb) - hp[1]);
+                const T hi = (hp[0] - hp[1]) + (Cn1(xb, hoffb[3]) - hp[1]);
                 yz[m] = (lo + hi) - T(2) * mid;
                 cc[m] = c[3];
             }
