@@ -694,35 +694,140 @@ k_press_rhs(PressArgs a, const T* __restrict__ C, const T* __restrict__ ph,
 
 // Solve along z per (ky, kx) mode after the 2-D transforms in x and y
 // (between walls): (1/h^2)(p[k+1] - 2 p[k] + p[k-1]) + lxy p[k] = f[k] with
-// p[-1] = p[0], p[nz] = p[nz-1] (dP/dz = 0), by the Thomas algorithm (the
-// rows are diagonally dominant for lxy < 0).  The mean mode (lxy = 0) is
-// singular: its mean over z is removed from f, then p[0] = 0 and the rows
+// p[-1] = p[0], p[nz] = p[nz-1] (dP/dz = 0).  The rows are diagonally
+// dominant for lxy < 0 and are eliminated from both ends at once: lane l
+// (l < 32) of a wave takes mode g*32 + l from row 0 up to row M - 1 (M = nz/2),
+// lane l + 32 the same mode from row nz - 1 down to M + 1; row M then
+// couples the two eliminated halves,
+//   (b_M - c_{M-1}/h^2 - e_{M+1}/h^2) p_M = f_M - (d_{M-1} + g_{M+1})/h^2,
+// and each lane substitutes back over its half.  This halves the serial chain
+// and doubles the threads of the plain Thomas sweep.  The mean mode (lxy = 0)
+// is singular: its mean over z is removed from f, then p[0] = 0 and the rows
 // 0 .. nz-2 give p[1 .. nz-1] by p[k+1] = 2 p[k] - p[k-1] + h^2 f[k]
 // (p[-1] = p[0]), and the mean of p is removed.  Spectra are [nz][ny][nxh]
 // complex (re, im interleaved); cp holds nz x nmodes reals of scratch.  The
 // result is scaled by `scale` (the inverse transform's 1 / (nx ny)).
 template <typename T>
+struct Cplx;
+template <>
+struct Cplx<float> {
+    typedef float2 V;
+};
+template <>
+struct Cplx<double> {
+    typedef double2 V;
+};
+
+template <typename T>
 __global__ void __launch_bounds__(256)
 k_press_tri(T* __restrict__ spec, T* __restrict__ cp, int nx, int ny, int nz, double h,
             double scale)
 {
+    typedef typename Cplx<T>::V V;
     const int nxh = nx / 2 + 1;
     const int64_t nm = (int64_t)ny * nxh;
+    const int64_t ngroups = (nm + 31) / 32;
     const double PI = 3.14159265358979323846;
-    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nm;
-         m += (int64_t)gridDim.x * blockDim.x) {
-        const int j = (int)(m / nxh), i = (int)(m - (int64_t)j * nxh);
+    const int lane = threadIdx.x & 63;
+    const int half = lane >> 5;
+    const int M = nz / 2;
+    const int len = half == 0 ? M : nz - 1 - M;   // rows eliminated by this lane
+    const T ih2 = T(1.0 / (h * h));
+    const T sc = T(scale);
+    const int64_t st = nm;                          // complex elements between planes
+    constexpr int PK = sizeof(T) == 4 ? 8 : 4;      // planes loaded ahead
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    // the group loop is uniform over a wave: every lane reaches the exchange
+    for (int64_t g = wave0; g < ngroups; g += nwaves) {
+        const int64_t m = g * 32 + (lane & 31);
+        const bool live = m < nm;
+        const bool special = m == 0;
+        const int64_t mm = live ? m : 0;
+        const int j = (int)(mm / nxh), i = (int)(mm - (int64_t)j * nxh);
         const double sx = sin(PI * i / nx), sy = sin(PI * j / ny);
-        const T ih2 = T(1.0 / (h * h));
         const T lxy = T(-4.0 / (h * h) * (sx * sx + sy * sy));
-        T* f = spec + 2 * m;            // f[k] at f + 2 k nm
-        const int64_t st = 2 * nm;
-        const T sc = T(scale);
-        if (i == 0 && j == 0) {
+        V* f = reinterpret_cast<V*>(spec) + mm;       // f[k] at f + k nm
+        auto row = [&](int s) { return half == 0 ? s : nz - 1 - s; };
+        auto diag = [&](int k) { return lxy - (k == 0 || k == nz - 1 ? ih2 : T(2) * ih2); };
+        // elimination towards row M: c into cp, d into f
+        T c = T(0), dr = T(0), di = T(0);
+        if (live && !special) {
+            for (int s0 = 0; s0 < len; s0 += PK) {
+                V fv[PK];
+#pragma unroll
+                for (int q = 0; q < PK; ++q) fv[q] = f[row(s0 + q < len ? s0 + q : len - 1) * st];
+#pragma unroll
+                for (int q = 0; q < PK; ++q) {
+                    const int sq = s0 + q;
+                    if (sq >= len) break;
+                    const int k = row(sq);
+                    const T den = diag(k) - ih2 * c;
+                    c = ih2 / den;
+                    dr = (fv[q].x - ih2 * dr) / den;
+                    di = (fv[q].y - ih2 * di) / den;
+                    V o;
+                    o.x = dr;
+                    o.y = di;
+                    f[k * st] = o;
+                    cp[k * nm + m] = c;
+                }
+            }
+        }
+        // row M, read by the lower lane only, and the other half's last
+        // coefficients (zero for an empty half), across the wave
+        T fmr = T(0), fmi = T(0);
+        if (live && !special && half == 0) {
+            const V v = f[M * st];
+            fmr = v.x;
+            fmi = v.y;
+        }
+        const T oc = __shfl_xor(c, 32), odr = __shfl_xor(dr, 32), odi = __shfl_xor(di, 32);
+        const T ofr = __shfl_xor(fmr, 32), ofi = __shfl_xor(fmi, 32);
+        if (live && !special) {
+            if (half == 1) {
+                fmr = ofr;
+                fmi = ofi;
+            }
+            const T den = diag(M) - ih2 * (c + oc);
+            T xr = (fmr - ih2 * (dr + odr)) / den;
+            T xi = (fmi - ih2 * (di + odi)) / den;
+            if (half == 0) {
+                V o;
+                o.x = xr * sc;
+                o.y = xi * sc;
+                f[M * st] = o;
+            }
+            // back substitution from row M outwards
+            for (int s1 = len - 1; s1 >= 0; s1 -= PK) {
+                V fv[PK];
+                T cc[PK];
+#pragma unroll
+                for (int q = 0; q < PK; ++q) {
+                    const int k = row(s1 - q >= 0 ? s1 - q : 0);
+                    fv[q] = f[k * st];
+                    cc[q] = cp[k * nm + m];
+                }
+#pragma unroll
+                for (int q = 0; q < PK; ++q) {
+                    const int sq = s1 - q;
+                    if (sq < 0) break;
+                    xr = fv[q].x - cc[q] * xr;
+                    xi = fv[q].y - cc[q] * xi;
+                    V o;
+                    o.x = xr * sc;
+                    o.y = xi * sc;
+                    f[row(sq) * st] = o;
+                }
+            }
+        }
+        if (live && special && half == 0) {
+            T* fs = spec;                  // mode 0: f[k] at fs + 2 k nm
+            const int64_t s2 = 2 * nm;
             T mr = T(0), mi = T(0);
             for (int k = 0; k < nz; ++k) {
-                mr += f[k * st];
-                mi += f[k * st + 1];
+                mr += fs[k * s2];
+                mi += fs[k * s2 + 1];
             }
             mr /= T(nz);
             mi /= T(nz);
@@ -730,9 +835,9 @@ k_press_tri(T* __restrict__ spec, T* __restrict__ cp, int nx, int ny, int nz, do
             T pr = T(0), pi = T(0), qr = T(0), qi = T(0);   // p[k-1], p[k]
             T sr = T(0), si = T(0);
             for (int k = 0; k < nz; ++k) {
-                const T fr = f[k * st] - mr, fi = f[k * st + 1] - mi;
-                f[k * st] = qr;         // p[k]
-                f[k * st + 1] = qi;
+                const T fr = fs[k * s2] - mr, fi = fs[k * s2 + 1] - mi;
+                fs[k * s2] = qr;         // p[k]
+                fs[k * s2 + 1] = qi;
                 sr += qr;
                 si += qi;
                 const T lr = k == 0 ? qr : pr, li = k == 0 ? qi : pi;
@@ -745,57 +850,8 @@ k_press_tri(T* __restrict__ spec, T* __restrict__ cp, int nx, int ny, int nz, do
             sr /= T(nz);
             si /= T(nz);
             for (int k = 0; k < nz; ++k) {
-                f[k * st] = (f[k * st] - sr) * sc;
-                f[k * st + 1] = (f[k * st + 1] - si) * sc;
-            }
-            continue;
-        }
-        // forward sweep: c'_k into cp, d'_k into f; the right-hand sides of
-        // PK planes are loaded before they are used
-        constexpr int PK = sizeof(T) == 4 ? 8 : 4;
-        T cprev = T(0), dr = T(0), di = T(0);
-        for (int k0 = 0; k0 < nz; k0 += PK) {
-            T fr[PK], fi[PK];
-#pragma unroll
-            for (int q = 0; q < PK; ++q) {
-                const int k = k0 + q < nz ? k0 + q : nz - 1;
-                fr[q] = f[k * st];
-                fi[q] = f[k * st + 1];
-            }
-#pragma unroll
-            for (int q = 0; q < PK; ++q) {
-                const int k = k0 + q;
-                if (k >= nz) break;
-                const T b = lxy - (k == 0 || k == nz - 1 ? ih2 : T(2) * ih2);
-                const T den = b - (k > 0 ? ih2 * cprev : T(0));
-                const T c = k + 1 < nz ? ih2 / den : T(0);
-                dr = (fr[q] - (k > 0 ? ih2 * dr : T(0))) / den;
-                di = (fi[q] - (k > 0 ? ih2 * di : T(0))) / den;
-                f[k * st] = dr;
-                f[k * st + 1] = di;
-                cp[k * nm + m] = c;
-                cprev = c;
-            }
-        }
-        // back substitution, PK planes loaded at a time
-        T xr = T(0), xi = T(0);
-        for (int k1 = nz - 1; k1 >= 0; k1 -= PK) {
-            T fr[PK], fi[PK], cc[PK];
-#pragma unroll
-            for (int q = 0; q < PK; ++q) {
-                const int k = k1 - q >= 0 ? k1 - q : 0;
-                fr[q] = f[k * st];
-                fi[q] = f[k * st + 1];
-                cc[q] = cp[k * nm + m];
-            }
-#pragma unroll
-            for (int q = 0; q < PK; ++q) {
-                const int k = k1 - q;
-                if (k < 0) break;
-                xr = fr[q] - (k + 1 < nz ? cc[q] * xr : T(0));
-                xi = fi[q] - (k + 1 < nz ? cc[q] * xi : T(0));
-                f[k * st] = xr * sc;
-                f[k * st + 1] = xi * sc;
+                fs[k * s2] = (fs[k * s2] - sr) * sc;
+                fs[k * s2 + 1] = (fs[k * s2 + 1] - si) * sc;
             }
         }
     }
@@ -1061,9 +1117,10 @@ hipError_t launch_press_solve(hipStream_t st, int zwalls, void* spec, void* cp, 
                               int nz, double h)
 {
     if (zwalls) {
+        // one wave per 32 modes (two lanes per mode)
         const int64_t nm = (int64_t)ny * (nx / 2 + 1);
-        hipLaunchKernelGGL((k_press_tri<T>), dim3(grid_for(nm)), dim3(256), 0, st, (T*)spec,
-                           (T*)cp, nx, ny, nz, h, 1.0 / ((double)nx * ny));
+        hipLaunchKernelGGL((k_press_tri<T>), dim3(grid_for((nm + 31) / 32 * 64)), dim3(256), 0, st,
+                           (T*)spec, (T*)cp, nx, ny, nz, h, 1.0 / ((double)nx * ny));
     } else {
         const int64_t n = (int64_t)nz * ny * (nx / 2 + 1);
         hipLaunchKernelGGL((k_press_div<T>), dim3(grid_for(n)), dim3(256), 0, st, (T*)spec, nx,

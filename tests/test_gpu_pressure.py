@@ -37,7 +37,8 @@ def _inputs(shape, zwalls, seed):
 
 
 @pytest.mark.parametrize("shape", [(8, 12, 10), (9, 8, 16), (12, 6, 8), (32, 64, 48),
-                                   (10, 7, 15)])   # odd y and x extents
+                                   (10, 7, 15),    # odd y and x extents
+                                   (2, 8, 8), (3, 6, 10)])   # one row each side of the middle
 @pytest.mark.parametrize("zwalls", [False, True])
 def test_poisson_solve_matches_oracle(shape, zwalls):
     from paper_2105_01865_amd import ch
