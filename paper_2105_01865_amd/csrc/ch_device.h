@@ -214,6 +214,17 @@ CH_HD void sched_fence()
 #endif
 }
 
+// Keep a wave-uniform value in a lane register from here on.
+template <typename T>
+CH_HD void in_vgpr(T& v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+v"(v));
+#else
+    (void)v;
+#endif
+}
+
 // Wait until every global load the wave has issued has landed (vmcnt(0);
 // expcnt and lgkmcnt untouched).  Used at the end of a loop's prologue: a load
 // left pending there makes the compiler's conservative merge at the loop
@@ -652,7 +663,7 @@ struct XState {
     T hq[MI][2][2];
 };
 
-template <typename T, typename A, int MI, bool E25, class X>
+template <typename T, typename A, int MI, bool E25, class X, bool VCONST = false>
 CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const PassArgs& pa,
                           int task, const T* __restrict__ C, const T* __restrict__ U,
                           const T* __restrict__ V, const T* __restrict__ W, T* __restrict__ E,
@@ -685,10 +696,24 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
     const T* Wb = W + bd.w_off;
     T* Eb = E + bd.c_off;
     T* Qb = Q + bd.c_off;
-    const T epsw = T(bd.eps * (12.0 / 13.0));
-    const T gdt = T(bd.gdt[k]), rdt = T(bd.rdt[k]), bdt = T(bd.bdt[k]);
-    const T inv_h = T(bd.inv_h), lap_s = T(bd.inv_h2 * bd.inv_pe);
-    const Cubic<T> mu = cubic<T>(bd.psi);
+    T epsw = T(bd.eps * (12.0 / 13.0));
+    T gdt = T(bd.gdt[k]), rdt = T(bd.rdt[k]), bdt = T(bd.bdt[k]);
+    T inv_h = T(bd.inv_h), lap_s = T(bd.inv_h2 * bd.inv_pe);
+    Cubic<T> mu = cubic<T>(bd.psi);
+    if constexpr (VCONST) {
+        // these constants live in lane registers, where the kernel has room,
+        // instead of scalar registers, which run out in double precision
+        in_vgpr(epsw);
+        in_vgpr(gdt);
+        in_vgpr(rdt);
+        in_vgpr(bdt);
+        in_vgpr(inv_h);
+        in_vgpr(lap_s);
+        in_vgpr(mu.c0);
+        in_vgpr(mu.c1);
+        in_vgpr(mu.c2);
+        in_vgpr(mu.c3);
+    }
     const A a1 = A(bd.a1[k]), a2 = A(bd.a2[k]), ic = A(bd.ic[k]);
     const int rows = t.rows;
     const int ncell = rows * nx;

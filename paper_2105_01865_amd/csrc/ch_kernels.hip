@@ -52,7 +52,10 @@ k_pass_x(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
     const int b = chd::find_box(boxes, nbox, chd::PASS_X, task);
     chd::GpuExec ex{(int)threadIdx.x, (int)blockDim.x};
     chd::XState<T, A, MI> st;
-    chd::pass_x_program<T, A, MI, E25>(ex, &st, boxes[b], pa, task, C, U, V, W, E, Q, smem);
+    // double precision with registers to spare: uniform constants in lane registers
+    constexpr bool VCONST = sizeof(T) == 8 && MI == 1 && NT <= 512 && !E25;
+    chd::pass_x_program<T, A, MI, E25, chd::GpuExec, VCONST>(ex, &st, boxes[b], pa, task, C, U, V,
+                                                             W, E, Q, smem);
 }
 
 template <typename T, typename A, int PASS>
