@@ -24,4 +24,5 @@ def test_weno_face_arithmetic_identities():
         r = subprocess.run([exe], capture_output=True, text=True,
                            env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"))
     print(r.stdout[-2000:])
-    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout[-2000:] + r.stderr[-2000:]
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), \
+        r.stdout[-2000:] + r.stderr[-2000:]
