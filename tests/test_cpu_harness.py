@@ -64,7 +64,8 @@ def test_config1_fp64_matches_oracle():
 
 @pytest.mark.parametrize("zc", [1, 3, 7])
 @pytest.mark.parametrize("shape,bc", [((20, 12, 16), (0, 0, 0)), ((16, 9, 24), (0, 0, 1)),
-                                      ((12, 16, 8), (1, 0, 1)), ((1, 24, 16), (0, 0, 0))])
+                                      ((12, 16, 8), (1, 0, 1)), ((1, 24, 16), (0, 0, 0)),
+                                      ((16, 20, 1), (0, 0, 0)), ((12, 1, 16), (0, 0, 1))])
 def test_fp64_matches_oracle_ragged_and_walls(shape, bc, zc):
     b = _box(shape, bc=bc, seed=1, amp=2.0)
     dt = 2e-4

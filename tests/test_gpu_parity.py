@@ -79,6 +79,9 @@ def test_config1_fp64_one_step_and_ten_steps():
     ((20, 12, 16), (0, 0, 0), dict(x_rows=3, seg_len=5, waves_yz=3)),
     ((16, 9, 24), (0, 0, 1), dict(x_rows=5, seg_len=7)),
     ((1, 24, 40), (0, 0, 0), {}),
+    ((16, 20, 1), (0, 0, 0), {}),                      # degenerate x: every column is its own halo
+    ((16, 20, 1), (0, 0, 0), dict(x_rows=3, z_chunk=3)),
+    ((12, 1, 16), (0, 0, 1), {}),                      # degenerate y
     ((48, 48, 48), (0, 0, 0), {}),
     ((40, 33, 72), (0, 0, 1), {}),
     ((96, 96, 96), (0, 0, 0), {}),
