@@ -281,7 +281,7 @@ void ch_poisson_destroy(ch_poisson* p);
  * The tiles of the x pass (rows per task, planes per task) are chosen by a
  * heuristic at creation.  ch_autotune / ch_batch_autotune time `steps` RK3
  * steps (1 .. 1000, after one untimed step) of every plan in the candidate
- * set  x_rows in {auto, 1, 2, 4} x z_chunk in {auto, 4, 6, ..., 16}  that
+ * set  x_rows in {auto, 1, 2, 4} x z_chunk in {auto, 4, 6, ..., 16, 20, 24}  that
  * the planner admits for dt, then the y / z segment lengths {auto, 128, 64}
  * with the fastest of those, each from the same C with the given velocity
  * (borrowed device pointers, as for ch_step), and keep the fastest as the

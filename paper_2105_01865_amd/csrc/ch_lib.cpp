@@ -691,7 +691,7 @@ ch_status autotune(Engine& e, const void* u, const void* v, const void* w, doubl
     // again last, where its time is taken
     std::vector<std::pair<int, int>> cand = {{0, 0}};
     for (int r : {1, 2, 4})
-        for (int z : {0, 4, 6, 8, 10, 12, 14, 16}) cand.push_back({r, z});
+        for (int z : {0, 4, 6, 8, 10, 12, 14, 16, 20, 24}) cand.push_back({r, z});
     cand.push_back({0, 0});
     hipEvent_t t0 = nullptr, t1 = nullptr;
     ch_status st = CH_OK;

@@ -78,6 +78,16 @@ def test_fp64_matches_oracle_ragged_and_walls(shape, bc, zc):
     assert plan["ntask"][1] > 0
 
 
+@pytest.mark.parametrize("shape,bc,zc", [((60, 10, 32), (0, 0, 0), 24), ((50, 9, 24), (0, 0, 1), 20)])
+def test_fp64_long_marches(shape, bc, zc):
+    # more planes per task than the automatic plan takes (the autotuner's
+    # 20 and 24), ragged last march
+    b = _box(shape, bc=bc, seed=7, amp=2.0)
+    out, _, plan = run_emu([b], 2e-4, 2, z_chunk=zc, x_rows=1)
+    assert plan["z_chunk"] == zc
+    assert _rel(out[0], _oracle(b, 2e-4, 2)) < 1e-12
+
+
 def test_fp64_large_dt_needs_long_warmup():
     b = _box((16, 16, 16), seed=2, amp=0.5, drops=False)
     dt = 0.05          # r >> 1: long recurrence warm-up, wrapping the line
