@@ -254,7 +254,8 @@ ch_status ch_step_multires(ch_state* s, ch_interp* ip, const void* uc, const voi
  * The density is rho = rho2 + (rho1 - rho2) clamp(C, 0, 1) (rho2 <= rho1),
  * taken on a face as the mean of its two cells.  Creation makes the hipFFT
  * plans and the work arrays (three fields and a spectrum); nx, ny, nz >= 2
- * (CH_EINVAL), fewer than 2^31 cells (CH_EUNSUPPORTED).  Device memory in
+ * (CH_EINVAL), fewer than 2^31 cells and planes (nx ny) under 4 GiB
+ * (CH_EUNSUPPORTED).  Device memory in
  * the given precision; work is enqueued on the handle's stream.
  *
  * ch_poisson_solve: P with lap P = rhs - mean(rhs) and zero mean, for the

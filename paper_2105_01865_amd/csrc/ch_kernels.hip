@@ -656,41 +656,100 @@ k_press_prep(const T* __restrict__ P, T* __restrict__ Pold, T* __restrict__ phat
     }
 }
 
-// Right-hand side of eq-newpoi at every cell, one (z, y) row per work-group:
+// The cell kernels of the pressure step take tiles of TX x-columns by TY
+// rows and march each column up TZ planes, carrying the plane below in
+// registers, so no plane is fetched twice for its z neighbours.  Planes are
+// addressed through 32-bit byte offsets from a per-plane base (a plane is
+// under 4 GiB).
+struct PressTile {
+    int tx, ty, tz;
+};
+constexpr PressTile RHS_TILE = {256, 2, 8}, UPD_TILE = {256, 1, 2};
+
+__host__ __device__ __forceinline__ int64_t press_tiles(PressTile p, int nx, int ny, int nz)
+{
+    return (int64_t)((nx + p.tx - 1) / p.tx) * ((ny + p.ty - 1) / p.ty) * ((nz + p.tz - 1) / p.tz);
+}
+
+// Column of thread t in task `task`: x, y and the march z0 .. z1 - 1; false
+// for a thread past the mesh.
+__device__ __forceinline__ bool press_column(PressTile p, int64_t task, int t, int nx, int ny,
+                                             int nz, int* x, int* y, int* z0, int* z1)
+{
+    const int tx = (nx + p.tx - 1) / p.tx, ty = (ny + p.ty - 1) / p.ty;
+    const int bx = (int)(task % tx);
+    const int64_t rest = task / tx;
+    const int by = (int)(rest % ty), bz = (int)(rest / ty);
+    *x = bx * p.tx + t % p.tx;
+    *y = by * p.ty + t / p.tx;
+    *z0 = bz * p.tz;
+    *z1 = *z0 + p.tz < nz ? *z0 + p.tz : nz;
+    return *x < nx && *y < ny;
+}
+
+// Right-hand side of eq-newpoi at every cell:
 // div[(1 - rho2/rho_f) grad Phat] + (rho2/dt) div u*.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(RHS_TILE.tx * RHS_TILE.ty)
 k_press_rhs(PressArgs a, const T* __restrict__ C, const T* __restrict__ ph,
             const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
             T* __restrict__ rhs)
 {
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int64_t plane = (int64_t)nx * ny;
+    constexpr uint32_t sT = sizeof(T);
+    const uint32_t pbytes = (uint32_t)(plane * sT);
     const T ih = T(1.0 / a.h), r2 = T(a.rho2), sdiv = T(a.rho2 / a.dt);
-    for (int64_t row = blockIdx.x; row < (int64_t)ny * nz; row += gridDim.x) {
-        const int z = (int)(row / ny), y = (int)(row - (int64_t)z * ny);
+    auto at = [&](const T* f, int z) { return chd::PlaneRef<T>(f + (int64_t)z * plane, pbytes); };
+    const int64_t ntask = press_tiles(RHS_TILE, nx, ny, nz);
+    for (int64_t task = blockIdx.x; task < ntask; task += gridDim.x) {
+        int x, y, z0, z1;
+        if (!press_column(RHS_TILE, task, (int)threadIdx.x, nx, ny, nz, &x, &y, &z0, &z1)) continue;
+        const int xm = x > 0 ? x - 1 : nx - 1, xp = x + 1 < nx ? x + 1 : 0;
         const int ym = y > 0 ? y - 1 : ny - 1, yp = y + 1 < ny ? y + 1 : 0;
-        const int zm = z > 0 ? z - 1 : nz - 1, zp = z + 1 < nz ? z + 1 : 0;
-        for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-            const int xm = x > 0 ? x - 1 : nx - 1, xp = x + 1 < nx ? x + 1 : 0;
-            const int64_t c = row * nx + x;
-            const T rc = press_rho(a, C[c]), pc = ph[c];
-            // flux through the face between cells c and nb (nb on the + side
-            // when s = 1): (1 - rho2/rho_f) (ph[hi] - ph[lo]) / h
-            auto flux = [&](int64_t nb, int s) {
-                const T rf = T(0.5) * (rc + press_rho(a, C[nb]));
-                const T g = s > 0 ? ph[nb] - pc : pc - ph[nb];
+        const uint32_t oc = (uint32_t)(y * nx + x) * sT, oxm = (uint32_t)(y * nx + xm) * sT,
+                       oxp = (uint32_t)(y * nx + xp) * sT, oym = (uint32_t)(ym * nx + x) * sT,
+                       oyp = (uint32_t)(yp * nx + x) * sT;
+        // rho and Phat of the column below the march (periodic wrap; not used
+        // at the bottom wall) and at its first plane, and w on its low face
+        T rlo = T(0), plo = T(0);
+        if (z0 > 0 || !a.zwalls) {
+            const int zb = z0 > 0 ? z0 - 1 : nz - 1;
+            rlo = press_rho(a, at(C, zb)(oc));
+            plo = at(ph, zb)(oc);
+        }
+        T rc = press_rho(a, at(C, z0)(oc)), pc = at(ph, z0)(oc);
+        T wlo = at(w, z0)(oc);
+        for (int z = z0; z < z1; ++z) {
+            const int zp = z + 1 < nz ? z + 1 : 0;
+            const bool up = !a.zwalls || z + 1 < nz;
+            T rhi = T(0), phi = T(0);
+            if (up) {
+                rhi = press_rho(a, at(C, zp)(oc));
+                phi = at(ph, zp)(oc);
+            }
+            const T whi = at(w, a.zwalls ? z + 1 : zp)(oc);
+            const chd::PlaneRef<T> Cz = at(C, z), Pz = at(ph, z), Uz = at(u, z), Vz = at(v, z);
+            // flux through the face between the cell and a neighbour (on the +
+            // side when s = 1): (1 - rho2/rho_f) (Phat[hi] - Phat[lo]) / h
+            auto flux = [&](T rn, T pn, int s) {
+                const T rf = T(0.5) * (rc + rn);
+                const T g = s > 0 ? pn - pc : pc - pn;
                 return (T(1) - r2 * chd::fast_rcp(rf)) * g * ih;
             };
-            T d = flux(row * nx + xp, 1) - flux(row * nx + xm, -1)
-                + flux(((int64_t)z * ny + yp) * nx + x, 1) - flux(((int64_t)z * ny + ym) * nx + x, -1);
-            if (!a.zwalls || z + 1 < nz) d += flux(c - (int64_t)z * plane + (int64_t)zp * plane, 1);
-            if (!a.zwalls || z > 0) d -= flux(c - (int64_t)z * plane + (int64_t)zm * plane, -1);
-            const T du = u[row * nx + xp] - u[c];
-            const T dv = v[((int64_t)z * ny + yp) * nx + x] - v[c];
-            const T dw = a.zwalls ? w[c + plane] - w[c]
-                                  : w[(int64_t)zp * plane + (int64_t)y * nx + x] - w[c];
-            rhs[c] = d * ih + sdiv * (du + dv + dw) * ih;
+            T d = flux(press_rho(a, Cz(oxp)), Pz(oxp), 1) - flux(press_rho(a, Cz(oxm)), Pz(oxm), -1)
+                + flux(press_rho(a, Cz(oyp)), Pz(oyp), 1) - flux(press_rho(a, Cz(oym)), Pz(oym), -1);
+            if (up) d += flux(rhi, phi, 1);
+            if (!a.zwalls || z > 0) d -= flux(rlo, plo, -1);
+            const T du = Uz(oxp) - Uz(oc);
+            const T dv = Vz(oyp) - Vz(oc);
+            const T dw = whi - wlo;
+            at(rhs, z).store(oc, d * ih + sdiv * (du + dv + dw) * ih);
+            rlo = rc;
+            plo = pc;
+            rc = rhi;
+            pc = phi;
+            wlo = whi;
         }
     }
 }
@@ -882,31 +941,49 @@ k_press_div(T* __restrict__ spec, int nx, int ny, int nz, double h, double scale
     }
 }
 
-// eq-u on the low faces of every cell (the wall faces of z stay as they are).
+// eq-u on the low faces of every cell (the wall faces of z stay as they are),
+// z-marching tiles as for the right-hand side.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(UPD_TILE.tx * UPD_TILE.ty)
 k_press_update(PressArgs a, const T* __restrict__ C, const T* __restrict__ P,
                const T* __restrict__ ph, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w)
 {
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int64_t plane = (int64_t)nx * ny;
+    constexpr uint32_t sT = sizeof(T);
+    const uint32_t pbytes = (uint32_t)(plane * sT);
     const T ih = T(1.0 / a.h), ir2 = T(1.0 / a.rho2), dt = T(a.dt);
-    for (int64_t row = blockIdx.x; row < (int64_t)ny * nz; row += gridDim.x) {
-        const int z = (int)(row / ny), y = (int)(row - (int64_t)z * ny);
-        const int ym = y > 0 ? y - 1 : ny - 1, zm = z > 0 ? z - 1 : nz - 1;
-        for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-            const int xm = x > 0 ? x - 1 : nx - 1;
-            const int64_t c = row * nx + x;
-            const T rc = press_rho(a, C[c]), pc = P[c], hc = ph[c];
-            auto corr = [&](int64_t nb) {   // face between nb (low side) and c
-                const T rf = T(0.5) * (rc + press_rho(a, C[nb]));
-                return dt * ((pc - P[nb]) * ih * ir2
-                             + (chd::fast_rcp(rf) - ir2) * (hc - ph[nb]) * ih);
+    auto at = [&](const T* f, int z) { return chd::PlaneRef<T>(f + (int64_t)z * plane, pbytes); };
+    const int64_t ntask = press_tiles(UPD_TILE, nx, ny, nz);
+    for (int64_t task = blockIdx.x; task < ntask; task += gridDim.x) {
+        int x, y, z0, z1;
+        if (!press_column(UPD_TILE, task, (int)threadIdx.x, nx, ny, nz, &x, &y, &z0, &z1)) continue;
+        const int xm = x > 0 ? x - 1 : nx - 1, ym = y > 0 ? y - 1 : ny - 1;
+        const uint32_t oc = (uint32_t)(y * nx + x) * sT, oxm = (uint32_t)(y * nx + xm) * sT,
+                       oym = (uint32_t)(ym * nx + x) * sT;
+        // rho, P and Phat of the column below the march (periodic wrap; not
+        // used at the bottom wall)
+        T rlo = T(0), qlo = T(0), hlo = T(0);
+        if (z0 > 0 || !a.zwalls) {
+            const int zb = z0 > 0 ? z0 - 1 : nz - 1;
+            rlo = press_rho(a, at(C, zb)(oc));
+            qlo = at(P, zb)(oc);
+            hlo = at(ph, zb)(oc);
+        }
+        for (int z = z0; z < z1; ++z) {
+            const chd::PlaneRef<T> Cz = at(C, z), Pz = at(P, z), Hz = at(ph, z);
+            const T rc = press_rho(a, Cz(oc)), pc = Pz(oc), hc = Hz(oc);
+            auto corr = [&](T rn, T qn, T hn) {   // face between a low neighbour and the cell
+                const T rf = T(0.5) * (rc + rn);
+                return dt * ((pc - qn) * ih * ir2 + (chd::fast_rcp(rf) - ir2) * (hc - hn) * ih);
             };
-            u[c] -= corr(row * nx + xm);
-            v[c] -= corr(((int64_t)z * ny + ym) * nx + x);
-            if (!a.zwalls) w[c] -= corr((int64_t)zm * plane + (int64_t)y * nx + x);
-            else if (z > 0) w[c] -= corr(c - plane);
+            const chd::PlaneRef<T> Uz = at(u, z), Vz = at(v, z), Wz = at(w, z);
+            Uz.store(oc, Uz(oc) - corr(press_rho(a, Cz(oxm)), Pz(oxm), Hz(oxm)));
+            Vz.store(oc, Vz(oc) - corr(press_rho(a, Cz(oym)), Pz(oym), Hz(oym)));
+            if (!a.zwalls || z > 0) Wz.store(oc, Wz(oc) - corr(rlo, qlo, hlo));
+            rlo = rc;
+            qlo = pc;
+            hlo = hc;
         }
     }
 }
@@ -1108,9 +1185,9 @@ template <typename T>
 hipError_t launch_press_rhs(hipStream_t st, const PressArgs& a, const void* C, const void* phat,
                             const void* u, const void* v, const void* w, void* rhs)
 {
-    const int64_t rows = (int64_t)a.ny * a.nz;
-    hipLaunchKernelGGL((k_press_rhs<T>), dim3((unsigned)(rows < 262144 ? rows : 262144)),
-                       dim3(256), 0, st, a, (const T*)C, (const T*)phat, (const T*)u,
+    const int64_t tiles = press_tiles(RHS_TILE, a.nx, a.ny, a.nz);
+    hipLaunchKernelGGL((k_press_rhs<T>), dim3((unsigned)(tiles < 1048576 ? tiles : 1048576)),
+                       dim3(RHS_TILE.tx * RHS_TILE.ty), 0, st, a, (const T*)C, (const T*)phat, (const T*)u,
                        (const T*)v, (const T*)w, (T*)rhs);
     return hipGetLastError();
 }
@@ -1136,10 +1213,10 @@ template <typename T>
 hipError_t launch_press_update(hipStream_t st, const PressArgs& a, const void* C, const void* P,
                                const void* phat, void* u, void* v, void* w)
 {
-    const int64_t rows = (int64_t)a.ny * a.nz;
-    hipLaunchKernelGGL((k_press_update<T>), dim3((unsigned)(rows < 262144 ? rows : 262144)),
-                       dim3(256), 0, st, a, (const T*)C, (const T*)P, (const T*)phat, (T*)u,
-                       (T*)v, (T*)w);
+    const int64_t tiles = press_tiles(UPD_TILE, a.nx, a.ny, a.nz);
+    hipLaunchKernelGGL((k_press_update<T>), dim3((unsigned)(tiles < 1048576 ? tiles : 1048576)),
+                       dim3(UPD_TILE.tx * UPD_TILE.ty), 0, st, a, (const T*)C, (const T*)P, (const T*)phat,
+                       (T*)u, (T*)v, (T*)w);
     return hipGetLastError();
 }
 

@@ -1394,6 +1394,8 @@ ch_status ch_poisson_create(const ch_grid* g, int z_walls, int precision, ch_poi
         return fail(CH_EINVAL, "the pressure mesh needs at least 2 cells per axis and h > 0");
     if ((double)g->nx * g->ny * (g->nz + 1) >= 2147483647.0)
         return fail(CH_EUNSUPPORTED, "pressure mesh of 2^31 cells or more");
+    if ((double)g->nx * g->ny * (precision == CH_FP64 ? 8.0 : 4.0) >= 4294967296.0)
+        return fail(CH_EUNSUPPORTED, "pressure mesh plane of 4 GiB or more");
     ch_poisson* p = new (std::nothrow) ch_poisson();
     if (!p) return fail(CH_ENOMEM, "host allocation failed");
     p->nx = (int)g->nx;
