@@ -54,6 +54,10 @@ def test_poisson_create_rejects_bad_meshes():
     assert L.ch_poisson_create(ctypes.byref(g), 0, 5, ctypes.byref(h)) == EINVAL
     g = ch.Grid(4096, 4096, 4096, 1e-3)
     assert L.ch_poisson_create(ctypes.byref(g), 1, ch.CH_FP32, ctypes.byref(h)) == EUNSUPPORTED
+    # under 2^31 cells, but an FP64 plane of 24000^2 cells is over 4 GiB
+    g = ch.Grid(24000, 24000, 2, 1e-3)
+    assert L.ch_poisson_create(ctypes.byref(g), 1, ch.CH_FP64, ctypes.byref(h)) == EUNSUPPORTED
+    assert "4 GiB" in L.ch_last_error().decode()
     assert h.value is None
 
 
