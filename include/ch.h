@@ -61,7 +61,7 @@ typedef enum {
     CH_EINVAL = -1,        /* invalid argument */
     CH_ENOMEM = -2,        /* device or host allocation failed */
     CH_EHIP = -3,          /* a HIP runtime call failed */
-    CH_EUNSUPPORTED = -4,  /* valid request this build does not support */
+    CH_EUNSUPPORTED = -4,  /* valid request outside what the library supports */
     CH_ENONFINITE = -5,    /* NaN or Inf found by a checking call */
     CH_EHANDLE = -6        /* handle not live (destroyed or never created) */
 } ch_status;

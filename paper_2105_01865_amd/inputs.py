@@ -360,5 +360,5 @@ def make_workload(config: int, n: int | None = None, seed: int | None = None, bo
 
 
 def ensemble(nbox=48, n_override=None):
-    """The batched ensemble: nbox independent periodic boxes (config 5)."""
+    """The batched ensemble: nbox independent periodic boxes."""
     return [make_workload(5, n=n_override, box=b) for b in range(nbox)]

@@ -124,7 +124,7 @@ def random_solenoidal(gen, shape, h, kmin, kmax, slope=-5.0 / 3.0, rms=1.0, devi
 
 def large_workload(n: int | None = None, device="cuda", dtype=torch.float32):
     """The 1536^3 periodic box: 4000 drops R ~ U[4,20] h (placement by the
-    host sampler, seed of config 4), k^-5/3 field on 1 <= |k| <= 48 with
+    host sampler, seed of the 1536^3 workload), k^-5/3 field on 1 <= |k| <= 48 with
     rms 1; dt = 1e-4 unless the advective bound sum_d max|u_d| dt / h <= 0.8
     needs less.  `n` shrinks the edge (drops scale with the volume)."""
     n = n or 1536

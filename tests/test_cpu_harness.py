@@ -52,7 +52,7 @@ def _rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
-def test_config1_fp64_matches_oracle():
+def test_32cube_fp64_matches_oracle():
     wl = inputs.make_workload(1)
     b = dict(C=wl.C, u=wl.u, v=wl.v, w=wl.w, h=wl.h, Cn=wl.Cn, Pe=wl.Pe, bc=(0, 0, 0))
     (C1,), (m,), plan = run_emu([b], wl.dt, 2)

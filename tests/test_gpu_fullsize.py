@@ -27,11 +27,11 @@ def _dev(a, dt_=torch.float64):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt_)
 
 
-def test_config3_full_size_one_step_against_oracle(wl3):
+def test_multires_512cube_full_size_one_step_against_oracle(wl3):
     wl = wl3
     nz, ny, nx = wl.shape
     zf, uc, vc, wc = (wl.coarse[k] for k in ("zf", "uc", "vc", "wc"))
-    print(f"[gpu] config 3 at {wl.shape}: oracle transfer + step", flush=True)
+    print(f"[gpu] multiple-resolution box {wl.shape}: oracle transfer + step", flush=True)
     uf, vf, wf = oracle.interp_velocity(zf, uc, vc, wc, (nx, ny, nz))
     ref = oracle.step(wl.C, uf, vf, wf, wl.h, wl.Cn, wl.Pe, wl.dt, 1, bc=wl.bc)
     del uf, vf, wf

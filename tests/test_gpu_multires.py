@@ -34,7 +34,7 @@ def _coarse(seed, nc, alpha=2.0):
     return zf, uc, vc, wc
 
 
-@pytest.mark.parametrize("fine,nc", [((32, 32, 32), (12, 16, 16)),       # config 3, shrunk
+@pytest.mark.parametrize("fine,nc", [((32, 32, 32), (12, 16, 16)),       # 512^3 workload shrunk
                                      ((36, 40, 48), (10, 16, 20)),       # uneven ratios
                                      ((24, 24, 24), (24, 24, 24)),       # same counts
                                      ((20, 18, 30), (8, 12, 16)),        # x targets not 4k
@@ -124,7 +124,7 @@ def test_solenoidal_transfer_matches_oracle(fine, nc):
 
 def test_solenoidal_transfer_is_divergence_free_on_the_gpu():
     """Property at a size beyond the oracle's small cases: a discrete-curl
-    coarse field (config 3's generator, 48 x 64 x 64) to a 128^3 fine mesh;
+    coarse field (the 512^3 workload's generator, 48 x 64 x 64) to a 128^3 fine mesh;
     the FP64 fine divergence is zero to rounding in every cell but the top
     layer, and the periodic closures vanish (ratio 2)."""
     nc = (48, 64, 64)

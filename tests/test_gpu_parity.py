@@ -65,7 +65,7 @@ def run_gpu(C, u, v, w, h, Cn, Pe, dt, nsteps, bc=(0, 0, 0), precision="fp64", s
     return out, cfg
 
 
-def test_config1_fp64_one_step_and_ten_steps():
+def test_32cube_fp64_one_step_and_ten_steps():
     wl = inputs.make_workload(1)
     for n, tol in ((1, TOL64), (10, 1e-11)):
         got, _ = run_gpu(wl.C, wl.u, wl.v, wl.w, wl.h, wl.Cn, wl.Pe, wl.dt, n)
@@ -223,7 +223,7 @@ def test_error_paths():
     s.close()
 
 
-def test_config2_full_size_fp64_one_step_against_oracle():
+def test_256cube_full_size_fp64_one_step_against_oracle():
     """The 256^3 workload in the launch configuration the benchmark times
     (default plan, graph replay on a stream), one step against the oracle."""
     wl = inputs.make_workload(2)
@@ -237,7 +237,7 @@ def test_config2_full_size_fp64_one_step_against_oracle():
     assert rel(got32, ref) <= 5e-6
 
 
-def test_config5_full_ensemble_sampled_boxes_against_oracle():
+def test_48box_ensemble_sampled_boxes_against_oracle():
     """The whole 48-box ensemble (about 1.2e8 points) in one batch, in the
     launch configuration the benchmark times: every box conserves its mass,
     and the smallest boxes of each edge up to 96 match the oracle."""
@@ -272,7 +272,7 @@ def test_config5_full_ensemble_sampled_boxes_against_oracle():
 
 def test_explicit25_against_oracle():
     """The explicit 25-point scheme (no line solves) against the oracle's:
-    config 1, a walled ragged box, FP32, and the 256^3 box at full size."""
+    the 32^3 box, a walled ragged box, FP32, and the 256^3 box at full size."""
     wl = inputs.make_workload(1)
     cases = [(wl.C, wl.u, wl.v, wl.w, wl.h, (0, 0, 0), 1e-4, 2)]
     C, u, v, w, h = _case((16, 9, 24), bc=(0, 0, 1), seed=21)

@@ -75,7 +75,7 @@ def test_seeds_are_reproducible():
     np.testing.assert_array_equal(c.C, d.C)
 
 
-def test_config1_matches_its_description():
+def test_32cube_workload_matches_its_description():
     w = inputs.make_workload(1)
     assert w.shape == (32, 32, 32) and w.h == 1 / 32 and w.Cn == w.h
     assert abs(w.Pe - 0.9 / w.Cn) < 1e-12 and w.dt == 1e-4 and w.nsteps == 100
