@@ -767,8 +767,9 @@ k_press_rhs(PressArgs a, const T* __restrict__ C, const T* __restrict__ ph,
 // is singular: its mean over z is removed from f, then p[0] = 0 and the rows
 // 0 .. nz-2 give p[1 .. nz-1] by p[k+1] = 2 p[k] - p[k-1] + h^2 f[k]
 // (p[-1] = p[0]), and the mean of p is removed.  Spectra are [nz][ny][nxh]
-// complex (re, im interleaved); cp holds nz x nmodes reals of scratch.  The
-// result is scaled by `scale` (the inverse transform's 1 / (nx ny)).
+// complex (re, im interleaved); cp holds nz x nmodes reals of scratch, of
+// which one per block of PK rows is used.  The result is scaled by `scale`
+// (the inverse transform's 1 / (nx ny)).
 template <typename T>
 struct Cplx;
 template <>
@@ -812,10 +813,13 @@ k_press_tri(T* __restrict__ spec, T* __restrict__ cp, int nx, int ny, int nz, do
         V* f = reinterpret_cast<V*>(spec) + mm;       // f[k] at f + k nm
         auto row = [&](int s) { return half == 0 ? s : nz - 1 - s; };
         auto diag = [&](int k) { return lxy - (k == 0 || k == nz - 1 ? ih2 : T(2) * ih2); };
-        // elimination towards row M: c into cp, d into f
+        // elimination towards row M in blocks of PK rows: d into f, and into
+        // cp at each block's first row the c entering the block (the block's
+        // c are formed again from it on the way back)
         T c = T(0), dr = T(0), di = T(0);
         if (live && !special) {
             for (int s0 = 0; s0 < len; s0 += PK) {
+                cp[row(s0) * nm + m] = c;
                 V fv[PK];
 #pragma unroll
                 for (int q = 0; q < PK; ++q) fv[q] = f[row(s0 + q < len ? s0 + q : len - 1) * st];
@@ -832,7 +836,6 @@ k_press_tri(T* __restrict__ spec, T* __restrict__ cp, int nx, int ny, int nz, do
                     o.x = dr;
                     o.y = di;
                     f[k * st] = o;
-                    cp[k * nm + m] = c;
                 }
             }
         }
@@ -860,20 +863,27 @@ k_press_tri(T* __restrict__ spec, T* __restrict__ cp, int nx, int ny, int nz, do
                 o.y = xi * sc;
                 f[M * st] = o;
             }
-            // back substitution from row M outwards
-            for (int s1 = len - 1; s1 >= 0; s1 -= PK) {
+            // back substitution from row M outwards, block by block: the
+            // block's c again from its checkpoint (the same operations as on
+            // the way up, so the same values), then its rows in reverse
+            for (int s0 = len > 0 ? (len - 1) / PK * PK : -1; s0 >= 0; s0 -= PK) {
                 V fv[PK];
                 T cc[PK];
+                T cin = cp[row(s0) * nm + m];
+#pragma unroll
+                for (int q = 0; q < PK; ++q) fv[q] = f[row(s0 + q < len ? s0 + q : len - 1) * st];
 #pragma unroll
                 for (int q = 0; q < PK; ++q) {
-                    const int k = row(s1 - q >= 0 ? s1 - q : 0);
-                    fv[q] = f[k * st];
-                    cc[q] = cp[k * nm + m];
+                    cc[q] = T(0);
+                    if (s0 + q >= len) break;
+                    const T den = diag(row(s0 + q)) - ih2 * cin;
+                    cin = ih2 / den;
+                    cc[q] = cin;
                 }
 #pragma unroll
-                for (int q = 0; q < PK; ++q) {
-                    const int sq = s1 - q;
-                    if (sq < 0) break;
+                for (int q = PK - 1; q >= 0; --q) {
+                    const int sq = s0 + q;
+                    if (sq >= len) continue;
                     xr = fv[q].x - cc[q] * xr;
                     xi = fv[q].y - cc[q] * xi;
                     V o;
