@@ -665,6 +665,11 @@ struct PressTile {
     int tx, ty, tz;
 };
 constexpr PressTile RHS_TILE = {256, 2, 8}, UPD_TILE = {256, 1, 2};
+constexpr PressTile RHS_TILE64 = {64, 4, 16}, UPD_TILE64 = {256, 1, 2};
+template <typename T>
+constexpr PressTile rhs_tile() { return sizeof(T) == 8 ? RHS_TILE64 : RHS_TILE; }
+template <typename T>
+constexpr PressTile upd_tile() { return sizeof(T) == 8 ? UPD_TILE64 : UPD_TILE; }
 
 __host__ __device__ __forceinline__ int64_t press_tiles(PressTile p, int nx, int ny, int nz)
 {
@@ -690,7 +695,7 @@ __device__ __forceinline__ bool press_column(PressTile p, int64_t task, int t, i
 // Right-hand side of eq-newpoi at every cell:
 // div[(1 - rho2/rho_f) grad Phat] + (rho2/dt) div u*.
 template <typename T>
-__global__ void __launch_bounds__(RHS_TILE.tx * RHS_TILE.ty)
+__global__ void __launch_bounds__(rhs_tile<T>().tx * rhs_tile<T>().ty)
 k_press_rhs(PressArgs a, const T* __restrict__ C, const T* __restrict__ ph,
             const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
             T* __restrict__ rhs)
@@ -701,10 +706,10 @@ k_press_rhs(PressArgs a, const T* __restrict__ C, const T* __restrict__ ph,
     const uint32_t pbytes = (uint32_t)(plane * sT);
     const T ih = T(1.0 / a.h), r2 = T(a.rho2), sdiv = T(a.rho2 / a.dt);
     auto at = [&](const T* f, int z) { return chd::PlaneRef<T>(f + (int64_t)z * plane, pbytes); };
-    const int64_t ntask = press_tiles(RHS_TILE, nx, ny, nz);
+    const int64_t ntask = press_tiles(rhs_tile<T>(), nx, ny, nz);
     for (int64_t task = blockIdx.x; task < ntask; task += gridDim.x) {
         int x, y, z0, z1;
-        if (!press_column(RHS_TILE, task, (int)threadIdx.x, nx, ny, nz, &x, &y, &z0, &z1)) continue;
+        if (!press_column(rhs_tile<T>(), task, (int)threadIdx.x, nx, ny, nz, &x, &y, &z0, &z1)) continue;
         const int xm = x > 0 ? x - 1 : nx - 1, xp = x + 1 < nx ? x + 1 : 0;
         const int ym = y > 0 ? y - 1 : ny - 1, yp = y + 1 < ny ? y + 1 : 0;
         const uint32_t oc = (uint32_t)(y * nx + x) * sT, oxm = (uint32_t)(y * nx + xm) * sT,
@@ -954,7 +959,7 @@ k_press_div(T* __restrict__ spec, int nx, int ny, int nz, double h, double scale
 // eq-u on the low faces of every cell (the wall faces of z stay as they are),
 // z-marching tiles as for the right-hand side.
 template <typename T>
-__global__ void __launch_bounds__(UPD_TILE.tx * UPD_TILE.ty)
+__global__ void __launch_bounds__(upd_tile<T>().tx * upd_tile<T>().ty)
 k_press_update(PressArgs a, const T* __restrict__ C, const T* __restrict__ P,
                const T* __restrict__ ph, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w)
 {
@@ -964,10 +969,10 @@ k_press_update(PressArgs a, const T* __restrict__ C, const T* __restrict__ P,
     const uint32_t pbytes = (uint32_t)(plane * sT);
     const T ih = T(1.0 / a.h), ir2 = T(1.0 / a.rho2), dt = T(a.dt);
     auto at = [&](const T* f, int z) { return chd::PlaneRef<T>(f + (int64_t)z * plane, pbytes); };
-    const int64_t ntask = press_tiles(UPD_TILE, nx, ny, nz);
+    const int64_t ntask = press_tiles(upd_tile<T>(), nx, ny, nz);
     for (int64_t task = blockIdx.x; task < ntask; task += gridDim.x) {
         int x, y, z0, z1;
-        if (!press_column(UPD_TILE, task, (int)threadIdx.x, nx, ny, nz, &x, &y, &z0, &z1)) continue;
+        if (!press_column(upd_tile<T>(), task, (int)threadIdx.x, nx, ny, nz, &x, &y, &z0, &z1)) continue;
         const int xm = x > 0 ? x - 1 : nx - 1, ym = y > 0 ? y - 1 : ny - 1;
         const uint32_t oc = (uint32_t)(y * nx + x) * sT, oxm = (uint32_t)(y * nx + xm) * sT,
                        oym = (uint32_t)(ym * nx + x) * sT;
@@ -1195,9 +1200,10 @@ template <typename T>
 hipError_t launch_press_rhs(hipStream_t st, const PressArgs& a, const void* C, const void* phat,
                             const void* u, const void* v, const void* w, void* rhs)
 {
-    const int64_t tiles = press_tiles(RHS_TILE, a.nx, a.ny, a.nz);
+    constexpr PressTile tl = rhs_tile<T>();
+    const int64_t tiles = press_tiles(tl, a.nx, a.ny, a.nz);
     hipLaunchKernelGGL((k_press_rhs<T>), dim3((unsigned)(tiles < 1048576 ? tiles : 1048576)),
-                       dim3(RHS_TILE.tx * RHS_TILE.ty), 0, st, a, (const T*)C, (const T*)phat, (const T*)u,
+                       dim3(tl.tx * tl.ty), 0, st, a, (const T*)C, (const T*)phat, (const T*)u,
                        (const T*)v, (const T*)w, (T*)rhs);
     return hipGetLastError();
 }
@@ -1223,9 +1229,10 @@ template <typename T>
 hipError_t launch_press_update(hipStream_t st, const PressArgs& a, const void* C, const void* P,
                                const void* phat, void* u, void* v, void* w)
 {
-    const int64_t tiles = press_tiles(UPD_TILE, a.nx, a.ny, a.nz);
+    constexpr PressTile tl = upd_tile<T>();
+    const int64_t tiles = press_tiles(tl, a.nx, a.ny, a.nz);
     hipLaunchKernelGGL((k_press_update<T>), dim3((unsigned)(tiles < 1048576 ? tiles : 1048576)),
-                       dim3(UPD_TILE.tx * UPD_TILE.ty), 0, st, a, (const T*)C, (const T*)P, (const T*)phat,
+                       dim3(tl.tx * tl.ty), 0, st, a, (const T*)C, (const T*)P, (const T*)phat,
                        (T*)u, (T*)v, (T*)w);
     return hipGetLastError();
 }
