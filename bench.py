@@ -348,6 +348,56 @@ def bench_large(args, stream):
             "plan": cfg, "autotune": tune}
 
 
+def bench_host_io(args, stream, wl, tune):
+    """The 256^3 FP32 box with C handed over in host memory: C copied in from
+    pinned host memory through ch_set_field, `steps_per_trip` steps, C copied
+    back out through ch_get_field, the velocity resident on the GPU.  Host
+    wall time of whole round trips (the copies wait for the stream)."""
+    import numpy as np
+    import torch
+    from paper_2105_01865_amd import ch
+    pts = wl.points
+    U, V, W = (torch.from_numpy(a).to(device="cuda", dtype=torch.float32)
+               for a in (wl.u, wl.v, wl.w))
+    hC = torch.from_numpy(wl.C.astype(np.float32)).pin_memory()
+    out = torch.empty(wl.shape, dtype=torch.float32).pin_memory()
+    plan = ({k: tune[k] for k in ("x_rows", "z_chunk", "seg_len")} if tune else {})
+    s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, precision="fp32", stream=stream, **plan)
+    s.set_field_host(hC)
+    s.step(U, V, W, wl.dt, 2)
+    s.get_field_host(out)
+    res = {}
+    for k in (1, 10):
+        t_in, t_step, t_out = [], [], []
+        for _ in range(args.host_io_reps):
+            t0 = time.perf_counter()
+            s.set_field_host(hC)
+            t1 = time.perf_counter()
+            s.step(U, V, W, wl.dt, k)
+            stream.synchronize()
+            t2 = time.perf_counter()
+            s.get_field_host(out)
+            t3 = time.perf_counter()
+            t_in.append(t1 - t0)
+            t_step.append(t2 - t1)
+            t_out.append(t3 - t2)
+        med = lambda a: float(np.median(a))
+        trip = med([a + b + c for a, b, c in zip(t_in, t_step, t_out)])
+        res[f"steps_per_trip_{k}"] = {"value": round(pts * k / trip / 1e9, 4), "unit": "Gpts/s",
+                                      "trip_ms": round(trip * 1e3, 3),
+                                      "h2d_ms": round(med(t_in) * 1e3, 3),
+                                      "steps_ms": round(med(t_step) * 1e3, 3),
+                                      "d2h_ms": round(med(t_out) * 1e3, 3)}
+    s.close()
+    nbytes = pts * 4
+    r1 = res["steps_per_trip_1"]
+    return {"workload": "256^3 FP32 box, C in and out through pinned host memory each trip, "
+                        "velocity resident, the headline's launch plan",
+            "reps": args.host_io_reps, "field_bytes": nbytes,
+            "h2d_gbs": round(nbytes / (r1["h2d_ms"] * 1e-3) / 1e9, 1),
+            "d2h_gbs": round(nbytes / (r1["d2h_ms"] * 1e-3) / 1e9, 1), **res}
+
+
 def bench_explicit25(args, stream, line):
     """The paper's starting point, the explicit 25-point biharmonic (no line
     solves), on the same 256^3 workload: its throughput at 0.85 of the
@@ -407,6 +457,7 @@ def main():
     ap.add_argument("--large-steps", type=int, default=10)
     ap.add_argument("--explicit-steps", type=int, default=200)
     ap.add_argument("--pressure-steps", type=int, default=20)
+    ap.add_argument("--host-io-reps", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the planner's automatic tiles (no launch-plan autotuning)")
     ap.add_argument("--no-extra", action="store_true",
@@ -565,6 +616,8 @@ def main():
         "kernels_fp64": kern(r64),
     }
 
+    line["host_io"] = bench_host_io(args, stream, wl, r32["tune"])
+    progress("host-memory round trips done")
     if not args.no_extra:
         line["batched"] = bench_ensemble(args, stream)
         progress("ensemble done")

@@ -123,8 +123,11 @@ ch_status ch_create(const ch_grid* g, double Cn, double Pe, const ch_psi* psi,
 ch_status ch_set_stream(ch_state* s, void* stream);
 
 /* Copy C in / out: nx*ny*nz values in the state's precision, x fastest.
- * on_device = 1: C is device memory; 0: host memory.  ch_get_field waits for
- * the copy. */
+ * on_device = 1: C is device memory; 0: host memory (pinned memory copies
+ * fastest).  ch_get_field always waits for the copy; ch_set_field waits when
+ * C is host memory, so the host buffer may be reused on return, and only
+ * enqueues a device-to-device copy.  Errors: CH_EINVAL (null pointer),
+ * CH_EHIP, CH_EHANDLE. */
 ch_status ch_set_field(ch_state* s, const void* C, int on_device);
 ch_status ch_get_field(ch_state* s, void* C, int on_device);
 

@@ -180,6 +180,18 @@ def _dev_tensor(t, dtype, shape, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _host_tensor(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cpu":
+        raise ValueError(f"{name} must be a CPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def _drops_call(fn, args, cap):
     """Run ch_drops / ch_batch_drops, growing the host arrays once if the
     box has more than `cap` drops.  Returns (root, cells) int64 arrays."""
@@ -252,6 +264,24 @@ class State(_StreamMixin):
         out = torch.empty(self.shape, dtype=self.dtype, device="cuda")
         self._enter()
         _check(lib().ch_get_field(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+        self._leave()
+        return out
+
+    def set_field_host(self, C):
+        """Copy C in from host memory (a CPU tensor; pinned memory copies
+        fastest).  Returns once the copy is done."""
+        ptr = _host_tensor(C, self.dtype, self.shape, "C")
+        self._enter()
+        _check(lib().ch_set_field(self._h, ptr, 0))
+        self._leave()
+
+    def get_field_host(self, out=None):
+        """Copy C out into host memory (`out`, or a new pinned CPU tensor)."""
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, pin_memory=True)
+        ptr = _host_tensor(out, self.dtype, self.shape, "out")
+        self._enter()
+        _check(lib().ch_get_field(self._h, ptr, 0))
         self._leave()
         return out
 
@@ -400,6 +430,23 @@ class Batch(_StreamMixin):
         out = torch.empty(self.totals[0], dtype=self.dtype, device="cuda")
         self._enter()
         _check(lib().ch_batch_get_field(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+        self._leave()
+        return out
+
+    def set_field_host(self, C_packed):
+        """Copy the packed C in from host memory; returns once it is done."""
+        ptr = _host_tensor(C_packed, self.dtype, (self.totals[0],), "C")
+        self._enter()
+        _check(lib().ch_batch_set_field(self._h, ptr, 0))
+        self._leave()
+
+    def get_field_host(self, out=None):
+        """Copy the packed C out into host memory (`out`, or a new pinned tensor)."""
+        if out is None:
+            out = torch.empty(self.totals[0], dtype=self.dtype, pin_memory=True)
+        ptr = _host_tensor(out, self.dtype, (self.totals[0],), "out")
+        self._enter()
+        _check(lib().ch_batch_get_field(self._h, ptr, 0))
         self._leave()
         return out
 

@@ -193,6 +193,55 @@ def test_checkpoint_resume_is_bitwise():
     s2.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_host_memory_fields_single_box(prec):
+    """C copied in and out through host memory (on_device = 0), from pinned and
+    from pageable tensors: the round trip returns C bit for bit, and steps
+    from a host copy equal steps from a device copy bit for bit."""
+    C, u, v, w, h = _case((12, 10, 36), seed=21)
+    dt_ = torch.float64 if prec == "fp64" else torch.float32
+    ref, _ = run_gpu(C, u, v, w, h, h, 0.9 / h, 1e-4, 2, precision=prec)
+    U, V, W = dev(u, dt_), dev(v, dt_), dev(w, dt_)
+    for pinned in (True, False):
+        print(f"[gpu] host fields {C.shape} {prec} pinned={pinned}", flush=True)
+        hC = torch.from_numpy(C).to(dt_)
+        hC = hC.pin_memory() if pinned else hC.contiguous()
+        s = ch.State(C.shape, h, h, 0.9 / h, precision=prec, stream=torch.cuda.Stream())
+        s.set_field_host(hC)
+        assert torch.equal(s.get_field_host(), hC)
+        out = torch.empty(C.shape, dtype=dt_)              # pageable
+        assert torch.equal(s.get_field_host(out), hC)
+        s.step(U, V, W, 1e-4, 2)
+        got = s.get_field_host(out).double().numpy()
+        s.close()
+        assert np.array_equal(got, ref)
+    with pytest.raises(ValueError, match="CPU tensor"):
+        s = ch.State(C.shape, h, h, 0.9 / h, precision=prec)
+        try:
+            s.set_field_host(dev(C, dt_))
+        finally:
+            s.close()
+
+
+def test_host_memory_fields_batch():
+    cases = [_case((16, 16, 16), seed=22), _case((12, 8, 24), seed=23)]
+    shapes = [c[0].shape for c in cases]
+    hs = [c[4] for c in cases]
+    b = ch.Batch(shapes, hs, hs, [0.9 / h for h in hs], stream=torch.cuda.Stream())
+    packed = b.pack([c[0] for c in cases], "c")
+    U, V, W = (b.pack([c[k] for c in cases], "uvw"[k - 1]) for k in (1, 2, 3))
+    print(f"[gpu] host fields batch {shapes}", flush=True)
+    b.set_field(packed)
+    b.step(U, V, W, 1e-4, 2)
+    ref = b.get_field().cpu()
+    hC = packed.cpu().pin_memory()
+    b.set_field_host(hC)
+    assert torch.equal(b.get_field_host(), hC)
+    b.step(U, V, W, 1e-4, 2)
+    assert torch.equal(b.get_field_host(), ref)
+    b.close()
+
+
 def test_error_paths():
     with pytest.raises(ch.CHError, match="EINVAL"):
         ch.State((4, 16, 16), 0.1, 0.1, 1.0)          # 4 cells on an axis
