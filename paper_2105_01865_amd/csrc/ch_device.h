@@ -413,10 +413,10 @@ CH_HD int line_chunk_len(int n, int tw, int cap)
     return K < 1 ? 1 : K;
 }
 
-CH_HD Chunk line_chunk(int tid, int nl, int n, int tw, int cap)
+// Chunk of thread tid for chunks of length K (line_chunk_len).
+CH_HD Chunk line_chunk_k(int tid, int nl, int n, int tw, int K)
 {
     Chunk ch;
-    const int K = line_chunk_len(n, tw, cap);
     ch.l = tid % nl;
     const int c = tid / nl;
     ch.c0 = c * K;
@@ -425,6 +425,11 @@ CH_HD Chunk line_chunk(int tid, int nl, int n, int tw, int cap)
     ch.fend = last ? n + tw : ch.c0 + K;
     ch.bend = ch.c0 + K < n ? ch.c0 + K : n;
     return ch;
+}
+
+CH_HD Chunk line_chunk(int tid, int nl, int n, int tw, int cap)
+{
+    return line_chunk_k(tid, nl, n, tw, line_chunk_len(n, tw, cap));
 }
 
 // The recurrences walk the tile in batches of LB values: the batch's loads
@@ -1126,80 +1131,104 @@ CH_HD LTask l_task(const BoxDesc& bd, const PassArgs& pa, int pass, int task)
     return t;
 }
 
+// Lanes of a y/z task: x columns of 128 bytes of accumulators (the planner's
+// `lanes`).
+template <typename A>
+constexpr int line_lanes()
+{
+    return 128 / (int)sizeof(A);
+}
+
 template <typename T, typename A, class X>
 CH_HD void pass_line_program(X& ex, LineState<A>* st, const BoxDesc& bd, const PassArgs& pa,
                              int pass, int task, const T* __restrict__ Qin,
                              T* __restrict__ Qout, unsigned char* smem)
 {
+    constexpr int Lw = line_lanes<A>();
     const LTask t = l_task(bd, pa, pass, task);
-    const int Lw = pa.lanes, nth = ex.nth, k = pa.k, tw = bd.tw[k];
+    const int nth = ex.nth, k = pa.k, tw = bd.tw[k];
     const int nlive = bd.n[0] - t.x0 < Lw ? bd.n[0] - t.x0 : Lw;
     const A a1 = A(bd.a1[k]), a2 = A(bd.a2[k]), ic = A(bd.ic[k]);
     A* tile = reinterpret_cast<A*>(smem);
     const int npos = t.len + 2 * tw;
-    // stage the segment with its halos: LB rows of loads in flight per thread
+    // a thread walks rows q0, q0 + qstep, ... of the tile, LB rows per batch
+    // with their loads in flight together; `dstep` is the distance in the
+    // field between two rows of a batch
     const int qstep = nth / Lw;
+    const int span = (LB - 1) * qstep;
+    const int64_t dstep = (int64_t)qstep * t.stride;
+    // stage the segment with its halos; tile row q holds line position
+    // s0 + q - tw.  A batch inside [0, n) walks one column pointer; a batch
+    // that reaches a halo outside the line maps every position.
     ex.phase([&](int tid) {
         const int l = tid % Lw;
         const bool on = l < nlive;
+        const T* col = Qin + t.base + l;
         for (int q0 = tid / Lw; q0 < npos; q0 += qstep * LB) {
-            A v[LB];
+            const int i0 = t.s0 + q0 - tw;
+            A* trow = tile + q0 * Lw + l;
+            if (on && i0 >= 0 && i0 + span < t.n && q0 + span < npos) {
+                const T* p = col + (int64_t)i0 * t.stride;
+                A v[LB];
 #pragma unroll
-            for (int j = 0; j < LB; ++j) {
-                const int q = q0 + j * qstep;
-                v[j] = A(0);
-                if (q < npos && on)
-                    v[j] = A(Qin[t.base + (int64_t)map_idx(t.s0 + q - tw, t.n, t.bc) * t.stride + l]);
-            }
+                for (int j = 0; j < LB; ++j) v[j] = A(p[j * dstep]);
 #pragma unroll
-            for (int j = 0; j < LB; ++j) {
-                const int q = q0 + j * qstep;
-                if (q < npos) tile[q * Lw + l] = v[j];
+                for (int j = 0; j < LB; ++j) trow[j * qstep * Lw] = v[j];
+            } else {
+                A v[LB];
+#pragma unroll
+                for (int j = 0; j < LB; ++j) {
+                    const int q = q0 + j * qstep;
+                    v[j] = A(0);
+                    if (q < npos && on)
+                        v[j] = A(col[(int64_t)map_idx(t.s0 + q - tw, t.n, t.bc) * t.stride]);
+                }
+#pragma unroll
+                for (int j = 0; j < LB; ++j)
+                    if (q0 + j * qstep < npos) trow[j * qstep * Lw] = v[j];
             }
         }
     });
+    const int K = line_chunk_len(t.len, tw, YZ_CHAINS);
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, Lw, t.len, tw, YZ_CHAINS);
+        const Chunk ch = line_chunk_k(tid, Lw, t.len, tw, K);
         line_f1<A>(ch, tile, Lw, tw, a1, a2, ic, st[ex.slot(tid)]);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, Lw, t.len, tw, YZ_CHAINS);
+        const Chunk ch = line_chunk_k(tid, Lw, t.len, tw, K);
         line_f2<A>(ch, tile, Lw, tw, a1, a2, ic, st[ex.slot(tid)]);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, Lw, t.len, tw, YZ_CHAINS);
+        const Chunk ch = line_chunk_k(tid, Lw, t.len, tw, K);
         line_b1<A>(ch, tile, Lw, tw, a1, a2, st[ex.slot(tid)]);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, Lw, t.len, tw, YZ_CHAINS);
+        const Chunk ch = line_chunk_k(tid, Lw, t.len, tw, K);
         line_b2<A>(ch, tile, Lw, tw, a1, a2, st[ex.slot(tid)]);
     });
+    // write the segment back (pass Z: C += dC); only the last batch of a
+    // thread can reach past the segment
     ex.phase([&](int tid) {
         const int l = tid % Lw;
         if (l >= nlive) return;
         for (int q0 = tid / Lw; q0 < t.len; q0 += qstep * LB) {
+            T* p = Qout + t.base + l + (int64_t)(t.s0 + q0) * t.stride;
+            const A* trow = tile + (q0 + tw) * Lw + l;
+            const bool full = q0 + span < t.len;
             if (pass == PASS_Z) {
                 // C += dC: the LB reads of C go out together
                 A c[LB];
 #pragma unroll
-                for (int j = 0; j < LB; ++j) {
-                    const int q = q0 + j * qstep;
-                    c[j] = q < t.len ? A(Qout[t.base + (int64_t)(t.s0 + q) * t.stride + l]) : A(0);
-                }
+                for (int j = 0; j < LB; ++j)
+                    c[j] = full || q0 + j * qstep < t.len ? A(p[j * dstep]) : A(0);
 #pragma unroll
-                for (int j = 0; j < LB; ++j) {
-                    const int q = q0 + j * qstep;
-                    if (q < t.len)
-                        Qout[t.base + (int64_t)(t.s0 + q) * t.stride + l] =
-                            T(c[j] + tile[(q + tw) * Lw + l]);
-                }
+                for (int j = 0; j < LB; ++j)
+                    if (full || q0 + j * qstep < t.len)
+                        p[j * dstep] = T(c[j] + trow[j * qstep * Lw]);
             } else {
 #pragma unroll
-                for (int j = 0; j < LB; ++j) {
-                    const int q = q0 + j * qstep;
-                    if (q < t.len)
-                        Qout[t.base + (int64_t)(t.s0 + q) * t.stride + l] = T(tile[(q + tw) * Lw + l]);
-                }
+                for (int j = 0; j < LB; ++j)
+                    if (full || q0 + j * qstep < t.len) p[j * dstep] = T(trow[j * qstep * Lw]);
             }
         }
     });
