@@ -181,6 +181,8 @@ ch_status ch_batch_create(int nbox, const ch_grid* g, const double* Cn, const do
 ch_status ch_batch_field_offsets(const ch_batch* b, int64_t* c_off, int64_t* u_off,
                                  int64_t* v_off, int64_t* w_off, int64_t totals[4]);
 ch_status ch_batch_set_stream(ch_batch* b, void* stream);
+/* Copy the packed C (totals[0] values) in / out; on_device and waiting as
+ * for ch_set_field / ch_get_field. */
 ch_status ch_batch_set_field(ch_batch* b, const void* C_packed, int on_device);
 ch_status ch_batch_get_field(ch_batch* b, void* C_packed, int on_device);
 ch_status ch_batch_step(ch_batch* b, const void* u_packed, const void* v_packed,
