@@ -13,7 +13,7 @@ throughput on a bounded sample of the same workload are reported on the
 same JSON line.
 
     python bench.py [--steps K] [--warmup W]
-    python bench.py --counter-probe    # 2 FP32 steps + one 256 MiB device
+    python bench.py --counter-probe [fp64]    # 2 FP32 (FP64) steps + one 256 MiB device
                                        # copy, for rocprofv3 counter runs
 """
 import argparse
@@ -89,17 +89,19 @@ def measured_traffic():
     return float(val.group(1))
 
 
-def counter_probe():
-    """A short run for rocprofv3 counter passes: two FP32 steps of the
-    workload, then one device-to-device copy of 256 MiB (the kernel whose
-    FETCH_SIZE / WRITE_SIZE readings calibrate the counters)."""
+def counter_probe(prec="fp32"):
+    """A short run for rocprofv3 counter passes: two steps of the workload
+    (FP32 unless `prec` says otherwise), then one device-to-device copy of
+    256 MiB (the kernel whose FETCH_SIZE / WRITE_SIZE readings calibrate the
+    counters)."""
     import torch
     from paper_2105_01865_amd import ch, inputs
     wl = inputs.make_workload(2)
     stream = torch.cuda.Stream()
-    s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, precision="fp32", stream=stream)
-    s.set_field(torch.from_numpy(wl.C).to("cuda", torch.float32))
-    U, V, W = (torch.from_numpy(a).to("cuda", torch.float32) for a in (wl.u, wl.v, wl.w))
+    dt_ = torch.float64 if prec == "fp64" else torch.float32
+    s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, precision=prec, stream=stream)
+    s.set_field(torch.from_numpy(wl.C).to("cuda", dt_))
+    U, V, W = (torch.from_numpy(a).to("cuda", dt_) for a in (wl.u, wl.v, wl.w))
     s.step(U, V, W, wl.dt, 2)
     torch.cuda.synchronize()
     s.close()
@@ -462,14 +464,16 @@ def main():
                     help="keep the planner's automatic tiles (no launch-plan autotuning)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-ensemble and multiple-resolution lines")
-    ap.add_argument("--counter-probe", action="store_true")
+    ap.add_argument("--counter-probe", nargs="?", const="fp32", default=None,
+                    choices=("fp32", "fp64"),
+                    help="two steps and a 256 MiB copy, for rocprofv3 counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library "
               "has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.counter_probe:
-        counter_probe()
+        counter_probe(args.counter_probe)
         return
 
     import numpy as np
