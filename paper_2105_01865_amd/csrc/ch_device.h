@@ -89,14 +89,11 @@ CH_HD int map_idx(int i, int n, int bc)
         if (bc == 0) return i < 0 ? i + n : i - n;
         return i < 0 ? -1 - i : 2 * n - 1 - i;
     }
-    if (bc == 0) {
-        int m = i % n;
-        return m < 0 ? m + n : m;
-    }
-    int p = 2 * n;
-    int m = i % p;
-    if (m < 0) m += p;
-    return m < n ? m : p - 1 - m;
+    // far out (warm-ups longer than the line): i lies in copy q of the line,
+    // at offset r; under reflection every odd-numbered copy runs backwards
+    const int q = i >= 0 ? i / n : -((n - 1 - i) / n);
+    const int r = i - q * n;
+    return (bc != 0 && (q & 1)) ? n - 1 - r : r;
 }
 
 // 1/x: on the GPU one hardware reciprocal (1 ulp) in single precision, and in

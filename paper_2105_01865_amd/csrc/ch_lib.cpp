@@ -17,7 +17,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
-#include <unordered_set>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/ch.h"
@@ -47,21 +47,33 @@ ch_status fail(ch_status st, const char* fmt, ...)
             return fail(CH_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
     } while (0)
 
-// live handles
-std::mutex g_mu;
-std::unordered_set<const void*> g_live;
+// live handles, each with the kind of object it names: a handle of one kind
+// passed where another is expected is rejected like a destroyed one
+enum HandleKind { H_STATE = 1, H_BATCH = 2, H_INTERP = 3, H_POISSON = 4 };
+constexpr HandleKind kind_of(const ch_state*) { return H_STATE; }
+constexpr HandleKind kind_of(const ch_batch*) { return H_BATCH; }
+constexpr HandleKind kind_of(const ch_interp*) { return H_INTERP; }
+constexpr HandleKind kind_of(const ch_poisson*) { return H_POISSON; }
 
-void reg(const void* p)
+std::mutex g_mu;
+std::unordered_map<const void*, HandleKind> g_live;
+
+template <typename H>
+void reg(const H* p)
 {
     std::lock_guard<std::mutex> l(g_mu);
-    g_live.insert(p);
+    g_live[p] = kind_of(p);
 }
-bool live(const void* p)
+template <typename H>
+bool live(const H* p)
 {
     std::lock_guard<std::mutex> l(g_mu);
-    return p && g_live.count(p);
+    if (!p) return false;
+    const auto it = g_live.find(p);
+    return it != g_live.end() && it->second == kind_of(p);
 }
-void unreg(const void* p)
+template <typename H>
+void unreg(const H* p)
 {
     std::lock_guard<std::mutex> l(g_mu);
     g_live.erase(p);
@@ -844,64 +856,10 @@ ch_status profile_enable(Engine& e, int on)
     return CH_OK;
 }
 
-// ---- multiple resolution: 1-D cubic Hermite stencils -----------------------
-// Source points s[0..n) on an axis: periodic (period 1), or between walls at
-// 0 and 1, continued evenly (cell-centred values) or oddly (face values that
-// include both walls, s[0] = 0, s[n-1] = 1).
-enum { SRC_PERIODIC = 0, SRC_EVEN = 1, SRC_ODD = 2 };
-
-struct Src {
-    std::vector<double> s;
-    int kind;
-    // coordinate, stored index and sign of extended point m
-    double at(long m, long* idx, double* sgn) const
-    {
-        const long n = (long)s.size();
-        *sgn = 1.0;
-        if (kind == SRC_PERIODIC) {
-            long q = m >= 0 ? m / n : -((-m + n - 1) / n);
-            long r = m - q * n;
-            *idx = r;
-            return s[r] + (double)q;
-        }
-        if (kind == SRC_EVEN) {
-            if (m < 0) { *idx = -1 - m; return -s[-1 - m]; }
-            if (m >= n) { *idx = 2 * n - 1 - m; return 2.0 - s[2 * n - 1 - m]; }
-            *idx = m;
-            return s[m];
-        }
-        if (m < 0) { *idx = -m; *sgn = -1.0; return -s[-m]; }
-        if (m >= n) { *idx = 2 * n - 2 - m; *sgn = -1.0; return 2.0 - s[2 * n - 2 - m]; }
-        *idx = m;
-        return s[m];
-    }
-};
-
-void hermite(const Src& src, double t, int idx[4], double w[4])
-{
-    long id;
-    double sg;
-    long m = -2;
-    while (src.at(m + 1, &id, &sg) <= t) ++m;   // s_m <= t < s_{m+1}
-    double x[4], sgn[4];
-    long ii[4];
-    for (int p = 0; p < 4; ++p) x[p] = src.at(m - 1 + p, &ii[p], &sgn[p]);
-    const double D = x[2] - x[1], u = (t - x[1]) / D;
-    const double u2 = u * u, u3 = u2 * u;
-    const double b00 = 2 * u3 - 3 * u2 + 1, b10 = u3 - 2 * u2 + u;
-    const double b01 = -2 * u3 + 3 * u2, b11 = u3 - u2;
-    const double g1 = D / (x[2] - x[0]), g2 = D / (x[3] - x[1]);
-    const double ww[4] = {-b10 * g1, b00 - b11 * g2, b01 + b10 * g1, b11 * g2};
-    for (int p = 0; p < 4; ++p) {
-        idx[p] = (int)ii[p];
-        w[p] = ww[p] * sgn[p];
-    }
-}
-
 // Build one transfer: source axes src[3] (x, y, z) of a [.][sy][sx] array,
 // target coordinates tgt[3].  A y-row extent that does not fit the LDS
 // leaves it unbuilt (ok = false) with CH_OK; other failures return an error.
-ch_status build_transfer(Transfer& t, const Src* const src[3],
+ch_status build_transfer(Transfer& t, const chp::SrcAxis* const src[3],
                          const std::vector<double>* const tgt[3], int64_t sx, int64_t sy,
                          int precision)
 {
@@ -911,9 +869,8 @@ ch_status build_transfer(Transfer& t, const Src* const src[3],
     std::vector<double> wt[3];
     for (int a = 0; a < 3; ++a) {
         const std::vector<double>& q = *tgt[a];
-        idx[a].resize(4 * q.size());
-        wt[a].resize(4 * q.size());
-        for (size_t n = 0; n < q.size(); ++n) hermite(*src[a], q[n], &idx[a][4 * n], &wt[a][4 * n]);
+        if (!chp::hermite_stencils(*src[a], q, &idx[a], &wt[a]))
+            return fail(CH_EINVAL, "transfer target outside the source axis");
         t.tn[a] = (int64_t)q.size();
     }
     std::vector<int> band;
@@ -1215,21 +1172,23 @@ ch_status ch_interp_create(const ch_grid* fine, int64_t ncx, int64_t ncy, int64_
         for (int64_t i = 0; i < n; ++i) t[i] = (i + off) / n;
         return t;
     };
-    const Src cxf{pts(ncx, 0.0), SRC_PERIODIC}, cxc{pts(ncx, 0.5), SRC_PERIODIC},
-        cyf{pts(ncy, 0.0), SRC_PERIODIC}, cyc{pts(ncy, 0.5), SRC_PERIODIC};
-    Src czc{{}, SRC_EVEN}, czf{{}, SRC_ODD};
+    using chp::SrcAxis;
+    const SrcAxis cxf{pts(ncx, 0.0), chp::AXIS_PERIODIC}, cxc{pts(ncx, 0.5), chp::AXIS_PERIODIC},
+        cyf{pts(ncy, 0.0), chp::AXIS_PERIODIC}, cyc{pts(ncy, 0.5), chp::AXIS_PERIODIC};
+    SrcAxis czc{{}, chp::AXIS_MIRROR}, czf{{}, chp::AXIS_ANTI};
     for (int64_t k = 0; k < ncz; ++k) czc.s.push_back(0.5 * (zf[k] + zf[k + 1]));
     for (int64_t k = 0; k <= ncz; ++k) czf.s.push_back(zf[k]);
     const std::vector<double> fxf = pts(nx, 0.0), fxc = pts(nx, 0.5), fyf = pts(ny, 0.0),
                               fyc = pts(ny, 0.5), fzc = pts(nz, 0.5), zero(1, 0.0);
     std::vector<double> fzf(nz + 1);   // z faces including both walls
     for (int64_t k = 0; k <= nz; ++k) fzf[k] = (double)k / nz;
-    const Src sfx{fxc, SRC_PERIODIC}, sfy{fyc, SRC_PERIODIC}, sfz{fzc, SRC_EVEN};
+    const SrcAxis sfx{fxc, chp::AXIS_PERIODIC}, sfy{fyc, chp::AXIS_PERIODIC},
+        sfz{fzc, chp::AXIS_MIRROR};
     std::vector<double> ccx(cxc.s), ccy(cyc.s), ccz(czc.s);
     // u: x faces, y and z centres; v: x centres, y faces, z centres; w: x
     // and y centres, z faces; then the solenoidal transfer's pieces and the
     // projection of C
-    const Src* srcs[TR_COUNT][3] = {{&cxf, &cyc, &czc}, {&cxc, &cyf, &czc}, {&cxc, &cyc, &czf},
+    const SrcAxis* srcs[TR_COUNT][3] = {{&cxf, &cyc, &czc}, {&cxc, &cyf, &czc}, {&cxc, &cyc, &czf},
                                     {&cxc, &cyc, &czc}, {&cxf, &cyc, &czc}, {&cxc, &cyf, &czc},
                                     {&sfx, &sfy, &sfz}};
     const std::vector<double>* tgts[TR_COUNT][3] = {

@@ -375,4 +375,147 @@ inline chd::PassArgs pass_args(const Plan& P, int k, int pass)
     return pa;
 }
 
+// ---- multiple resolution: 1-D transfer stencils (sec. 3.4) ---------------
+// The transfer from one mesh to another is a tensor product of 1-D cubic
+// Hermite interpolants with four source points per direction.  The slope at
+// a source point is the chord slope through its two neighbours.  These
+// helpers build, for every target coordinate, the four stored source
+// indices and weights, once per transfer.
+//
+// A source axis lists its stored points s[0..n) in increasing order and
+// says how the sequence continues beyond its ends:
+//   AXIS_PERIODIC  period 1: the point n + j sits at s[j] + 1;
+//   AXIS_MIRROR    cell-centred values between walls at 0 and 1, continued
+//                  evenly: the image of s[j] across a wall carries +s[j]'s
+//                  value;
+//   AXIS_ANTI      face values that include both walls (s[0] = 0,
+//                  s[n-1] = 1), continued oddly: the image of s[j] across a
+//                  wall carries minus its value, and the walls themselves are
+//                  not repeated.
+enum { AXIS_PERIODIC = 0, AXIS_MIRROR = 1, AXIS_ANTI = 2 };
+
+struct SrcAxis {
+    std::vector<double> s;
+    int kind = AXIS_PERIODIC;
+};
+
+// The source axis with `pad` images added on each side, written out as
+// arrays: position, the stored point that carries the value, and the sign
+// of that value.  Entry e is the point e - pad of the continued sequence.
+struct PaddedAxis {
+    int pad = 0;
+    std::vector<double> x;
+    std::vector<int> from;
+    std::vector<double> sign;
+};
+
+inline PaddedAxis pad_axis(const SrcAxis& a, int pad)
+{
+    const int n = (int)a.s.size();
+    PaddedAxis out;
+    // images in order of increasing position: the left ones first
+    std::vector<double> lx, rx, ls, rs;
+    std::vector<int> lf, rf;
+    // a reflected axis has as many images per side as stored points (less
+    // the wall itself when it is stored)
+    const int lim = a.kind == AXIS_PERIODIC ? pad : std::min(pad, a.kind == AXIS_MIRROR ? n : n - 1);
+    out.pad = lim;
+    for (int g = lim; g >= 1; --g) {
+        // the g-th image left of s[0], and the g-th right of s[n-1]
+        int jl, jr;
+        double pl, pr, sg = 1.0;
+        if (a.kind == AXIS_PERIODIC) {
+            // whole periods away, for axes shorter than the padding too
+            const int q = (g + n - 1) / n;
+            jl = q * n - g;
+            jr = g - 1 - (q - 1) * n;
+            pl = a.s[jl] - q;
+            pr = a.s[jr] + q;
+        } else if (a.kind == AXIS_MIRROR) {
+            jl = g - 1;                 // mirror of s[g-1] about 0
+            jr = n - g;                 // mirror of s[n-g] about 1
+            pl = -a.s[jl];
+            pr = 2.0 - a.s[jr];
+        } else {
+            jl = g;                     // the wall point s[0] is its own image
+            jr = n - 1 - g;
+            pl = -a.s[jl];
+            pr = 2.0 - a.s[jr];
+            sg = -1.0;
+        }
+        lx.push_back(pl);
+        lf.push_back(jl);
+        ls.push_back(sg);
+        rx.insert(rx.begin(), pr);
+        rf.insert(rf.begin(), jr);
+        rs.insert(rs.begin(), sg);
+    }
+    out.x = lx;
+    out.from = lf;
+    out.sign = ls;
+    for (int j = 0; j < n; ++j) {
+        out.x.push_back(a.s[j]);
+        out.from.push_back(j);
+        out.sign.push_back(1.0);
+    }
+    out.x.insert(out.x.end(), rx.begin(), rx.end());
+    out.from.insert(out.from.end(), rf.begin(), rf.end());
+    out.sign.insert(out.sign.end(), rs.begin(), rs.end());
+    return out;
+}
+
+// Slope of the chord through (xa, fa) and (xb, fb).
+inline double chord_slope(double xa, double fa, double xb, double fb)
+{
+    return (fb - fa) / (xb - xa);
+}
+
+// The cubic on [x1, x2] with values f1, f2 and slopes d1, d2 at its ends,
+// evaluated at t in power form about x1 (Horner).
+inline double hermite_cubic(double x1, double x2, double f1, double f2, double d1, double d2,
+                            double t)
+{
+    const double L = x2 - x1, tau = (t - x1) / L;
+    const double c1 = L * d1;
+    const double c2 = 3.0 * (f2 - f1) - 2.0 * L * d1 - L * d2;
+    const double c3 = 2.0 * (f1 - f2) + L * d1 + L * d2;
+    return f1 + tau * (c1 + tau * (c2 + tau * c3));
+}
+
+// Stored indices and weights of the four source points that interpolate the
+// axis at t (the reflection sign folded into the weight).  t must lie
+// within the padded axis, between its second and its second-to-last point.
+inline bool hermite_stencil(const PaddedAxis& P, double t, int idx[4], double w[4])
+{
+    // the interval [x[e], x[e+1]) holding t
+    const auto it = std::upper_bound(P.x.begin(), P.x.end(), t);
+    const long e = (long)(it - P.x.begin()) - 1;
+    if (e < 1 || e + 2 >= (long)P.x.size()) return false;
+    const double* x = &P.x[e - 1];
+    // each weight is the interpolant of the data that is 1 at one of the
+    // four points and 0 at the others
+    for (int p = 0; p < 4; ++p) {
+        double f[4] = {0.0, 0.0, 0.0, 0.0};
+        f[p] = 1.0;
+        const double d1 = chord_slope(x[0], f[0], x[2], f[2]);
+        const double d2 = chord_slope(x[1], f[1], x[3], f[3]);
+        w[p] = hermite_cubic(x[1], x[2], f[1], f[2], d1, d2, t) * P.sign[e - 1 + p];
+        idx[p] = P.from[e - 1 + p];
+    }
+    return true;
+}
+
+// Stencils of every target coordinate: idx[4 q + p], w[4 q + p].
+inline bool hermite_stencils(const SrcAxis& a, const std::vector<double>& tgt,
+                             std::vector<int>* idx, std::vector<double>* w)
+{
+    if (a.s.size() < 2) return false;
+    const PaddedAxis P = pad_axis(a, 3);
+    idx->assign(4 * tgt.size(), 0);
+    w->assign(4 * tgt.size(), 0.0);
+    for (size_t q = 0; q < tgt.size(); ++q)
+        if (!hermite_stencil(P, tgt[q], &(*idx)[4 * q], &(*w)[4 * q])) return false;
+    return true;
+}
+
 }  // namespace chp

@@ -183,6 +183,58 @@ def staggered_divergence(u, v, w, h, bc=(0, 0, 0)):
     return dd(u, 2, bc[0] == 0) + dd(v, 1, bc[1] == 0) + dd(w, 0, bc[2] == 0)
 
 
+def wall_velocity(rng, shape, bc, h, smooth=2):
+    """Divergence-free staggered velocity on a uniform mesh with no-flux
+    walls on any axis (bc = (bx, by, bz), 1 = walls): the discrete curl of an
+    edge-located vector potential whose components tangential to each wall
+    vanish on it, so the wall-normal velocity is zero there.
+
+    A potential component lives on the mesh nodes along the axes it is not
+    aligned with (n + 1 nodes along a walled axis, n along a periodic one)
+    and on the cell centres along its own axis.  The random potentials are
+    smoothed by `smooth` passes of a three-point average along every axis.
+    Returns u (nz, ny, fx), v (nz, fy, nx), w (fz, ny, nx), f = n (+1 with
+    walls).
+    """
+    nz, ny, nx = shape
+    nodes = [n + 1 if b else n for n, b in zip((nx, ny, nz), bc)]   # x, y, z
+
+    def field(sz, sy, sx):
+        a = rng.normal(size=(sz, sy, sx))
+        for _ in range(smooth):
+            for axis in range(3):
+                a = (np.roll(a, 1, axis) + 2.0 * a + np.roll(a, -1, axis)) / 4.0
+        return a
+
+    Ax = field(nodes[2], nodes[1], nx)
+    Ay = field(nodes[2], ny, nodes[0])
+    Az = field(nz, nodes[1], nodes[0])
+    if bc[0]:
+        Ay[:, :, 0] = Ay[:, :, -1] = 0.0
+        Az[:, :, 0] = Az[:, :, -1] = 0.0
+    if bc[1]:
+        Ax[:, 0, :] = Ax[:, -1, :] = 0.0
+        Az[:, 0, :] = Az[:, -1, :] = 0.0
+    if bc[2]:
+        Ax[0] = Ax[-1] = 0.0
+        Ay[0] = Ay[-1] = 0.0
+
+    def d(a, axis, walled):
+        # node-to-centre difference: forward neighbour, wrapped when periodic
+        if walled:
+            hi = [slice(None)] * 3
+            lo = [slice(None)] * 3
+            hi[axis] = slice(1, None)
+            lo[axis] = slice(0, -1)
+            return (a[tuple(hi)] - a[tuple(lo)]) / h
+        return (np.roll(a, -1, axis=axis) - a) / h
+
+    u = d(Az, 1, bc[1]) - d(Ay, 0, bc[2])
+    v = d(Ax, 0, bc[2]) - d(Az, 2, bc[0])
+    w = d(Ay, 2, bc[0]) - d(Ax, 1, bc[1])
+    return u, v, w
+
+
 def stretched_faces(n, alpha=2.0):
     """Face positions z_k = 1/2 [1 + tanh(alpha (2k/n - 1)) / tanh(alpha)],
     k = 0..n, clustered towards both walls."""

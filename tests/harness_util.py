@@ -59,3 +59,36 @@ def run_emu(boxes, dt, nsteps, prec=0, kappa=4.0, eps=1e-6, solve=0, x_rows=0, s
         out.append(flat[o:o + n].reshape(b["C"].shape))
         o += n
     return out, masses, plan
+
+
+_STENCIL_EXE = None
+
+
+def lib_stencils(kind, s, targets):
+    """The library's 1-D transfer stencils (ch_plan.h, built for the host
+    with sanitizers): (idx [m,4] int, w [m,4] float64), or None when the
+    library refuses the axis."""
+    global _STENCIL_EXE
+    if _STENCIL_EXE is None:
+        d = tempfile.mkdtemp(prefix="ch_stencil_")
+        exe = os.path.join(d, "stencil_dump")
+        subprocess.run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+                        "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-o", exe,
+                        os.path.join(ROOT, "tests", "cpu_harness", "stencil_dump.cpp")],
+                       check=True)
+        _STENCIL_EXE = exe
+    s = np.asarray(s, dtype=np.float64)
+    t = np.atleast_1d(np.asarray(targets, dtype=np.float64))
+    text = f"{int(kind)} {s.size}\n" + " ".join(repr(float(x)) for x in s) + \
+        f"\n{t.size}\n" + " ".join(repr(float(x)) for x in t) + "\n"
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([_STENCIL_EXE], input=text, capture_output=True, text=True, env=env)
+    if r.returncode != 0:
+        raise RuntimeError(f"stencil_dump failed ({r.returncode}):\n{r.stderr[-4000:]}")
+    if r.stdout.strip() == "FAIL":
+        return None
+    rows = [line.split() for line in r.stdout.strip().splitlines()]
+    idx = np.array([[int(x) for x in row[:4]] for row in rows], dtype=np.int64)
+    w = np.array([[float(x) for x in row[4:]] for row in rows], dtype=np.float64)
+    return idx, w

@@ -28,10 +28,9 @@ def _box(shape, bc=(0, 0, 0), seed=0, amp=1.0, drops=True):
     elif bc == (0, 0, 1):
         zf = np.arange(nz + 1) / nz
         u, v, w = inputs.coarse_wall_velocity(rng, shape, zf, kmax=3, nmodes_z=3)
-    else:
+    elif bc == (1, 0, 1):
         # walls in x and z: a stream function on the x-z cell corners that
         # vanishes on the walls; v depends on x and z only
-        assert bc == (1, 0, 1)
         xf = np.arange(nx + 1) / nx
         zf = np.arange(nz + 1) / nz
         psi = sum(rng.normal() * np.outer(np.sin(m * np.pi * zf), np.sin(q * np.pi * xf))
@@ -39,6 +38,8 @@ def _box(shape, bc=(0, 0, 0), seed=0, amp=1.0, drops=True):
         u = np.repeat(((psi[1:, :] - psi[:-1, :]) / h)[:, None, :], ny, axis=1)
         w = np.repeat((-(psi[:, 1:] - psi[:, :-1]) / h)[:, None, :], ny, axis=1)
         v = np.repeat(rng.normal(size=(nz, 1, nx)), ny, axis=1)
+    else:
+        u, v, w = inputs.wall_velocity(rng, shape, bc, h)
     s = amp / max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max())
     return dict(C=C, u=u * s, v=v * s, w=w * s, h=h, Cn=h, Pe=0.9 / h, bc=bc)
 
@@ -76,6 +77,31 @@ def test_fp64_matches_oracle_ragged_and_walls(shape, bc, zc):
     ref = _oracle(b, dt, 2)
     assert _rel(out[0], ref) < 1e-12
     assert plan["ntask"][1] > 0
+
+
+@pytest.mark.parametrize("zc", [1, 4])
+@pytest.mark.parametrize("shape,bc,opts", [
+    ((10, 12, 17), (1, 0, 0), dict(x_rows=3, seg=5)),     # x walls, odd nx
+    ((9, 13, 16), (0, 1, 0), dict(x_rows=2, seg=4)),      # y walls, tiles touching them
+    ((11, 10, 9), (1, 1, 1), {}),                         # walls everywhere
+    ((12, 9, 8), (1, 0, 0), dict(x_rows=4)),              # x walls, the shortest x line
+    ((10, 9, 1), (1, 1, 0), dict(x_rows=3)),              # degenerate x with x walls
+    ((8, 11, 13), (1, 1, 0), dict(x_rows=5, seg=3, waves=2)),
+    ((14, 8, 1), (0, 1, 1), {}),                          # degenerate x between y walls
+    ((1, 12, 10), (1, 1, 0), {}),                         # degenerate z
+])
+def test_fp64_matches_oracle_walls_in_x_and_y(shape, bc, opts, zc):
+    """No-flux walls along x and y: the wall face flux, the reflected x halo
+    (also where every column of the tile is a halo column), the y-wall top
+    face, segmented lines reaching a wall."""
+    b = _box(shape, bc=bc, seed=17, amp=2.0, drops=min(shape) > 4)
+    dt = 2e-4
+    out, masses, plan = run_emu([b], dt, 2, z_chunk=zc, **opts)
+    ref = _oracle(b, dt, 2)
+    assert _rel(out[0], ref) < 1e-12
+    assert abs(masses[0] - oracle.mass(ref, b["h"])) < 1e-12 * abs(masses[0])
+    out32, _, _ = run_emu([b], dt, 2, prec=1, z_chunk=zc, **opts)
+    assert _rel(out32[0], ref) < 2e-6
 
 
 @pytest.mark.parametrize("shape,bc,zc", [((60, 10, 32), (0, 0, 0), 24), ((50, 9, 24), (0, 0, 1), 20)])

@@ -4,6 +4,7 @@ FP64 bar: relative L-infinity error of C after one step <= 1e-12 (the
 tolerance of the project's stated target).  FP32 bar: derived from the
 arithmetic (see the design notes): <= 5e-6 relative after a few steps.
 """
+import ctypes
 import math
 import sys
 
@@ -41,11 +42,13 @@ def _case(shape, bc=(0, 0, 0), seed=0, amp=1.0):
     cen, rad = inputs.place_drops(rng, 4, 2, 5, shape, h, walls_z=bc[2] == 1, gap_cells=1)
     C = inputs.drop_field(shape, h, h, cen, rad, walls_z=bc[2] == 1)
     C = C + 0.01 * rng.normal(size=shape)
-    if bc[2] == 0:
+    if bc == (0, 0, 0):
         u, v, w = inputs.curl_velocity(*(rng.normal(size=shape) for _ in range(3)), h)
-    else:
+    elif bc == (0, 0, 1):
         u, v, w = inputs.coarse_wall_velocity(rng, shape, np.arange(nz + 1) / nz, kmax=4,
                                               nmodes_z=4)
+    else:
+        u, v, w = inputs.wall_velocity(rng, shape, bc, h)
     s = amp / max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max())
     return C, u * s, v * s, w * s, h
 
@@ -87,6 +90,16 @@ def test_32cube_fp64_one_step_and_ten_steps():
     ((96, 96, 96), (0, 0, 0), {}),
     ((96, 96, 96), (0, 0, 0), dict(x_rows=2, z_chunk=5)),
     ((8, 9, 1100), (0, 0, 0), dict(z_chunk=3)),
+    # no-flux walls along x and y: wall faces, reflected x halos, the y-wall
+    # top face, segments and tiles touching the walls
+    ((10, 12, 17), (1, 0, 0), dict(x_rows=3, seg_len=5)),
+    ((9, 13, 16), (0, 1, 0), dict(x_rows=2, seg_len=4)),
+    ((11, 10, 9), (1, 1, 1), {}),
+    ((12, 9, 8), (1, 0, 0), dict(x_rows=4, z_chunk=4)),
+    ((10, 9, 1), (1, 1, 0), dict(x_rows=3)),
+    ((8, 11, 13), (1, 1, 0), dict(x_rows=5, seg_len=3, waves_yz=2)),
+    ((40, 33, 72), (1, 1, 1), {}),
+    ((64, 48, 56), (1, 1, 0), dict(x_rows=2, z_chunk=5)),
 ])
 def test_fp64_parity_tiles_walls_ragged(shape, bc, opts):
     C, u, v, w, h = _case(shape, bc, seed=sum(shape), amp=2.0)
@@ -95,6 +108,11 @@ def test_fp64_parity_tiles_walls_ragged(shape, bc, opts):
     ref = oracle.step(C, u, v, w, h, h, 0.9 / h, dt, 1, bc=bc)
     print(f"  cfg={cfg} rel={rel(got, ref):.3e}")
     assert rel(got, ref) <= TOL64
+    if bc[0] or bc[1]:
+        # FP32 storage in the same launch shapes
+        got32, _ = run_gpu(C, u, v, w, h, h, 0.9 / h, dt, 1, bc=bc, precision="fp32", **opts)
+        print(f"  fp32 rel={rel(got32, ref):.3e}")
+        assert rel(got32, ref) <= 5e-6
 
 
 def test_fp64_parity_large_dt_long_warmup():
@@ -263,6 +281,36 @@ def test_error_paths():
     h = s._h
     s.close()
     assert ch.lib().ch_step(h, z.data_ptr(), z.data_ptr(), z.data_ptr(), 1e-4, 1) == -6
+    # a live handle of another kind is rejected like a destroyed one
+    L = ch.lib()
+    g = ch.Grid(32, 32, 32, 1 / 32)
+    zf = np.ascontiguousarray(np.linspace(0.0, 1.0, 9))
+    ip = ctypes.c_void_p()
+    assert L.ch_interp_create(ctypes.byref(g), 8, 8, 8, zf.ctypes.data_as(ch._PD), ch.CH_FP64,
+                              ctypes.byref(ip)) == 0
+    pp = ctypes.c_void_p()
+    assert L.ch_poisson_create(ctypes.byref(g), 1, ch.CH_FP64, ctypes.byref(pp)) == 0
+    bt = ch.Batch([(16, 16, 16)], [1 / 16], [1 / 16], [14.4])
+    live = ch.State((16, 16, 16), 1 / 16, 1 / 16, 14.4)
+    m = ctypes.c_double()
+    for foreign in (ip, pp, bt._h):
+        assert L.ch_step(foreign, z.data_ptr(), z.data_ptr(), z.data_ptr(), 1e-4, 1) == -6
+        assert L.ch_mass(foreign, ctypes.byref(m)) == -6
+        assert "handle" in L.ch_last_error().decode()
+    for foreign in (ip, pp, live._h):
+        assert L.ch_batch_step(foreign, z.data_ptr(), z.data_ptr(), z.data_ptr(), 1e-4, 1) == -6
+    assert L.ch_interp_apply(pp, z.data_ptr(), z.data_ptr(), z.data_ptr(), z.data_ptr(),
+                             z.data_ptr(), z.data_ptr()) == -6
+    assert L.ch_poisson_solve(ip, z.data_ptr(), z.data_ptr()) == -6
+    # destroying through a handle of the wrong kind does nothing; the right
+    # kind still works afterwards
+    L.ch_destroy(ip)
+    L.ch_batch_destroy(pp)
+    live.step(z, z, z, 1e-4, 1)
+    L.ch_interp_destroy(ip)
+    L.ch_poisson_destroy(pp)
+    bt.close()
+    live.close()
     # a no-flux wall with a non-zero normal velocity is reported
     s = ch.State((16, 16, 16), 1 / 16, 1 / 16, 14.4, bc=(0, 0, 1))
     w = torch.zeros((17, 16, 16), dtype=torch.float64, device="cuda")
@@ -289,12 +337,12 @@ def test_256cube_full_size_fp64_one_step_against_oracle():
 def test_48box_ensemble_sampled_boxes_against_oracle():
     """The whole 48-box ensemble (about 1.2e8 points) in one batch, in the
     launch configuration the benchmark times: every box conserves its mass,
-    and the smallest boxes of each edge up to 96 match the oracle."""
+    and one box of every edge (48 to 192) matches the oracle."""
     E = inputs.ensemble(48)
     shapes = [w.shape for w in E]
     hs = [w.h for w in E]
     pick = []
-    for edge in (48, 64, 96):
+    for edge in (48, 64, 96, 128, 160, 192):
         pick.append(next(i for i, w in enumerate(E) if w.shape[0] == edge))
     refs = {i: oracle.step(E[i].C, E[i].u, E[i].v, E[i].w, E[i].h, E[i].Cn, E[i].Pe, 1e-4, 1)
             for i in pick}

@@ -326,17 +326,22 @@ def _small_case(shape, bc, seed, amp=0.3):
     nz, ny, nx = shape
     h = 1.0 / nx
     C = 0.5 + 0.4 * rng.uniform(-1, 1, size=shape)
-    if bc[2] == 0:
+    if bc == (0, 0, 0):
         Ax, Ay, Az = (rng.normal(size=shape) for _ in range(3))
         u, v, w = inputs.curl_velocity(Ax, Ay, Az, h)
-    else:
+    elif bc == (0, 0, 1):
         zf = np.arange(nz + 1) / nz
         u, v, w = inputs.coarse_wall_velocity(rng, shape, zf, kmax=3, nmodes_z=3)
+    else:
+        u, v, w = inputs.wall_velocity(rng, shape, bc, h, smooth=0)
     s = amp / max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max())
     return C, u * s, v * s, w * s, h
 
 
-@pytest.mark.parametrize("bc", [(0, 0, 0), (0, 0, 1)])
+ALL_BC = [(0, 0, 0), (0, 0, 1), (1, 0, 0), (0, 1, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1)]
+
+
+@pytest.mark.parametrize("bc", ALL_BC)
 @pytest.mark.parametrize("shape", [(6, 7, 8), (8, 6, 6)])
 def test_oracle_matches_dense_bruteforce(shape, bc):
     C, u, v, w, h = _small_case(shape, bc, seed=7)
@@ -347,7 +352,7 @@ def test_oracle_matches_dense_bruteforce(shape, bc):
         assert np.abs(a - b).max() < 1e-13 * np.abs(b).max()
 
 
-@pytest.mark.parametrize("bc", [(0, 0, 0), (0, 0, 1)])
+@pytest.mark.parametrize("bc", ALL_BC)
 def test_mass_is_conserved(bc):
     C, u, v, w, h = _small_case((16, 12, 10), bc, seed=11, amp=2.0)
     Cn, Pe, dt = h, 0.9 / h, 1e-3
