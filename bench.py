@@ -30,10 +30,15 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
 # Vector FMA rate without packed FP32 (which this library does not emit):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz, the same in FP32 and FP64.
 VALU_PEAK_TFLOPS = 78.6
+# MI355X's published FP32 vector peak (packed FP32 math)
+VALU_PEAK_PUBLISHED_FP32_TFLOPS = 157.3
 METRIC = ("CH grid-point updates/s (Gpts/s) FP32 & batched vs FP64 at stated error; "
           "%HBM peak")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_x_256cube_fp32_traffic.md")
+TRAFFIC_FILE_LARGE = os.path.join(ROOT, "profiles", "k_pass_x_1536cube_fp32_traffic.md")
 X_SOURCES = ("ch_device.h", "ch_kernels.hip", "ch_plan.h")
+DROPS_DEF = ("face-connected cells with C >= 1/2 (periodic axes wrap, walls do not connect), "
+             "V = h^3 cells, (4 pi/3)(D/2)^3 = V, H = box height")
 
 
 def progress(msg):
@@ -75,11 +80,13 @@ def x_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per x-pass launch from the committed counter summary, if it
-    was taken on the current kernel sources; otherwise None."""
+def measured_traffic(path=None):
+    """HBM bytes per x-pass launch from a committed counter summary (the
+    256^3 one unless `path` names another), if it was taken on the current
+    kernel sources; otherwise None."""
+    path = path or TRAFFIC_FILE
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     src = re.search(r"^source-hash:\s*(\w+)", text, re.M)
@@ -89,6 +96,67 @@ def measured_traffic():
     return float(val.group(1))
 
 
+def x_roofline(avg_us, points, es, traffic=None, kernel="k_pass_x"):
+    """The x pass (explicit terms, RHS and x solve) against HBM: algorithmic
+    bytes of one launch (x_pass_bytes_per_point x points) over its average
+    launch time from HIP events; `traffic` is the counter-measured HBM bytes
+    of one launch, when a summary for the current sources exists."""
+    nbytes = x_pass_bytes_per_point(es) * points
+    gbs = nbytes / (avg_us * 1e-6) / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "algorithmic_bytes_per_launch": nbytes,
+            "avg_launch_us": round(avg_us, 2)}
+
+
+def step_hbm_frac(points, es, ms_per_step, extra_bytes=0.0):
+    """Whole-step algorithmic bytes (34 element accesses per point, plus any
+    transfer bytes) over the step time, as a fraction of HBM peak."""
+    return round((step_bytes_per_point(es) * points + extra_bytes) /
+                 (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+
+
+def dh_histogram(cells, h, H, nbins=12):
+    """PDF of D/H over drops (D the equivalent-sphere diameter of the drop's
+    volume h^3 cells): equal bins from 0 to the largest D/H."""
+    import numpy as np
+    if len(cells) == 0:
+        return None
+    dh = np.cbrt(6.0 * np.asarray(cells, dtype=np.float64) * h ** 3 / np.pi) / H
+    top = float(dh.max()) * 1.0001
+    counts, edges = np.histogram(dh, bins=nbins, range=(0.0, top))
+    width = edges[1] - edges[0]
+    return {"drops": int(len(dh)), "edges": [round(float(e), 5) for e in edges],
+            "counts": [int(c) for c in counts],
+            "pdf": [round(float(c) / (len(dh) * width), 4) for c in counts],
+            "min": float(dh.min()), "median": float(np.median(dh)), "max": float(dh.max())}
+
+
+def fp32_errors(C32, C64, m32, m64, drops32, drops64, h, H, steps):
+    """FP32 against FP64 after `steps` steps from the same field: relative
+    L2(C), the FP64-summed mass drift of each, the drop-volume error
+    |V32 - V64| / V64 with V = h^3 #{C >= 1/2}, and per-drop volumes matched
+    by root (the drop's smallest cell index)."""
+    import numpy as np
+    (r32, c32), (r64, c64) = drops32, drops64
+    v32 = float(np.sum(c32)) * h ** 3
+    v64 = float(np.sum(c64)) * h ** 3
+    by64 = dict(zip(r64.tolist(), c64.tolist()))
+    matched = [(c, by64[r]) for r, c in zip(r32.tolist(), c32.tolist()) if r in by64]
+    return {"steps": steps,
+            "l2_rel": float(np.linalg.norm(C32 - C64) / np.linalg.norm(C64)),
+            "mass_drift_fp32": abs(m32[1] - m32[0]) / abs(m32[0]),
+            "mass_drift_fp64": abs(m64[1] - m64[0]) / abs(m64[0]),
+            "drop_volume_err": abs(v32 - v64) / v64 if v64 > 0 else None,
+            "drops": {"definition": DROPS_DEF, "count_fp32": int(len(r32)),
+                      "count_fp64": int(len(r64)), "matched_by_root": len(matched),
+                      "max_rel_volume_err_fp32_vs_fp64":
+                          max((abs(a - b) / b for a, b in matched), default=None),
+                      "l_loss_fp32": (m32[1] - m32[0]) / m32[0],
+                      "l_loss_fp64": (m64[1] - m64[0]) / m64[0],
+                      "D_over_H_pdf_fp64": dh_histogram(c64, h, H)}}
+
+
 def counter_probe(prec="fp32"):
     """A short run for rocprofv3 counter passes: two steps of the workload
     (FP32 unless `prec` says otherwise), then one device-to-device copy of
@@ -96,15 +164,29 @@ def counter_probe(prec="fp32"):
     counters)."""
     import torch
     from paper_2105_01865_amd import ch, inputs
-    wl = inputs.make_workload(2)
     stream = torch.cuda.Stream()
-    dt_ = torch.float64 if prec == "fp64" else torch.float32
-    s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, precision=prec, stream=stream)
-    s.set_field(torch.from_numpy(wl.C).to("cuda", dt_))
-    U, V, W = (torch.from_numpy(a).to("cuda", dt_) for a in (wl.u, wl.v, wl.w))
-    s.step(U, V, W, wl.dt, 2)
-    torch.cuda.synchronize()
-    s.close()
+    if prec == "large":
+        # one step of the 1536^3 box, in the bench's automatic plan
+        from paper_2105_01865_amd import inputs_gpu
+        wl = inputs_gpu.large_workload()
+        s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, precision="fp32", stream=stream)
+        s.set_field(wl.C)
+        del wl.C
+        torch.cuda.empty_cache()
+        s.step(wl.u, wl.v, wl.w, wl.dt, 1)
+        torch.cuda.synchronize()
+        s.close()
+        del wl
+        torch.cuda.empty_cache()
+    else:
+        wl = inputs.make_workload(2)
+        dt_ = torch.float64 if prec == "fp64" else torch.float32
+        s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, precision=prec, stream=stream)
+        s.set_field(torch.from_numpy(wl.C).to("cuda", dt_))
+        U, V, W = (torch.from_numpy(a).to("cuda", dt_) for a in (wl.u, wl.v, wl.w))
+        s.step(U, V, W, wl.dt, 2)
+        torch.cuda.synchronize()
+        s.close()
     a = torch.ones(64 << 20, device="cuda", dtype=torch.float32)
     b = torch.empty_like(a)
     b.copy_(a)
@@ -127,14 +209,18 @@ def _timed_events(stream, fn):
 def bench_ensemble(args, stream):
     """The batched ensemble: 48 independent periodic boxes with edges from
     {48, 64, 96, 128, 160, 192}, 1-20 drops each, per-box ABC flows; all boxes
-    advance in one graph launch per step."""
+    advance in one graph launch per step.  Each precision steps from the
+    same initial fields: warm-up, the timed steps, then on to --acc-steps
+    steps in all, for the FP32-vs-FP64 errors."""
     import numpy as np
-    import torch
     from paper_2105_01865_amd import ch, inputs
     E = inputs.ensemble(48)
     pts = sum(w.points for w in E)
     res = {}
     fields = {}
+    drops = {}
+    masses = {}
+    nacc = 0
     for prec in ("fp32", "fp64"):
         b = ch.Batch([w.shape for w in E], [w.h for w in E], [w.Cn for w in E],
                      [w.Pe for w in E], stream=stream, precision=prec)
@@ -144,25 +230,57 @@ def bench_ensemble(args, stream):
         m0 = np.array(b.mass())
         b.step(U, V, W, 1e-4, args.warmup)
         ms = _timed_events(stream, lambda: b.step(U, V, W, 1e-4, args.ensemble_steps))
+        done = args.warmup + args.ensemble_steps
+        if args.acc_steps > done:
+            b.step(U, V, W, 1e-4, args.acc_steps - done)
+        nacc = max(done, args.acc_steps)
         m1 = np.array(b.mass())
-        fields[prec] = b.get_field().double().cpu().numpy()
+        masses[prec] = (m0, m1)
+        fields[prec] = b.unpack(b.get_field())
+        fields[prec] = [f.double().cpu().numpy() for f in fields[prec]]
+        drops[prec] = [b.drops(i) for i in range(len(E))]
         b.profile(True)
         b.step(U, V, W, 1e-4, 5)
         kern = {k: b.profile_read(k) for k in ("x", "y", "z")}
         b.profile(False)
         b.close()
+        es = 4 if prec == "fp32" else 8
+        x_us = 1e3 * kern["x"][0] / max(1, kern["x"][1])
         res[prec] = {"value": round(pts * args.ensemble_steps / (ms * 1e-3) / 1e9, 4),
                      "unit": "Gpts/s", "ms_per_step": round(ms / args.ensemble_steps, 4),
                      "max_box_mass_drift": float(np.max(np.abs(m1 - m0) / np.abs(m0))),
                      "autotune": tune,
                      "kernels_avg_us": {k: round(1e3 * v[0] / max(1, v[1]), 1)
-                                        for k, v in kern.items()}}
-    d = fields["fp32"] - fields["fp64"]
+                                        for k, v in kern.items()},
+                     "hbm_frac_step_model": step_hbm_frac(pts, es, ms / args.ensemble_steps),
+                     "roofline": x_roofline(x_us, pts, es)}
+    # FP32 against FP64, box by box
+    l2n = sum(float(np.sum((a - c) ** 2)) for a, c in zip(fields["fp32"], fields["fp64"]))
+    l2d = sum(float(np.sum(c ** 2)) for c in fields["fp64"])
+    vol_err, drop_err, cnt = [], [], [0, 0]
+    for i, w in enumerate(E):
+        (r32, c32), (r64, c64) = drops["fp32"][i], drops["fp64"][i]
+        cnt[0] += len(r32)
+        cnt[1] += len(r64)
+        v64 = float(np.sum(c64))
+        if v64 > 0:
+            vol_err.append(abs(float(np.sum(c32)) - v64) / v64)
+        by64 = dict(zip(r64.tolist(), c64.tolist()))
+        drop_err += [abs(c - by64[r]) / by64[r] for r, c in zip(r32.tolist(), c32.tolist())
+                     if r in by64]
+    (a0, a1), (b0, b1) = masses["fp32"], masses["fp64"]
+    acc = {"steps": nacc, "l2_rel": (l2n / l2d) ** 0.5,
+           "max_box_mass_drift_fp32": float(np.max(np.abs(a1 - a0) / np.abs(a0))),
+           "max_box_mass_drift_fp64": float(np.max(np.abs(b1 - b0) / np.abs(b0))),
+           "max_box_drop_volume_err": max(vol_err) if vol_err else None,
+           "drops": {"definition": DROPS_DEF, "count_fp32": cnt[0], "count_fp64": cnt[1],
+                     "matched_by_root": len(drop_err),
+                     "max_rel_volume_err_fp32_vs_fp64": max(drop_err) if drop_err else None}}
     return {"workload": "48 periodic boxes, edge ~ U{48,64,96,128,160,192}, h = 1/edge, "
                         "1-20 tanh drops R~U[4,12]h, ABC flow A,B,C~U[0.05,0.2], dt=1e-4",
             "points": pts, "steps": args.ensemble_steps, "fp32": res["fp32"], "fp64": res["fp64"],
             "fp32_over_fp64": round(res["fp32"]["value"] / res["fp64"]["value"], 3),
-            "l2_rel_fp32_vs_fp64": float(np.linalg.norm(d) / np.linalg.norm(fields["fp64"]))}
+            "accuracy_fp32_vs_fp64": acc, "roofline": res["fp32"]["roofline"]}
 
 
 def transfer_bytes_per_component(nc, nf, es):
@@ -185,6 +303,9 @@ def bench_multires(args, stream):
     zf, uc, vc, wc = (wl.coarse[k] for k in ("zf", "uc", "vc", "wc"))
     res = {}
     fields = {}
+    masses = {}
+    drops = {}
+    nacc = 0
     for prec in ("fp32", "fp64"):
         dt_ = torch.float32 if prec == "fp32" else torch.float64
         es = 4 if prec == "fp32" else 8
@@ -203,9 +324,17 @@ def bench_multires(args, stream):
             s.step_multires(ip, UC, VC, WC, wl.dt, args.warmup)
             ms = _timed_events(stream, lambda: s.step_multires(ip, UC, VC, WC, wl.dt,
                                                                args.multires_steps))
+            if mode == "plain":
+                # on to --multires-acc-steps steps from the initial field
+                done = args.warmup + args.multires_steps
+                if args.multires_acc_steps > done:
+                    s.step_multires(ip, UC, VC, WC, wl.dt, args.multires_acc_steps - done)
+                nacc = max(done, args.multires_acc_steps)
             m1 = s.mass()
             if mode == "plain":
                 fields[prec] = s.get_field().double().cpu().numpy()
+                masses[prec] = (m0, m1)
+                drops[prec] = s.drops()
             s.profile(True)
             s.step_multires(ip, UC, VC, WC, wl.dt, 5)
             kern = {k: s.profile_read(k) for k in ("x", "y", "z", "interp")}
@@ -214,12 +343,18 @@ def bench_multires(args, stream):
             s.close()
             ip.close()
             t_us = 1e3 * kern["interp"][0] / max(1, kern["interp"][1])
+            x_us = 1e3 * kern["x"][0] / max(1, kern["x"][1])
+            nbytes = transfer_bytes_per_component(uc.shape, wl.shape, es)
             r = {"value": round(wl.points * args.multires_steps / (ms * 1e-3) / 1e9, 4),
                  "unit": "Gpts/s", "ms_per_step": round(ms / args.multires_steps, 4),
                  "mass_drift": abs(m1 - m0) / abs(m0), "autotune": tune,
                  "kernels_avg_us": {k: round(1e3 * v[0] / max(1, v[1]), 1)
-                                    for k, v in kern.items()}}
-            nbytes = transfer_bytes_per_component(uc.shape, wl.shape, es)
+                                    for k, v in kern.items()},
+                 "roofline": x_roofline(x_us, wl.points, es)}
+            if mode == "plain":
+                # the step's 34 element accesses per point plus three transfers
+                r["hbm_frac_step_model"] = step_hbm_frac(wl.points, es, ms / args.multires_steps,
+                                                         3 * nbytes)
             if mode == "plain":
                 # the transfer of one component is one k_interp launch
                 r["transfer_roofline"] = {
@@ -241,7 +376,8 @@ def bench_multires(args, stream):
                 r["closure_max"] = [float(c) for c in clo]
             res.setdefault(prec, {})[mode] = r
         del UC, VC, WC, C0
-    d = fields["fp32"] - fields["fp64"]
+    acc = fp32_errors(fields["fp32"], fields["fp64"], masses["fp32"], masses["fp64"],
+                      drops["fp32"], drops["fp64"], wl.h, wl.shape[0] * wl.h, nacc)
     return {"workload": "512^3 fine mesh, periodic x,y, no-flux z, 1000 tanh drops R~U[4,12]h; "
                         "velocity on 256x256x192 (tanh-stretched z) transferred every step "
                         "(transfer inside the step time), plain and solenoidal transfer",
@@ -249,7 +385,7 @@ def bench_multires(args, stream):
             "fp32": res["fp32"]["plain"], "fp64": res["fp64"]["plain"],
             "solenoidal": {"fp32": res["fp32"]["solenoidal"], "fp64": res["fp64"]["solenoidal"]},
             "fp32_over_fp64": round(res["fp32"]["plain"]["value"] / res["fp64"]["plain"]["value"], 3),
-            "l2_rel_fp32_vs_fp64": float(np.linalg.norm(d) / np.linalg.norm(fields["fp64"]))}
+            "accuracy_fp32_vs_fp64": acc, "roofline": res["fp32"]["plain"]["roofline"]}
 
 
 def pressure_bytes_per_step(n, es):
@@ -335,19 +471,50 @@ def bench_large(args, stream):
     s.profile(False)
     cfg = s.config()
     s.close()
+    dt = wl.dt
     del wl
     torch.cuda.empty_cache()
     pts = 1536 ** 3
+    x_us = 1e3 * kern["x"][0] / max(1, kern["x"][1])
     return {"workload": "1536^3 periodic box, FP32 storage, 4000 tanh drops R~U[4,20]h, "
                         "k^-5/3 field 1<=k<=48 rms 1 (inputs generated on the GPU), "
                         "dt from the advective bound",
-            "points": pts, "steps": args.large_steps,
+            "points": pts, "steps": args.large_steps, "dt": dt,
             "fp32": {"value": round(pts * args.large_steps / (ms * 1e-3) / 1e9, 4),
                      "unit": "Gpts/s", "ms_per_step": round(ms / args.large_steps, 3),
                      "mass_drift": abs(m1 - m0) / abs(m0),
                      "kernels_avg_us": {k: round(1e3 * v[0] / max(1, v[1]), 1)
-                                        for k, v in kern.items()}},
+                                        for k, v in kern.items()},
+                     "hbm_frac_step_model": step_hbm_frac(pts, 4, ms / args.large_steps)},
+            "roofline": x_roofline(x_us, pts, 4, measured_traffic(TRAFFIC_FILE_LARGE)),
             "plan": cfg, "autotune": tune}
+
+
+def bench_subbox(args, stream, dt):
+    """The error reference of the 1536^3 workload: its 256^3 sub-box (same h,
+    the drops inside it, the velocity modes periodic on it) run in FP32 and
+    FP64 for --subbox-steps steps with the 1536^3 run's dt."""
+    import torch
+    from paper_2105_01865_amd import ch, inputs
+    wl = inputs.large_subbox()
+    out = {}
+    for prec in ("fp32", "fp64"):
+        dt_ = torch.float32 if prec == "fp32" else torch.float64
+        s = ch.State(wl.shape, wl.h, wl.Cn, wl.Pe, precision=prec, stream=stream)
+        s.set_field(torch.from_numpy(wl.C).to("cuda", dt_))
+        U, V, W = (torch.from_numpy(a).to("cuda", dt_) for a in (wl.u, wl.v, wl.w))
+        m0 = s.mass()
+        s.step(U, V, W, dt, args.subbox_steps)
+        m1 = s.mass()
+        out[prec] = (s.get_field().double().cpu().numpy(), (m0, m1), s.drops())
+        s.close()
+    acc = fp32_errors(out["fp32"][0], out["fp64"][0], out["fp32"][1], out["fp64"][1],
+                      out["fp32"][2], out["fp64"][2], wl.h, wl.shape[0] * wl.h,
+                      args.subbox_steps)
+    return {"workload": "256^3 sub-box of the 1536^3 workload: h = 1/1536, the "
+                        f"{wl.ndrops} drops lying inside it, k^-5/3 modes periodic on it "
+                        "(big-box k = 6..48) at their share of the rms",
+            "dt": dt, **acc}
 
 
 def bench_host_io(args, stream, wl, tune):
@@ -447,6 +614,90 @@ def bench_explicit25(args, stream, line):
             "time_to_solution_explicit_over_implicit_fp32": round(tts, 3)}
 
 
+def _oracle_rate(step_fn, points_per_step, tmin, tmax):
+    """Whole oracle steps until tmin seconds of work (at least one step,
+    stopping before tmax): (Gpts/s, steps, seconds)."""
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        step_fn()
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= tmin or el / steps * (steps + 1) > tmax:
+            break
+    return points_per_step * steps / el / 1e9, steps, el
+
+
+def cpu_baselines(wl, args):
+    """The FP64 oracle timed on this host: the 256^3 workload on all cores
+    (whole steps until about 10 s, the line's cpu_baseline figure) and on one
+    core (one step), then bounded samples of the other workloads: the 32^3
+    box on all cores and on one, the multiple-resolution recipe shrunk to
+    256^3 (transfer + step), one box of each edge of the ensemble, and the
+    1536^3 workload's 256^3 sub-box."""
+    import oracle
+    from paper_2105_01865_amd import inputs
+    cores = oracle.threads()
+    C = [wl.C]
+
+    def step_of(w, bc=(0, 0, 0), dt=None):
+        def f():
+            C[0] = oracle.step(C[0], w.u, w.v, w.w, w.h, w.Cn, w.Pe, dt or w.dt, 1, bc=bc)
+        return f
+
+    v, n, el = _oracle_rate(step_of(wl), wl.points, 10.0, 30.0)
+    out = {"value": round(v, 6), "unit": "Gpts/s", "cores": cores, "kind": "oracle",
+           "sample": f"{n} RK3 step(s) of the same {wl.shape[2]}^3 workload in FP64, "
+                     f"{el:.1f} s, on all {cores} threads"}
+    others = {}
+    try:
+        oracle.set_threads(1)
+        C[0] = wl.C
+        v, n, el = _oracle_rate(step_of(wl), wl.points, 0.0, 1e9)
+        out["one_core"] = {"value": round(v, 6), "unit": "Gpts/s", "cores": 1,
+                           "sample": f"{n} step of the {wl.shape[2]}^3 workload, {el:.1f} s"}
+        w1 = inputs.make_workload(1)
+        C[0] = w1.C
+        v, n, el = _oracle_rate(step_of(w1), w1.points, 2.0, 10.0)
+        others["32cube_one_core"] = {"value": round(v, 6), "cores": 1,
+                                     "sample": f"{n} steps, {el:.1f} s"}
+    finally:
+        oracle.set_threads(cores)
+    C[0] = w1.C
+    v, n, el = _oracle_rate(step_of(w1), w1.points, 2.0, 10.0)
+    others["32cube"] = {"value": round(v, 6), "cores": cores, "sample": f"{n} steps, {el:.1f} s"}
+    # the multiple-resolution recipe at 256^3: transfer from the coarse mesh
+    # and step, every step
+    w3 = inputs.make_workload(3, n=256)
+    zf, uc, vc, wc = (w3.coarse[k] for k in ("zf", "uc", "vc", "wc"))
+    C[0] = w3.C
+
+    def step3():
+        u, v_, w_ = oracle.interp_velocity(zf, uc, vc, wc, w3.shape)
+        C[0] = oracle.step(C[0], u, v_, w_, w3.h, w3.Cn, w3.Pe, w3.dt, 1, bc=(0, 0, 1))
+
+    v, n, el = _oracle_rate(step3, w3.points, 2.0, 30.0)
+    others["multires_recipe_256cube"] = {"value": round(v, 6), "cores": cores,
+                                         "sample": f"{n} steps (transfer + step), {el:.1f} s"}
+    # one box of each ensemble edge, one step each
+    E = inputs.ensemble(48)
+    picks = [next(w for w in E if w.shape[0] == e) for e in (48, 64, 96, 128, 160, 192)]
+    t0 = time.perf_counter()
+    for w in picks:
+        oracle.step(w.C, w.u, w.v, w.w, w.h, w.Cn, w.Pe, w.dt, 1)
+    el = time.perf_counter() - t0
+    others["ensemble_one_box_per_edge"] = {
+        "value": round(sum(w.points for w in picks) / el / 1e9, 6), "cores": cores,
+        "sample": f"one step of one box of each edge 48..192, {el:.1f} s"}
+    sb = inputs.large_subbox()
+    C[0] = sb.C
+    v, n, el = _oracle_rate(step_of(sb, dt=4e-5), sb.points, 1.0, 30.0)
+    others["large_subbox_256cube"] = {"value": round(v, 6), "cores": cores,
+                                      "sample": f"{n} step(s), {el:.1f} s"}
+    out["other_workloads"] = others
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -465,8 +716,16 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-ensemble and multiple-resolution lines")
     ap.add_argument("--counter-probe", nargs="?", const="fp32", default=None,
-                    choices=("fp32", "fp64"),
-                    help="two steps and a 256 MiB copy, for rocprofv3 counter runs")
+                    choices=("fp32", "fp64", "large"),
+                    help="two steps of the 256^3 box (or one of the 1536^3 box) and a "
+                         "256 MiB copy, for rocprofv3 counter runs")
+    ap.add_argument("--acc-steps", type=int, default=1000,
+                    help="steps of the FP32-vs-FP64 accuracy leg of the 256^3 box and the "
+                         "ensemble (independent of --steps)")
+    ap.add_argument("--multires-acc-steps", type=int, default=500,
+                    help="steps of the multiple-resolution accuracy leg")
+    ap.add_argument("--subbox-steps", type=int, default=200,
+                    help="steps of the 1536^3 workload's 256^3 sub-box error reference")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library "
@@ -507,6 +766,10 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = e0.elapsed_time(e1)
+        # on to --acc-steps steps from the initial field (accuracy leg)
+        done = args.warmup + args.steps
+        if args.acc_steps > done:
+            s.step(U, V, W, wl.dt, args.acc_steps - done)
         m1 = s.mass()
         C = s.get_field().double().cpu().numpy()
         cfg = s.config()
@@ -524,7 +787,7 @@ def main():
         s.profile(False)
         s.close()
         return dict(ms=ms, wall=wall, m0=m0, m1=m1, C=C, cfg=cfg, prof=prof, roots=roots,
-                    cells=cells, label_ms=label_ms, tune=tune)
+                    cells=cells, label_ms=label_ms, tune=tune, nacc=max(done, args.acc_steps))
 
     r32 = timed("fp32")
     progress("256^3 fp32 done")
@@ -534,30 +797,13 @@ def main():
     v32 = pts * nstep / (r32["ms"] * 1e-3) / 1e9
     v64 = pts * nstep / (r64["ms"] * 1e-3) / 1e9
 
-    # accuracy of FP32 against FP64 after warmup + steps
-    C32, C64 = r32["C"], r64["C"]
-    l2 = float(np.linalg.norm(C32 - C64) / np.linalg.norm(C64))
-    drift32 = abs(r32["m1"] - r32["m0"]) / r32["m0"]
-    drift64 = abs(r64["m1"] - r64["m0"]) / r64["m0"]
-    v32vol = float((C32 >= 0.5).sum()) * h ** 3
-    v64vol = float((C64 >= 0.5).sum()) * h ** 3
-    vol_err = abs(v32vol - v64vol) / v64vol
-    # per-drop volumes (drops matched by their root, the smallest cell index)
-    c64 = dict(zip(r64["roots"].tolist(), r64["cells"].tolist()))
-    matched = [(c, c64[r]) for r, c in zip(r32["roots"].tolist(), r32["cells"].tolist()) if r in c64]
-    dh = np.cbrt(6.0 * r64["cells"] * h ** 3 / np.pi) / (wl.shape[0] * h)
-    drops = {"definition": "face-connected cells with C >= 1/2 (periodic), V = h^3 cells, "
-                           "(4 pi/3)(D/2)^3 = V, H = box height",
-             "count_fp32": int(len(r32["roots"])), "count_fp64": int(len(r64["roots"])),
-             "matched_by_root": len(matched),
-             "max_rel_volume_err_fp32_vs_fp64": max((abs(a - b) / b for a, b in matched),
-                                                    default=None),
-             "D_over_H_fp64": {"min": float(dh.min()), "median": float(np.median(dh)),
-                               "max": float(dh.max())} if len(dh) else None,
-             "label_ms_fp32": round(r32["label_ms"], 2), "label_ms_fp64": round(r64["label_ms"], 2),
-             "label_ms_note": "ch_drops wall time: labelling, counting, copy-out and sort",
-             "l_loss_fp32": (r32["m1"] - r32["m0"]) / r32["m0"],
-             "l_loss_fp64": (r64["m1"] - r64["m0"]) / r64["m0"]}
+    # accuracy of FP32 against FP64 after --acc-steps steps from the same field
+    acc = fp32_errors(r32["C"], r64["C"], (r32["m0"], r32["m1"]), (r64["m0"], r64["m1"]),
+                      (r32["roots"], r32["cells"]), (r64["roots"], r64["cells"]), h,
+                      wl.shape[0] * h, r32["nacc"])
+    acc["drops"]["label_ms_fp32"] = round(r32["label_ms"], 2)
+    acc["drops"]["label_ms_fp64"] = round(r64["label_ms"], 2)
+    acc["drops"]["label_ms_note"] = "ch_drops wall time: labelling, counting, copy-out and sort"
 
     def kern(r):
         return {k: dict(avg_us=round(1e3 * r["prof"][k][0] / max(1, r["prof"][k][1]), 2),
@@ -568,9 +814,26 @@ def main():
     x_avg_s = xms / xn * 1e-3
     x_flops = x_pass_flops_per_point() * pts
     achieved = x_flops / x_avg_s / 1e12
-    x_bytes = x_pass_bytes_per_point(4) * pts
-    x_gbs = x_bytes / x_avg_s / 1e9
     traffic = measured_traffic()
+    roof = x_roofline(x_avg_s * 1e6, pts, 4, traffic,
+                      kernel="k_pass_x (explicit terms + RHS + x solve), fp32")
+    roof.update({
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                        "copy-calibrated)",
+        "bytes_per_point": x_pass_bytes_per_point(4),
+        "measured_gbs": round(traffic / x_avg_s / 1e9, 1) if traffic else None,
+        "measured_frac": round(traffic / x_avg_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+        "traffic_over_algorithmic": (round(traffic / roof["algorithmic_bytes_per_launch"], 3)
+                                     if traffic else None),
+        # the same launch against the vector ALUs (the pass issues more VALU
+        # instructions than its algorithmic flops)
+        "alu_view": {"flops_per_point": x_pass_flops_per_point(),
+                     "achieved_tflops": round(achieved, 3),
+                     "peak_published_fp32_tflops": VALU_PEAK_PUBLISHED_FP32_TFLOPS,
+                     "frac_published": round(achieved / VALU_PEAK_PUBLISHED_FP32_TFLOPS, 4),
+                     "peak_nonpacked_tflops": VALU_PEAK_TFLOPS,
+                     "frac_nonpacked": round(achieved / VALU_PEAK_TFLOPS, 4)},
+        "window": f"{args.profile_steps} profiled steps, HIP events per launch"})
 
     line = {
         "metric": METRIC,
@@ -594,28 +857,10 @@ def main():
                  "ms_per_step": round(r64["ms"] / nstep, 5), "plan": r64["cfg"],
                  "autotune": r64["tune"]},
         "fp32_over_fp64": round(v32 / v64, 3),
-        "accuracy_fp32_vs_fp64": {"steps": args.warmup + nstep, "l2_rel": l2,
-                                  "mass_drift_fp32": drift32, "mass_drift_fp64": drift64,
-                                  "drop_volume_err": vol_err, "drops": drops},
-        "hbm_frac_step_model": round(step_bytes_per_point(4) * pts /
-                                     (r32["ms"] / nstep * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "roofline": {"bound": "alu", "kernel": "k_pass_x (explicit terms + RHS + x solve), fp32",
-                     "achieved": round(achieved, 3), "peak": VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TFLOPS, 4),
-                     "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 "
-                     "FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "flops_per_point": x_pass_flops_per_point(),
-                     "avg_launch_us": round(x_avg_s * 1e6, 2),
-                     "hbm_view": {"bytes_per_point": x_pass_bytes_per_point(4),
-                                  "achieved_gbs": round(x_gbs, 1),
-                                  "frac_of_8000": round(x_gbs / HBM_PEAK_GBS, 4),
-                                  # measured bytes (counters) over the same launch time
-                                  "measured_gbs": (round(traffic / x_avg_s / 1e9, 1)
-                                                   if traffic else None),
-                                  "measured_frac_of_8000": (round(traffic / x_avg_s / 1e9
-                                                                  / HBM_PEAK_GBS, 4)
-                                                            if traffic else None)},
-                     "window": f"{args.profile_steps} profiled steps, HIP events per launch"},
+        "accuracy_fp32_vs_fp64": acc,
+        "hbm_frac_step_model": step_hbm_frac(pts, 4, r32["ms"] / nstep),
+        "hbm_frac_step_model_fp64": step_hbm_frac(pts, 8, r64["ms"] / nstep),
+        "roofline": roof,
         "kernels_fp32": kern(r32),
         "kernels_fp64": kern(r64),
     }
@@ -631,26 +876,14 @@ def main():
         progress("pressure step done")
         line["large"] = bench_large(args, stream)
         progress("1536^3 done")
+        line["large"]["subbox_accuracy_fp32_vs_fp64"] = bench_subbox(args, stream,
+                                                                     line["large"]["dt"])
+        progress("1536^3 sub-box accuracy done")
         line["explicit25"] = bench_explicit25(args, stream, line)
         progress("explicit 25-point done")
 
     if not args.no_cpu_baseline:
-        # the FP64 oracle on the same workload, whole RK3 steps until about
-        # 10 s of work (at most 30 s)
-        import oracle
-        C = wl.C
-        steps = 0
-        t0 = time.perf_counter()
-        while True:
-            C = oracle.step(C, wl.u, wl.v, wl.w, h, wl.Cn, wl.Pe, wl.dt, 1)
-            steps += 1
-            el = time.perf_counter() - t0
-            if el >= 10.0 or el / steps * (steps + 1) > 30.0:
-                break
-        line["cpu_baseline"] = {"value": round(pts * steps / el / 1e9, 6), "unit": "Gpts/s",
-                                "cores": oracle.threads(), "kind": "oracle",
-                                "sample": f"{steps} RK3 step(s) of the same {wl.shape[2]}^3 "
-                                          f"workload in FP64, {el:.1f} s"}
+        line["cpu_baseline"] = cpu_baselines(wl, args)
         progress("cpu baseline done")
     print(json.dumps(line), flush=True)
 

@@ -101,6 +101,12 @@ typedef struct {
     int seg_len;        /* y/z line segment per work-group; 0 = automatic */
     int waves_yz;       /* waves per y/z work-group (1..8); 0 = automatic */
     int z_chunk;        /* planes one x-pass work-group marches over; 0 = automatic */
+    double dt_hint;     /* > 0: plan the line-solve recurrences and launches for
+                           this dt at creation (a dt the solver cannot take is
+                           then reported by the create call, and a first step
+                           with this dt does no planning); 0 (default): plan
+                           at the first step.  Negative or non-finite:
+                           CH_EINVAL. */
 } ch_opts;
 
 typedef struct ch_state ch_state;

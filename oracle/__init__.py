@@ -60,6 +60,8 @@ def lib():
                                              _D, _D, _D, ctypes.c_double, ctypes.c_int]
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_threads.argtypes = []
+        L.oracle_set_threads.restype = None
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_mass.restype = ctypes.c_double
         L.oracle_mass.argtypes = [ctypes.c_int64, ctypes.c_double, _D]
         L.oracle_hermite_stencil.argtypes = [ctypes.c_int64, _D, ctypes.c_double, ctypes.c_int,
@@ -195,6 +197,12 @@ def step_explicit25(C, u, v, w, h, Cn, Pe, dt, nsteps=1, bc=(0, 0, 0),
 def threads():
     """Threads the oracle's parallel loops use."""
     return lib().oracle_threads()
+
+
+def set_threads(n):
+    """Threads for the oracle's parallel loops from now on (0: one per
+    processor)."""
+    lib().oracle_set_threads(int(n))
 
 
 def mass(C, h):

@@ -592,3 +592,13 @@ int oracle_threads(void)
     return 1;
 #endif
 }
+
+/* Set the threads of the parallel loops (n <= 0: one per processor). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}

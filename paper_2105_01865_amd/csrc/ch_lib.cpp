@@ -939,6 +939,7 @@ ch_status ch_create(const ch_grid* g, double Cn, double Pe, const ch_psi* psi, c
     ch_state* s = new (std::nothrow) ch_state();
     if (!s) return fail(CH_ENOMEM, "host allocation failed");
     ch_status st = init_engine(s->e, 1, g, &Cn, &Pe, psi, bc, opt);
+    if (st == CH_OK && s->e.P.opt.dt_hint > 0.0) st = set_dt(s->e, s->e.P.opt.dt_hint);
     if (st != CH_OK) {
         free_engine(s->e);
         delete s;
@@ -1047,6 +1048,7 @@ ch_status ch_batch_create(int nbox, const ch_grid* g, const double* Cn, const do
     ch_batch* b = new (std::nothrow) ch_batch();
     if (!b) return fail(CH_ENOMEM, "host allocation failed");
     ch_status st = init_engine(b->e, nbox, g, Cn, Pe, psi, bc, opt);
+    if (st == CH_OK && b->e.P.opt.dt_hint > 0.0) st = set_dt(b->e, b->e.P.opt.dt_hint);
     if (st != CH_OK) {
         free_engine(b->e);
         delete b;

@@ -141,6 +141,8 @@ inline ch_status plan_init(Plan& P, int nbox, const ch_grid* g, const double* Cn
         return P.fail(CH_EINVAL, "weno_eps must be > 0 and finite");
     if (o.solve_fp64 < CH_SOLVE_AUTO || o.solve_fp64 > CH_SOLVE_NATIVE)
         return P.fail(CH_EINVAL, "unknown solve_fp64 mode");
+    if (!(o.dt_hint >= 0.0) || !std::isfinite(o.dt_hint))
+        return P.fail(CH_EINVAL, "dt_hint must be >= 0 and finite");
     if (o.x_rows < 0 || o.x_rows > 64 || o.seg_len < 0 || o.waves_yz < 0 || o.waves_yz > 8 ||
         o.z_chunk < 0)
         return P.fail(CH_EINVAL, "launch options out of range");

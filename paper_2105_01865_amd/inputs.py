@@ -411,6 +411,35 @@ def make_workload(config: int, n: int | None = None, seed: int | None = None, bo
     raise ValueError(f"unknown config {config}")
 
 
+def large_subbox(n_sub=256, n_big=1536):
+    """The error reference of the 1536^3 workload: a 256^3 periodic box with
+    the same h = 1/1536, holding the drops of the 1536^3 workload that lie
+    inside the sub-box [0, 256 h)^3 (their centres at least R + 4 h from its
+    faces, so the sub-box's own wrap does not cut them), in a k^-5/3 field
+    made of the modes that are periodic on the sub-box: wavenumbers 6 to 48
+    of the big box are 1 to 8 of the sub-box.  Its rms is the share of the
+    big field's energy those modes carry (shell energies ~ k^-5/3).  The
+    phases are the sub-box's own (seed of the 1536^3 workload, box 1).
+    dt is left to the caller (the 1536^3 run's)."""
+    h = 1.0 / n_big
+    rng = np.random.default_rng(seed_for(4))
+    cen, rad = place_drops(rng, 4000, 4, 20, (n_big,) * 3, h)
+    L = n_sub * h
+    gap = 4 * h
+    inside = np.all((cen >= rad[:, None] + gap) & (cen <= L - rad[:, None] - gap), axis=1)
+    cen, rad = cen[inside], rad[inside]
+    shape = (n_sub,) * 3
+    C = drop_field(shape, h, h, cen, rad)
+    ratio = n_big // n_sub
+    kmax_big = 48
+    ks = np.arange(1, kmax_big + 1, dtype=np.float64)
+    share = math.sqrt((ks[ks >= ratio] ** (-5.0 / 3.0)).sum() / (ks ** (-5.0 / 3.0)).sum())
+    rng = np.random.default_rng(seed_for(4, box=1))
+    u, v, w = random_solenoidal(rng, shape, h, 1, kmax_big // ratio, rms=share)
+    return Workload("large-subbox", shape, h, h, 0.9 / h, 1e-4, 200, (0, 0, 0), C, u, v, w,
+                    ndrops=len(rad))
+
+
 def ensemble(nbox=48, n_override=None):
     """The batched ensemble: nbox independent periodic boxes."""
     return [make_workload(5, n=n_override, box=b) for b in range(nbox)]

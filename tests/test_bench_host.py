@@ -45,3 +45,39 @@ def test_traffic_is_reported_only_for_the_sources_it_was_taken_on(tmp_path, monk
     assert bench.measured_traffic() is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.md"))
     assert bench.measured_traffic() is None
+
+
+def test_roofline_and_step_fractions():
+    # 16.78 M points at 25.33 B each in 100 us: 4.25 TB/s
+    r = bench.x_roofline(100.0, 256 ** 3, 4, traffic=5e8)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert r["algorithmic_bytes_per_launch"] == pytest.approx(256 ** 3 * 19 / 3 * 4)
+    assert r["achieved"] == pytest.approx(256 ** 3 * 19 / 3 * 4 / 1e-4 / 1e9, rel=1e-4)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, rel=1e-3)
+    assert r["traffic"] == 5e8
+    # 34 elements per point per step
+    f = bench.step_hbm_frac(256 ** 3, 4, 0.5, extra_bytes=1e8)
+    assert f == pytest.approx((136 * 256 ** 3 + 1e8) / 5e-4 / 8e12, rel=1e-3)
+
+
+def test_fp32_error_summary_and_drop_pdf():
+    import numpy as np
+    rng = np.random.default_rng(0)
+    C64 = rng.uniform(size=(8, 8, 8))
+    C32 = C64 + 1e-6
+    roots = np.array([0, 40, 90])
+    d64 = (roots, np.array([100, 30, 8]))
+    d32 = (roots[:2], np.array([101, 30]))
+    e = bench.fp32_errors(C32, C64, (2.0, 2.0 + 1e-9), (2.0, 2.0), d32, d64, 0.5, 4.0, 7)
+    assert e["steps"] == 7
+    assert e["l2_rel"] == pytest.approx(1e-6 * np.sqrt(C64.size) / np.linalg.norm(C64), rel=1e-6)
+    assert e["mass_drift_fp32"] == pytest.approx(5e-10) and e["mass_drift_fp64"] == 0.0
+    assert e["drop_volume_err"] == pytest.approx(abs(131 - 138) / 138)
+    assert e["drops"]["matched_by_root"] == 2
+    assert e["drops"]["max_rel_volume_err_fp32_vs_fp64"] == pytest.approx(0.01)
+    pdf = e["drops"]["D_over_H_pdf_fp64"]
+    assert pdf["drops"] == 3 and sum(pdf["counts"]) == 3
+    width = pdf["edges"][1] - pdf["edges"][0]
+    assert sum(pdf["pdf"]) * width == pytest.approx(1.0, rel=1e-3)
+    dmax = np.cbrt(6 * 100 * 0.125 / np.pi) / 4.0
+    assert pdf["max"] == pytest.approx(dmax)

@@ -320,6 +320,22 @@ def test_error_paths():
     s.close()
 
 
+def test_dt_hint_plans_at_creation_and_steps_alike():
+    """ch_opts.dt_hint plans the recurrences and launches at creation; the
+    steps are the same bits as those of a state planned at its first step."""
+    C, u, v, w, h = _case((24, 20, 28), seed=31)
+    dt = 3e-4
+    a = ch.State(C.shape, h, h, 0.9 / h, dt_hint=dt)
+    assert a.config()["tw"][0] > 0          # planned before any step
+    b = ch.State(C.shape, h, h, 0.9 / h)
+    for s in (a, b):
+        s.set_field(dev(C))
+        s.step(dev(u), dev(v), dev(w), dt, 2)
+    assert torch.equal(a.get_field(), b.get_field())
+    a.close()
+    b.close()
+
+
 def test_256cube_full_size_fp64_one_step_against_oracle():
     """The 256^3 workload in the launch configuration the benchmark times
     (default plan, graph replay on a stream), one step against the oracle."""

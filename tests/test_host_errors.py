@@ -92,3 +92,9 @@ def test_create_rejects_bad_parameters_before_any_allocation():
     assert L.ch_create(ctypes.byref(g), 0.0625, 14.4, None, None, ctypes.byref(o),
                        ctypes.byref(h)) == EINVAL
     assert h.value is None
+    for bad in (-1e-4, float("inf"), float("nan")):
+        o = ch.make_opts(dt_hint=bad)
+        assert L.ch_create(ctypes.byref(g), 0.0625, 14.4, None, None, ctypes.byref(o),
+                           ctypes.byref(h)) == EINVAL
+        assert "dt_hint" in L.ch_last_error().decode()
+        assert h.value is None
