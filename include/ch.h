@@ -163,6 +163,23 @@ ch_status ch_step_explicit25(ch_state* s, const void* u, const void* v, const vo
  * the mass-loss measure of sec. 4.3.1).  Waits for the stream. */
 ch_status ch_mass(ch_state* s, double* out);
 
+/* Allocation-free mass of a field, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same fixed-order FP64 sum h^3 sum C as ch_mass
+ * (the same bits for the same field), of the field C (device memory,
+ * [nz][ny][nx] x-fastest, FP64 or FP32 by `precision`), written as one
+ * double to out_dev (device memory) on `stream` (a hipStream_t; NULL is the
+ * null stream).  It enqueues two kernels and returns without waiting; it
+ * calls no allocating routine.  The partial sums live in one library-wide
+ * device array of 2^20 doubles (8 MiB, held per GPU until the process
+ * ends), so a field has at most 2^32 cells (CH_EINVAL beyond).  Calls that
+ * overlap on one GPU (different streams, or threads) share that array and
+ * race: order them on one stream.  Errors: CH_EINVAL (null pointer, an
+ * extent < 1, h <= 0 or non-finite, unknown precision, too many cells),
+ * CH_EHIP. */
+ch_status ch_mass_field_noalloc(const void* C, int64_t nx, int64_t ny, int64_t nz, double h,
+                                int precision, void* stream, double* out_dev);
+
 /* Check the velocity: finite everywhere and zero on no-flux walls.  Waits.
  * Returns CH_OK, CH_ENONFINITE or CH_EINVAL. */
 ch_status ch_check_velocity(ch_state* s, const void* u, const void* v, const void* w);

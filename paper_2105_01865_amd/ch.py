@@ -82,6 +82,8 @@ SIGNATURES = {
     "ch_step": (_I, [_VP, _VP, _VP, _VP, _D, _I]),
     "ch_step_explicit25": (_I, [_VP, _VP, _VP, _VP, _D, _I]),
     "ch_mass": (_I, [_VP, _PD]),
+    "ch_mass_field_noalloc": (_I, [_VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _D, _I,
+                                   _VP, _VP]),
     "ch_check_velocity": (_I, [_VP, _VP, _VP, _VP]),
     "ch_destroy": (None, [_VP]),
     "ch_last_error": (ctypes.c_char_p, []),
@@ -167,6 +169,24 @@ def make_opts(precision="fp64", kappa=4.0, weno_eps=1e-6, solve="auto", use_grap
     o.x_rows, o.seg_len, o.waves_yz, o.z_chunk = x_rows, seg_len, waves_yz, z_chunk
     o.dt_hint = float(dt_hint)
     return o
+
+
+def mass_field_noalloc(C, h, out, stream=None):
+    """ch_mass_field_noalloc: h^3 sum C of the CUDA tensor C (nz, ny, nx),
+    FP64 or FP32, written to the one-element float64 CUDA tensor `out` on
+    `stream` (the current stream if None), without allocating."""
+    if C.dim() != 3:
+        raise ValueError("C must be (nz, ny, nx)")
+    prec = _prec(C.dtype)
+    p = _dev_tensor(C, C.dtype, tuple(C.shape), "C")
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
+            and out.numel() >= 1):
+        raise ValueError("out must be a float64 CUDA tensor")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    nz, ny, nx = C.shape
+    _check(lib().ch_mass_field_noalloc(p, nx, ny, nz, float(h), prec,
+                                       ctypes.c_void_p(st.cuda_stream),
+                                       ctypes.c_void_p(out.data_ptr())))
 
 
 def _dev_tensor(t, dtype, shape, name):

@@ -26,6 +26,12 @@ template <typename T>
 hipError_t launch_mass(int nblk, int nbox, hipStream_t st, const chd::BoxDesc* boxes,
                        const void* C, double* partial, const double* h3, double* out);
 
+// Mass of one field described by bd (c_off 0, nmblk blocks): partial holds
+// bd.nmblk doubles of scratch, out one double (device memory).
+template <typename T>
+hipError_t launch_mass_one(hipStream_t st, const chd::BoxDesc& bd, const void* C,
+                           double* partial, double h3, double* out);
+
 template <typename T>
 hipError_t launch_check_velocity(hipStream_t st, const chd::BoxDesc* boxes, int nbox,
                                  const void* U, const void* V, const void* W, int* flags);

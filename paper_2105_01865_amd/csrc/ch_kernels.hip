@@ -71,14 +71,48 @@ k_pass_line(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
     chd::pass_line_program<T, A>(ex, &st, boxes[b], pa, PASS, task, Qin, Qout, smem);
 }
 
-// Mass, stage 1: one fixed block of C per work-group, summed in double in a
-// fixed order.
+// Mass, stage 1 body: block `blk` of box bd (MASS_BLOCK elements of C),
+// summed in double in a fixed order, written to *partial.
+template <typename T>
+__device__ void mass_partial_body(const chd::BoxDesc& bd, int blk, const T* __restrict__ C,
+                                  double* __restrict__ partial)
+{
+    __shared__ double sh[chd::MASS_THREADS];
+    const int tid = threadIdx.x;
+    sh[tid] = chd::mass_thread_sum<T>(tid, bd, blk, C);
+    __syncthreads();
+    for (int s = chd::MASS_THREADS / 2; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0) *partial = sh[0];
+}
+
+// Mass, stage 2 body: a box's nmblk partials summed in a fixed order and
+// scaled by h^3.
+__device__ void mass_final_body(const double* __restrict__ partial, int nmblk, double h3,
+                                double* __restrict__ out)
+{
+    __shared__ double sh[chd::MASS_THREADS];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int i = tid; i < nmblk; i += chd::MASS_THREADS) s += partial[i];
+    sh[tid] = s;
+    __syncthreads();
+    for (int st = chd::MASS_THREADS / 2; st > 0; st >>= 1) {
+        if (tid < st) sh[tid] += sh[tid + st];
+        __syncthreads();
+    }
+    if (tid == 0) *out = sh[0] * h3;
+}
+
+// Mass, stage 1: one fixed block of C per work-group (the box found from the
+// block index).
 template <typename T>
 __global__ void __launch_bounds__(chd::MASS_THREADS)
 k_mass_partial(const chd::BoxDesc* __restrict__ boxes, int nbox, const T* __restrict__ C,
                double* __restrict__ partial)
 {
-    __shared__ double sh[chd::MASS_THREADS];
     const int blk = blockIdx.x;
     int lo = 0, hi = nbox - 1;
     while (lo < hi) {
@@ -87,34 +121,32 @@ k_mass_partial(const chd::BoxDesc* __restrict__ boxes, int nbox, const T* __rest
         else hi = mid - 1;
     }
     const chd::BoxDesc& bd = boxes[lo];
-    const int tid = threadIdx.x;
-    sh[tid] = chd::mass_thread_sum<T>(tid, bd, blk - bd.mblk0, C);
-    __syncthreads();
-    for (int s = chd::MASS_THREADS / 2; s > 0; s >>= 1) {
-        if (tid < s) sh[tid] += sh[tid + s];
-        __syncthreads();
-    }
-    if (tid == 0) partial[blk] = sh[0];
+    mass_partial_body<T>(bd, blk - bd.mblk0, C, partial + blk);
 }
 
-// Mass, stage 2: one work-group per box sums its partials in a fixed order
-// and scales by h^3.
+// Mass, stage 2: one work-group per box.
 __global__ void __launch_bounds__(chd::MASS_THREADS)
 k_mass_final(const chd::BoxDesc* __restrict__ boxes, const double* __restrict__ partial,
              const double* __restrict__ h3, double* __restrict__ out)
 {
-    __shared__ double sh[chd::MASS_THREADS];
     const chd::BoxDesc& bd = boxes[blockIdx.x];
-    const int tid = threadIdx.x;
-    double s = 0.0;
-    for (int i = tid; i < bd.nmblk; i += chd::MASS_THREADS) s += partial[bd.mblk0 + i];
-    sh[tid] = s;
-    __syncthreads();
-    for (int st = chd::MASS_THREADS / 2; st > 0; st >>= 1) {
-        if (tid < st) sh[tid] += sh[tid + st];
-        __syncthreads();
-    }
-    if (tid == 0) out[blockIdx.x] = sh[0] * h3[blockIdx.x];
+    mass_final_body(partial + bd.mblk0, bd.nmblk, h3[blockIdx.x], out + blockIdx.x);
+}
+
+// The same two stages for one field described by value (no box table in
+// device memory): the allocation-free mass.
+template <typename T>
+__global__ void __launch_bounds__(chd::MASS_THREADS)
+k_mass_partial_one(chd::BoxDesc bd, const T* __restrict__ C, double* __restrict__ partial)
+{
+    mass_partial_body<T>(bd, blockIdx.x, C, partial + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(chd::MASS_THREADS)
+k_mass_final_one(int nmblk, const double* __restrict__ partial, double h3,
+                 double* __restrict__ out)
+{
+    mass_final_body(partial, nmblk, h3, out);
 }
 
 // Velocity check: non-finite values anywhere, non-zero normal velocity on a
@@ -1087,6 +1119,19 @@ hipError_t launch_mass(int nblk, int nbox, hipStream_t st, const chd::BoxDesc* b
 }
 
 template <typename T>
+hipError_t launch_mass_one(hipStream_t st, const chd::BoxDesc& bd, const void* C,
+                           double* partial, double h3, double* out)
+{
+    hipLaunchKernelGGL((k_mass_partial_one<T>), dim3(bd.nmblk), dim3(chd::MASS_THREADS), 0, st,
+                       bd, (const T*)C, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mass_final_one, dim3(1), dim3(chd::MASS_THREADS), 0, st, bd.nmblk,
+                       (const double*)partial, h3, out);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_check_velocity(hipStream_t st, const chd::BoxDesc* boxes, int nbox,
                                  const void* U, const void* V, const void* W, int* flags)
 {
@@ -1254,6 +1299,10 @@ template hipError_t launch_mass<double>(int, int, hipStream_t, const chd::BoxDes
                                         double*, const double*, double*);
 template hipError_t launch_mass<float>(int, int, hipStream_t, const chd::BoxDesc*, const void*,
                                        double*, const double*, double*);
+template hipError_t launch_mass_one<double>(hipStream_t, const chd::BoxDesc&, const void*, double*,
+                                            double, double*);
+template hipError_t launch_mass_one<float>(hipStream_t, const chd::BoxDesc&, const void*, double*,
+                                           double, double*);
 template hipError_t launch_check_velocity<double>(hipStream_t, const chd::BoxDesc*, int,
                                                   const void*, const void*, const void*, int*);
 template hipError_t launch_check_velocity<float>(hipStream_t, const chd::BoxDesc*, int,

@@ -922,6 +922,37 @@ struct ch_poisson {
     void* cp = nullptr;     // Thomas scratch, nz x ny x (nx/2 + 1) reals
 };
 
+// ---- allocation-free mass ---------------------------------------------------
+// Partial sums of ch_mass_field_noalloc: one array per GPU, for the life of
+// the process.  Host code never uses this name as an address (on the host it
+// is only a stand-in); the device address comes from hipGetSymbolAddress,
+// once per device, and is kept in g_scratch_ptr.
+constexpr int NOALLOC_PARTIALS = 1 << 20;
+static __device__ __align__(256) double scratch[NOALLOC_PARTIALS];
+
+static std::mutex g_scratch_mu;
+static std::unordered_map<int, double*> g_scratch_ptr;
+
+// Device address of `scratch` on the current device (looked up on the
+// first call there).
+static ch_status scratch_ptr(double** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> l(g_scratch_mu);
+    const auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return CH_OK;
+    }
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(CH_EHIP, "no device address for the mass scratch array");
+    g_scratch_ptr[dev] = (double*)p;
+    *out = (double*)p;
+    return CH_OK;
+}
+
 extern "C" {
 
 void ch_default_opts(ch_opts* o)
@@ -994,6 +1025,39 @@ ch_status ch_mass(ch_state* s, double* out)
 {
     CHECK_STATE(s);
     return mass(s->e, out);
+}
+
+ch_status ch_mass_field_noalloc(const void* C, int64_t nx, int64_t ny, int64_t nz, double h,
+                                int precision, void* stream, double* out_dev)
+{
+    if (!C || !out_dev) return fail(CH_EINVAL, "null pointer");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(CH_EINVAL, "extents must be >= 1");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(CH_EINVAL, "h must be > 0 and finite");
+    if (precision != CH_FP64 && precision != CH_FP32) return fail(CH_EINVAL, "unknown precision");
+    // cells within NOALLOC_PARTIALS blocks, and each extent within the box
+    // table's 32-bit fields
+    if (nx > INT32_MAX || ny > INT32_MAX || nz > INT32_MAX ||
+        (double)nx * (double)ny * (double)nz > (double)NOALLOC_PARTIALS * chd::MASS_BLOCK)
+        return fail(CH_EINVAL, "field larger than %lld cells (the scratch array's limit)",
+                    (long long)NOALLOC_PARTIALS * chd::MASS_BLOCK);
+    const int64_t cells = nx * ny * nz;
+    chd::BoxDesc bd{};
+    bd.n[0] = (int)nx;
+    bd.n[1] = (int)ny;
+    bd.n[2] = (int)nz;
+    bd.c_off = 0;
+    bd.mblk0 = 0;
+    bd.nmblk = (int)((cells + chd::MASS_BLOCK - 1) / chd::MASS_BLOCK);
+    double* partial = nullptr;
+    ch_status st = scratch_ptr(&partial);
+    if (st != CH_OK) return st;
+    const hipStream_t hs = (hipStream_t)stream;
+    const double h3 = h * h * h;
+    const hipError_t err = precision == CH_FP64
+        ? chk::launch_mass_one<double>(hs, bd, C, partial, h3, out_dev)
+        : chk::launch_mass_one<float>(hs, bd, C, partial, h3, out_dev);
+    if (err != hipSuccess) return fail(CH_EHIP, "mass kernels failed: %s", hipGetErrorString(err));
+    return CH_OK;
 }
 
 ch_status ch_check_velocity(ch_state* s, const void* u, const void* v, const void* w)

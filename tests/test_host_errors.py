@@ -98,3 +98,14 @@ def test_create_rejects_bad_parameters_before_any_allocation():
                            ctypes.byref(h)) == EINVAL
         assert "dt_hint" in L.ch_last_error().decode()
         assert h.value is None
+
+
+def test_noalloc_mass_checks_arguments_before_any_gpu_call():
+    L = ch.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.ch_mass_field_noalloc(fake, 0, 4, 4, 0.1, ch.CH_FP64, None, fake) == EINVAL
+    assert L.ch_mass_field_noalloc(None, 4, 4, 4, 0.1, ch.CH_FP64, None, fake) == EINVAL
+    assert L.ch_mass_field_noalloc(fake, 4, 4, 4, float("nan"), ch.CH_FP64, None, fake) == EINVAL
+    # 2^32 cells is the limit of the scratch array's partial sums
+    assert L.ch_mass_field_noalloc(fake, 4096, 4096, 257, 0.1, ch.CH_FP32, None, fake) == EINVAL
+    assert "limit" in L.ch_last_error().decode()
