@@ -101,6 +101,9 @@ typedef struct {
     int seg_len;        /* y/z line segment per work-group; 0 = automatic */
     int waves_yz;       /* waves per y/z work-group (1..8); 0 = automatic */
     int z_chunk;        /* planes one x-pass work-group marches over; 0 = automatic */
+    int x_general;      /* 1: always run the general x-pass program; 0 (default):
+                           the one-row program wherever a task holds one x-line
+                           (the same arithmetic; a tuning and testing knob) */
     double dt_hint;     /* > 0: plan the line-solve recurrences and launches for
                            this dt at creation (a dt the solver cannot take is
                            then reported by the create call, and a first step

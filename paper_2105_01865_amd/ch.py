@@ -49,7 +49,8 @@ class Opts(ctypes.Structure):
                 ("weno_eps", ctypes.c_double), ("solve_fp64", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("x_rows", ctypes.c_int),
                 ("seg_len", ctypes.c_int), ("waves_yz", ctypes.c_int),
-                ("z_chunk", ctypes.c_int), ("dt_hint", ctypes.c_double)]
+                ("z_chunk", ctypes.c_int), ("x_general", ctypes.c_int),
+                ("dt_hint", ctypes.c_double)]
 
 
 _lib = None
@@ -158,7 +159,7 @@ def _prec(p):
 
 
 def make_opts(precision="fp64", kappa=4.0, weno_eps=1e-6, solve="auto", use_graph=True,
-              x_rows=0, seg_len=0, waves_yz=0, z_chunk=0, dt_hint=0.0):
+              x_rows=0, seg_len=0, waves_yz=0, z_chunk=0, dt_hint=0.0, x_general=False):
     o = Opts()
     lib().ch_default_opts(ctypes.byref(o))
     o.precision = _prec(precision)
@@ -168,6 +169,7 @@ def make_opts(precision="fp64", kappa=4.0, weno_eps=1e-6, solve="auto", use_grap
     o.use_graph = 1 if use_graph else 0
     o.x_rows, o.seg_len, o.waves_yz, o.z_chunk = x_rows, seg_len, waves_yz, z_chunk
     o.dt_hint = float(dt_hint)
+    o.x_general = 1 if x_general else 0
     return o
 
 

@@ -164,13 +164,15 @@ struct PlaneRef {
             return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
         }
     }
-    __device__ void store(uint32_t boff, T v) const
+    __device__ void store(uint32_t boff, T v) const { store(boff, 0u, v); }
+    __device__ void store(uint32_t voff, uint32_t soff, T v) const
     {
         if constexpr (sizeof(T) == 4) {
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, boff, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rs, voff, soff,
+                                                  0);
         } else {
             typedef uint32_t u2 __attribute__((ext_vector_type(2)));
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, boff, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, voff, soff, 0);
         }
     }
 #else
@@ -189,6 +191,7 @@ struct PlaneRef {
 #endif
     }
     CH_HD T operator()(uint32_t voff, uint32_t soff) const { return (*this)(voff + soff); }
+    CH_HD void store(uint32_t voff, uint32_t soff, T v) const { store(voff + soff, v); }
     CH_HD void store(uint32_t boff, T v) const
     {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -990,8 +993,10 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                     T dZ[5];
 #pragma unroll
                     for (int j = 0; j < 5; ++j) dZ[j] = c[j + 2] - c[j + 1];
-                    if (zs == 0)
-                        s.fzl[m] = vl[4] * face_weno<T>(vl[4], c[0], c[1], c[2], c[3], c[4], c[5], epsw);
+                    if (zs == 0)   // the low face of the task's first plane, in the same
+                                   // form as every face after it
+                        s.fzl[m] = flux_weno_d<T>(vl[4], c[1] - c[0], c[2] - c[1], c[3] - c[2],
+                                                  c[4] - c[3], c[5] - c[4], c[2], c[3], epsw);
                     const T fzh =
                         flux_weno_d<T>(vl[5], dZ[0], dZ[1], dZ[2], dZ[3], dZ[4], c[3], c[4], epsw);
                     s.pz[m] = fzh - s.fzl[m];
@@ -1081,6 +1086,293 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 Qz.store(s.col[m], T(tb[(x + tw) * L.tbp + zs * rows + r]));
             }
         }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Pass X with one row per task (the same arithmetic as pass_x_program, which
+// the plan takes instead whenever a task holds one x-line and the fields
+// fit the addressing below).
+//
+// With one row per work-group the y-direction stencil of a cell is its own
+// column: the six halo rows of C go straight into the thread's registers,
+// and the y differences, both y face fluxes and the y neighbours of psi'(C)
+// are formed there.  LDS carries only the owned row (C and psi'(C) with
+// their x halos), the x face fluxes and the solve tile.  Each field of the
+// box is one buffer resource with 32-bit byte offsets (every field of every
+// box under 4 GiB): the plane goes into the scalar offset, the cell into the
+// lane offset, so no address is formed per plane and lane.  Threads past the
+// row's end read the last cell and store nothing.
+//
+// LDS (launch-wide):
+//   cr: nx_max + 6 T       C of the owned row, columns -3 .. nx+2
+//   mr: nx_max + 2 T       psi'(C) of the owned row, columns -1 .. nx
+//   fr: nx_max + 1 T       flux through x face f
+//   tb: (nx_max + 2 tw_max) x (zcmax + 1) A    RHS -> solve tile, line zs
+// ---------------------------------------------------------------------------
+struct XRowLayout {
+    size_t cr, mr, fr, tb, total;   // byte offsets and total size
+    int tbp;                        // pitch of the solve tile (elements)
+};
+
+CH_HD XRowLayout x_row_layout(int nx_max, int zcmax, int tw_max, int sT, int sA)
+{
+    XRowLayout L;
+    L.tbp = zcmax + 1;
+    L.cr = 0;
+    L.mr = al16(L.cr + (size_t)(nx_max + 6) * sT);
+    L.fr = al16(L.mr + (size_t)(nx_max + 2) * sT);
+    L.tb = al16(L.fr + (size_t)(nx_max + 1) * sT);
+    L.total = al16(L.tb + (size_t)(nx_max + 2 * tw_max) * L.tbp * sA);
+    return L;
+}
+
+template <typename T, typename A>
+struct XRowState {
+    T c[7];                   // C at z-3 .. z+3 of the owned cell
+    T mq[3];                  // psi'(C) at z-1, z, z+1
+    T yh[6];                  // C of this plane at rows y-3, y-2, y-1, y+1, y+2, y+3
+    T ul, vl, vh, wl, wh;     // u on the low x face, v on the low and high y faces,
+                              // w on the low and high z faces
+    T fzl;                    // flux through the low z face
+    T eold;                   // E of the previous substage at the plane whose RHS is next
+    T py, pz, plap, pb4;      // y and z flux differences, Laplacian of psi', sum of D4
+    T nc, nu, nvl, nvh, nwh, ne, nyh[6];   // the next plane's loads
+    int cxp, cxm;             // halo columns of the C and psi' rows fed by the
+                              // owned column (or the column itself)
+    LineState<A> ls;
+};
+
+template <typename T, typename A, class X, bool VCONST = false>
+CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, const PassArgs& pa,
+                              int task, const T* __restrict__ C, const T* __restrict__ U,
+                              const T* __restrict__ V, const T* __restrict__ W,
+                              T* __restrict__ E, T* __restrict__ Q, unsigned char* smem)
+{
+    const XZTask t = xz_task(bd, task);   // one row: t.rows == 1
+    const int nx = bd.n[0], ny = bd.n[1], nz = bd.n[2];
+    const int fx = bd.nf[0], fy = bd.nf[1], fz = bd.nf[2];
+    const int bcx = bd.bc[0];
+    const int k = pa.k, tw = bd.tw[k];
+    const int nth = ex.nth;
+    const XRowLayout L = x_row_layout(pa.nx_max, pa.zcmax, pa.tw_max, (int)sizeof(T),
+                                      (int)sizeof(A));
+    constexpr uint32_t sT = sizeof(T);
+    T* cr = reinterpret_cast<T*>(smem + L.cr) + 3;   // cr[x], -3 <= x < nx + 3
+    T* mr = reinterpret_cast<T*>(smem + L.mr) + 1;   // mr[x], -1 <= x < nx + 1
+    T* fr = reinterpret_cast<T*>(smem + L.fr);       // fr[f], 0 <= f <= nx
+    A* tb = reinterpret_cast<A*>(smem + L.tb);
+    const int tbp = L.tbp;
+    // bytes of a plane of C (E, q and w too), of u and of v
+    const uint32_t pbytes = (uint32_t)((int64_t)nx * ny * sT);
+    const uint32_t ubytes = (uint32_t)((int64_t)ny * fx * sT);
+    const uint32_t vbytes = (uint32_t)((int64_t)fy * nx * sT);
+    const PlaneRef<T> Cr(C + bd.c_off, (uint32_t)((int64_t)pbytes * nz));
+    const PlaneRef<T> Ur(U + bd.u_off, (uint32_t)((int64_t)ubytes * nz));
+    const PlaneRef<T> Vr(V + bd.v_off, (uint32_t)((int64_t)vbytes * nz));
+    const PlaneRef<T> Wr(W + bd.w_off, (uint32_t)((int64_t)pbytes * fz));
+    const PlaneRef<T> Er(E + bd.c_off, (uint32_t)((int64_t)pbytes * nz));
+    const PlaneRef<T> Qr(Q + bd.c_off, (uint32_t)((int64_t)pbytes * nz));
+    T epsw = T(bd.eps * (12.0 / 13.0));
+    T gdt = T(bd.gdt[k]), rdt = T(bd.rdt[k]), bdt = T(bd.bdt[k]);
+    T inv_h = T(bd.inv_h), lap_s = T(bd.inv_h2 * bd.inv_pe);
+    Cubic<T> mu = cubic<T>(bd.psi);
+    if constexpr (VCONST) {
+        in_vgpr(epsw);
+        in_vgpr(gdt);
+        in_vgpr(rdt);
+        in_vgpr(bdt);
+        in_vgpr(inv_h);
+        in_vgpr(lap_s);
+        in_vgpr(mu.c0);
+        in_vgpr(mu.c1);
+        in_vgpr(mu.c2);
+        in_vgpr(mu.c3);
+    }
+    const A a1 = A(bd.a1[k]), a2 = A(bd.a2[k]), ic = A(bd.ic[k]);
+    const int y = t.y0;
+    const int z0 = t.z0, nzc = t.nzc;
+    // byte offsets within a plane: the owned row of C (and v, w), of u, the
+    // row of the high y face (periodic wrap, or the wall face ny), the halo rows
+    const uint32_t yoff = (uint32_t)(y * nx) * sT;
+    const uint32_t yoffu = (uint32_t)(y * fx) * sT;
+    const uint32_t vtop = (uint32_t)((y + 1 == ny && bd.bc[1] == 0 ? 0 : y + 1) * nx) * sT;
+    uint32_t hoff[6];
+#pragma unroll
+    for (int hr = 0; hr < 6; ++hr)
+        hoff[hr] = (uint32_t)(map_idx(y + (hr < 3 ? hr - 3 : hr - 2), ny, bd.bc[1]) * nx) * sT;
+    auto cplane = [&](int z) { return (uint32_t)map_idx(z, nz, bd.bc[2]) * pbytes; };
+
+    // all global loads of plane z
+    auto fetch = [&](XRowState<T, A>& s, int xb, int z) {
+        const uint32_t zo = (uint32_t)z * pbytes;
+        s.nc = Cr(xb + yoff, cplane(z + 3));
+        s.nu = Ur(xb + yoffu, (uint32_t)z * ubytes);
+        s.nvl = Vr(xb + yoff, (uint32_t)z * vbytes);
+        s.nvh = Vr(xb, (uint32_t)z * vbytes + vtop);
+        s.nwh = Wr(xb + yoff, (uint32_t)((z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1) * pbytes);
+        s.ne = pa.e_mode != 0 ? Er(xb + yoff, zo) : T(0);
+#pragma unroll
+        for (int hr = 0; hr < 6; ++hr) s.nyh[hr] = Cr(xb, zo + hoff[hr]);
+    };
+    // RHS of plane zs of the owned cell into the solve tile (and E out)
+    auto rhs_plane = [&](XRowState<T, A>& s, int x, bool live, int zs) {
+        const T fhi = x + 1 < nx ? fr[x + 1] : fr[bcx == 0 ? 0 : nx];
+        const T adv = ((fhi - fr[x]) + s.py) + s.pz;
+        const T e = -adv * inv_h + s.plap * lap_s;
+        T rhs = gdt * e - bdt * s.pb4;
+        if (pa.e_mode != 0) rhs += rdt * s.eold;
+        if (live) {
+            if (pa.e_mode != 2) Er.store((uint32_t)x * sT + yoff, (uint32_t)(z0 + zs) * pbytes, e);
+            tb[(x + tw) * tbp + zs] = A(rhs);
+        }
+    };
+
+    // the thread's halo columns, the column below the first plane, its loads
+    ex.phase([&](int tid) {
+        XRowState<T, A>& s = st[ex.slot(tid)];
+        const int x = tid < nx ? tid : nx - 1;
+        const uint32_t xb = (uint32_t)x * sT;
+        s.cxp = x;
+        s.cxm = x;
+        for (int q = 0; q < 6; ++q) {
+            const int hc = q < 3 ? q - 3 : nx + q - 3;
+            if (map_idx(hc, nx, bcx) == x) {
+                s.cxp = hc;
+                if (q == 2 || q == 3) s.cxm = hc;
+            }
+        }
+#pragma unroll
+        for (int q = 1; q < 7; ++q) s.c[q] = Cr(xb + yoff, cplane(z0 - 4 + q));
+        s.mq[1] = mu(s.c[3]);   // psi'(C) at z0-2 .. z0 after the first shift
+        s.mq[2] = mu(s.c[4]);
+        s.wh = Wr(xb + yoff, (uint32_t)z0 * pbytes);   // becomes the low face of z0
+        wait_loads();
+        fetch(s, (int)xb, z0);
+    });
+
+    for (int zs = 0; zs < nzc; ++zs) {
+        const int z = z0 + zs;
+        // ---- this plane's loads in, the next plane's loads out, the RHS of
+        //      the plane below, the owned row into LDS
+        ex.phase([&](int tid) {
+            XRowState<T, A>& s = st[ex.slot(tid)];
+            const bool live = tid < nx;
+            const int x = live ? tid : nx - 1;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) s.c[q] = s.c[q + 1];
+            s.c[6] = s.nc;
+            s.ul = s.nu;
+            s.vl = s.nvl;
+            s.vh = s.nvh;
+            s.wl = s.wh;
+            s.wh = s.nwh;
+#pragma unroll
+            for (int hr = 0; hr < 6; ++hr) s.yh[hr] = s.nyh[hr];
+            const T e_here = s.ne;
+            if (zs + 1 < nzc) fetch(s, (int)((uint32_t)x * sT), z + 1);
+            if (zs > 0) rhs_plane(s, x, live, zs - 1);
+            s.eold = e_here;
+            s.mq[0] = s.mq[1];
+            s.mq[1] = s.mq[2];
+            s.mq[2] = mu(s.c[4]);
+            if (live) {
+                cr[x] = s.c[3];
+                cr[s.cxp] = s.c[3];
+                mr[x] = s.mq[1];
+                mr[s.cxm] = s.mq[1];
+            }
+        });
+        // ---- face fluxes, Laplacian of psi'(C), fourth differences
+        ex.phase([&](int tid) {
+            XRowState<T, A>& s = st[ex.slot(tid)];
+            const bool live = tid < nx;
+            const int x = live ? tid : nx - 1;
+            const T* row = cr + x;   // row[o] = C(x + o)
+            {
+                const T dX[5] = {row[-2] - row[-3], row[-1] - row[-2], row[0] - row[-1],
+                                 row[1] - row[0], row[2] - row[1]};
+                const T f = flux_weno_d<T>(s.ul, dX[0], dX[1], dX[2], dX[3], dX[4], row[-1],
+                                           row[0], epsw);
+                if (live) fr[x] = f;
+                s.pb4 = d4_d<T>(dX[1], dX[2], dX[3], dX[4]);
+            }
+            if (bcx != 0 && live && x == nx - 1) {
+                // the wall face nx (its normal velocity is zero by the interface's rule)
+                const T uw = Ur((uint32_t)(x + 1) * sT + yoffu, (uint32_t)z * ubytes);
+                fr[nx] = uw * face_weno<T>(uw, row[-2], row[-1], row[0], row[1], row[2], row[3],
+                                           epsw);
+            }
+            // y: the owned column from the halo registers
+            {
+                const T yc[7] = {s.yh[0], s.yh[1], s.yh[2], s.c[3], s.yh[3], s.yh[4], s.yh[5]};
+                T dY[6];
+#pragma unroll
+                for (int j = 0; j < 6; ++j) dY[j] = yc[j + 1] - yc[j];
+                const T fyl =
+                    flux_weno_d<T>(s.vl, dY[0], dY[1], dY[2], dY[3], dY[4], yc[2], yc[3], epsw);
+                const T fyh =
+                    flux_weno_d<T>(s.vh, dY[1], dY[2], dY[3], dY[4], dY[5], yc[3], yc[4], epsw);
+                s.py = fyh - fyl;
+                s.pb4 += d4_d<T>(dY[1], dY[2], dY[3], dY[4]);
+            }
+            // z: planes z-1 .. z+3; the high face (the low one carries over)
+            {
+                const T* c = s.c;
+                T dZ[5];
+#pragma unroll
+                for (int j = 0; j < 5; ++j) dZ[j] = c[j + 2] - c[j + 1];
+                if (zs == 0)   // the low face of the task's first plane, in the same form
+                               // as every face after it
+                    s.fzl = flux_weno_d<T>(s.wl, c[1] - c[0], c[2] - c[1], c[3] - c[2],
+                                           c[4] - c[3], c[5] - c[4], c[2], c[3], epsw);
+                const T fzh =
+                    flux_weno_d<T>(s.wh, dZ[0], dZ[1], dZ[2], dZ[3], dZ[4], c[3], c[4], epsw);
+                s.pz = fzh - s.fzl;
+                s.fzl = fzh;
+                s.pb4 += d4_d<T>(dZ[0], dZ[1], dZ[2], dZ[3]);
+            }
+            s.plap = ((mr[x + 1] + mr[x - 1]) + (mu(s.yh[3]) + mu(s.yh[2])))
+                   + (s.mq[2] + s.mq[0]) - T(6) * s.mq[1];
+        });
+    }
+    // ---- RHS of the last plane
+    ex.phase([&](int tid) {
+        const bool live = tid < nx;
+        rhs_plane(st[ex.slot(tid)], live ? tid : nx - 1, live, nzc - 1);
+    });
+    // ---- halos of the solve tile (periodic or reflected continuation)
+    ex.phase([&](int tid) {
+        const int span = 2 * tw;
+        for (int j = tid; j < nzc * span; j += nth) {
+            const int ln = j / span, q = j - ln * span;
+            const int pp = q < tw ? q - tw : nx + q - tw;
+            tb[(pp + tw) * tbp + ln] = tb[(map_idx(pp, nx, bcx) + tw) * tbp + ln];
+        }
+    });
+    // ---- x solve of the task's lines
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nzc, nx, tw, X_CHAINS);
+        line_f1<A>(ch, tb, tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nzc, nx, tw, X_CHAINS);
+        line_f2<A>(ch, tb, tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nzc, nx, tw, X_CHAINS);
+        line_b1<A>(ch, tb, tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nzc, nx, tw, X_CHAINS);
+        line_b2<A>(ch, tb, tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+    });
+    // ---- q out, plane by plane
+    ex.phase([&](int tid) {
+        if (tid >= nx) return;
+        const uint32_t o = (uint32_t)tid * sT + yoff;
+        for (int zs = 0; zs < nzc; ++zs)
+            Qr.store(o, (uint32_t)(z0 + zs) * pbytes, T(tb[(tid + tw) * tbp + zs]));
     });
 }
 

@@ -99,6 +99,7 @@ struct Plan {
     double dt = NAN;
     bool acc64 = true;
     bool e25 = false;   // explicit 25-point scheme: no line solves, one row per x task
+    bool row1 = false;  // the x pass runs the one-row program
     int tw_max = 0;
     int x_rows = 0, x_threads = 256, zc = 1, mi = 1, lanes = 32, yz_threads = 256, seg_cap = 0;
     int ntask[3] = {0, 0, 0};
@@ -143,6 +144,7 @@ inline ch_status plan_init(Plan& P, int nbox, const ch_grid* g, const double* Cn
         return P.fail(CH_EINVAL, "unknown solve_fp64 mode");
     if (!(o.dt_hint >= 0.0) || !std::isfinite(o.dt_hint))
         return P.fail(CH_EINVAL, "dt_hint must be >= 0 and finite");
+    if (o.x_general != 0 && o.x_general != 1) return P.fail(CH_EINVAL, "x_general must be 0 or 1");
     if (o.x_rows < 0 || o.x_rows > 64 || o.seg_len < 0 || o.waves_yz < 0 || o.waves_yz > 8 ||
         o.z_chunk < 0)
         return P.fail(CH_EINVAL, "launch options out of range");
@@ -274,7 +276,19 @@ inline ch_status plan_dt(Plan& P, double dt)
     // ---- x pass: rows per task and planes per task
     // chunks per x line (fixed by the line: see line_chunk_len)
     auto nch_x = [](int n) { return std::max(1, std::min(n / 16, chd::X_CHAINS)); };
+    // the one-row x program: every box's columns feed at most one halo
+    // column each (nx >= 6), and every field of every box is under 4 GiB
+    // (32-bit byte offsets from one buffer resource per field)
+    bool row_ok = !P.e25 && P.opt.x_general == 0 && P.mi == 1;
+    for (int b = 0; b < P.nbox && row_ok; ++b) {
+        const chd::BoxDesc& d = P.boxes[b];
+        const double n0 = d.n[0], n1 = d.n[1], n2 = d.n[2], s = (double)sT;
+        row_ok = d.n[0] >= 6 && n0 * n1 * n2 * s < 4294967296.0 &&
+                 (double)d.nf[0] * n1 * n2 * s < 4294967296.0 &&
+                 n0 * d.nf[1] * n2 * s < 4294967296.0 && n0 * n1 * d.nf[2] * s < 4294967296.0;
+    }
     auto xlds = [&](int R, int zc) {
+        if (R == 1 && row_ok) return chd::x_row_layout(nxm, zc, P.tw_max, (int)sT, (int)sA).total;
         return chd::x_layout(nxm, R, zc, P.tw_max, (int)sT, (int)sA, P.e25).total;
     };
     const int xwaves = sT == 4 ? X_WAVES_F32 : X_WAVES_F64;
@@ -295,6 +309,7 @@ inline ch_status plan_dt(Plan& P, double dt)
     }
     if (R * nxm > xcap) return P.fail(CH_EINVAL, "x_rows too large for the x extent");
     P.x_rows = R;
+    P.row1 = row_ok && R == 1;
     P.x_threads = ((R * nxm + P.mi - 1) / P.mi + 63) / 64 * 64;
     if (P.x_threads > X_MAX_THREADS) return P.fail(CH_EINVAL, "x_rows too large for the x extent");
     // planes per task: every line of a task needs its chunks' threads

@@ -7,12 +7,13 @@
 // planned size, it checks the kernels' indexing without a GPU.
 //
 // usage: emu PARAMS IN_DIR OUT_DIR
-//   PARAMS: "nbox prec kappa eps solve x_rows seg_len waves z_chunk dt nsteps mode"
+//   PARAMS: "nbox prec kappa eps solve x_rows seg_len waves z_chunk dt nsteps mode
+//           x_general"
 //           then per box "nx ny nz h Cn Pe bcx bcy bcz"; mode 0 is the
 //           factorised implicit scheme, 1 the explicit 25-point scheme
 //   IN_DIR/{C,u,v,w}.bin: packed float64 arrays (the library's layout)
 //   OUT_DIR/C.bin: packed float64 result; OUT_DIR/mass.txt: per-box mass;
-//   OUT_DIR/plan.txt: x_rows seg_cap chains tw_max acc64 ntask0..2 lds0..2
+//   OUT_DIR/plan.txt: x_rows seg_cap chains tw_max acc64 ntask0..2 lds0..2 z_chunk row1
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -61,6 +62,23 @@ static void run_x(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T* v
     }
 }
 
+// the one-row x-pass program
+template <typename T, typename A>
+static void run_xrow(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T* v, const T* w)
+{
+    const chd::BoxDesc* boxes = P.boxes.data();
+    const chd::PassArgs pa = chp::pass_args(P, k, 0);
+    chd::CpuExec ex{P.x_threads};
+    std::vector<chd::XRowState<T, A>> st(ex.nth);
+    for (int task = 0; task < P.ntask[0]; ++task) {
+        unsigned char* lds = (unsigned char*)malloc(P.lds[0]);
+        memset(lds, 0xff, P.lds[0]);
+        const int b = chd::find_box(boxes, P.nbox, chd::PASS_X, task);
+        chd::pass_x_row_program<T, A>(ex, st.data(), boxes[b], pa, task, C, u, v, w, E, qa, lds);
+        free(lds);
+    }
+}
+
 template <typename T, typename A>
 static void run(chp::Plan& P, T* C, T* E, T* qa, T* qb, const T* u, const T* v, const T* w,
                 int nsteps)
@@ -69,7 +87,8 @@ static void run(chp::Plan& P, T* C, T* E, T* qa, T* qb, const T* u, const T* v, 
     for (int s = 0; s < nsteps; ++s)
         for (int k = 0; k < 3; ++k) {
             // pass x
-            if (P.mi == 1) run_x<T, A, 1>(P, k, C, E, qa, u, v, w);
+            if (P.row1) run_xrow<T, A>(P, k, C, E, qa, u, v, w);
+            else if (P.mi == 1) run_x<T, A, 1>(P, k, C, E, qa, u, v, w);
             else run_x<T, A, 2>(P, k, C, E, qa, u, v, w);
             // passes y, z
             for (int pass = 1; pass <= 2; ++pass) {
@@ -159,9 +178,9 @@ static int go(chp::Plan& P, const std::string& in, const std::string& out, int n
     for (double x : m) fprintf(f, "%.17g\n", x);
     fclose(f);
     f = fopen((out + "/plan.txt").c_str(), "w");
-    fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu %d\n", P.x_rows, P.seg_cap, P.yz_threads,
+    fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu %d %d\n", P.x_rows, P.seg_cap, P.yz_threads,
             P.tw_max, P.acc64 ? 1 : 0, P.ntask[0], P.ntask[1], P.ntask[2], P.lds[0], P.lds[1],
-            P.lds[2], P.zc);
+            P.lds[2], P.zc, P.row1 ? 1 : 0);
     fclose(f);
     free(C); free(E); free(qa); free(qb); free(u); free(v); free(w);
     return 0;
@@ -175,10 +194,10 @@ int main(int argc, char** argv)
     }
     FILE* f = fopen(argv[1], "r");
     if (!f) return 2;
-    int nbox, prec, solve, x_rows, seg, waves, zchunk, nsteps, mode;
+    int nbox, prec, solve, x_rows, seg, waves, zchunk, nsteps, mode, xgen;
     double kappa, eps, dt;
-    if (fscanf(f, "%d %d %lf %lf %d %d %d %d %d %lf %d %d", &nbox, &prec, &kappa, &eps, &solve,
-               &x_rows, &seg, &waves, &zchunk, &dt, &nsteps, &mode) != 12)
+    if (fscanf(f, "%d %d %lf %lf %d %d %d %d %d %lf %d %d %d", &nbox, &prec, &kappa, &eps, &solve,
+               &x_rows, &seg, &waves, &zchunk, &dt, &nsteps, &mode, &xgen) != 13)
         return 2;
     std::vector<ch_grid> g(nbox);
     std::vector<double> Cn(nbox), Pe(nbox);
@@ -203,6 +222,7 @@ int main(int argc, char** argv)
     o.seg_len = seg;
     o.waves_yz = waves;
     o.z_chunk = zchunk;
+    o.x_general = xgen;
     chp::Plan P;
     P.e25 = mode == 1;
     if (chp::plan_init(P, nbox, g.data(), Cn.data(), Pe.data(), nullptr, bc.data(), &o) != CH_OK ||

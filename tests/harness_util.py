@@ -27,13 +27,13 @@ def pack(arrays):
 
 
 def run_emu(boxes, dt, nsteps, prec=0, kappa=4.0, eps=1e-6, solve=0, x_rows=0, seg=0,
-            waves=0, z_chunk=0, mode=0):
+            waves=0, z_chunk=0, mode=0, x_general=0):
     """boxes: list of dicts with C, u, v, w, h, Cn, Pe, bc.  Returns (list of
     C arrays, masses, plan dict)."""
     with tempfile.TemporaryDirectory() as d:
         with open(os.path.join(d, "params.txt"), "w") as f:
             f.write(f"{len(boxes)} {prec} {kappa!r} {eps!r} {solve} {x_rows} {seg} {waves} "
-                    f"{z_chunk} {dt!r} {nsteps} {mode}\n")
+                    f"{z_chunk} {dt!r} {nsteps} {mode} {x_general}\n")
             for b in boxes:
                 nz, ny, nx = b["C"].shape
                 bc = b.get("bc", (0, 0, 0))
@@ -52,7 +52,7 @@ def run_emu(boxes, dt, nsteps, prec=0, kappa=4.0, eps=1e-6, solve=0, x_rows=0, s
         p = open(os.path.join(d, "plan.txt")).read().split()
         plan = dict(x_rows=int(p[0]), seg=int(p[1]), yz_threads=int(p[2]), tw_max=int(p[3]),
                     acc64=int(p[4]), ntask=[int(x) for x in p[5:8]],
-                    lds=[int(x) for x in p[8:11]], z_chunk=int(p[11]))
+                    lds=[int(x) for x in p[8:11]], z_chunk=int(p[11]), row1=int(p[12]))
     out, o = [], 0
     for b in boxes:
         n = b["C"].size

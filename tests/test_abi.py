@@ -43,8 +43,8 @@ def test_binding_covers_every_declared_symbol():
     assert sorted(ch.SIGNATURES) == declared()
     # the ctypes structures match the C layout
     assert ctypes.sizeof(ch.Grid) == 32 and ctypes.sizeof(ch.BC) == 12
-    assert ch.Opts.kappa.offset == 8 and ch.Opts.dt_hint.offset == 48
-    assert ctypes.sizeof(ch.Opts) == 56
+    assert ch.Opts.kappa.offset == 8 and ch.Opts.x_general.offset == 48
+    assert ch.Opts.dt_hint.offset == 56 and ctypes.sizeof(ch.Opts) == 64
 
 
 def test_binding_fails_loudly_without_the_library(monkeypatch):

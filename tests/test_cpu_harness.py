@@ -176,3 +176,58 @@ def test_explicit25_matches_oracle(shape, bc, zc):
     assert abs(masses[0] - oracle.mass(ref, b["h"])) < 1e-12 * abs(masses[0])
     out32, _, _ = run_emu([b], dt, 2, prec=1, mode=1, z_chunk=zc)
     assert _rel(out32[0], ref) < 2e-6
+
+
+@pytest.mark.parametrize("shape,bc,zc", [
+    ((12, 10, 16), (0, 0, 0), 5),      # 16 of 64 threads live, ragged march
+    ((9, 11, 70), (0, 0, 1), 4),       # two waves, the second partly idle
+    ((10, 12, 17), (1, 0, 0), 3),      # x walls: the wall face, reflected halo columns
+    ((9, 13, 16), (0, 1, 0), 4),       # y walls: reflected halo rows, the wall face ny
+    ((11, 10, 9), (1, 1, 1), 2),
+    ((8, 1, 24), (0, 0, 0), 3),        # degenerate y
+    ((1, 9, 20), (0, 1, 0), 1),        # degenerate z
+    ((14, 8, 8), (1, 1, 0), 7),        # the shortest x line
+])
+def test_one_row_program_equals_the_general_one(shape, bc, zc):
+    """One x-line per task: the one-row x program (y stencil in registers)
+    and the general one give the same bits, and both the oracle's step."""
+    b = _box(shape, bc=bc, seed=23, amp=2.0, drops=min(shape) > 4)
+    dt = 2e-4
+    ref = _oracle(b, dt, 2)
+    for prec, solve, tol in ((0, 0, 1e-12), (1, 0, 2e-6), (1, 1, 2e-6)):
+        out = {}
+        for xg in (0, 1):
+            o, m, plan = run_emu([b], dt, 2, prec=prec, solve=solve, x_rows=1, z_chunk=zc,
+                                 x_general=xg)
+            assert plan["row1"] == (1 - xg)
+            out[xg] = (o[0], m[0])
+        assert np.array_equal(out[0][0], out[1][0])
+        assert out[0][1] == out[1][1]
+        assert _rel(out[0][0], ref) < tol
+
+
+def test_one_row_program_in_a_batch():
+    # boxes of different widths in one launch: the narrow ones leave threads idle
+    boxes = [_box((16, 12, 40), seed=31), _box((10, 9, 8), seed=32, bc=(0, 0, 0)),
+             _box((12, 14, 33), seed=33)]
+    dt = 3e-4
+    got, masses, plan = run_emu(boxes, dt, 2, x_rows=1)
+    assert plan["row1"] == 1
+    gen, _, _ = run_emu(boxes, dt, 2, x_rows=1, x_general=1)
+    for a, g, b in zip(got, gen, boxes):
+        assert np.array_equal(a, g)
+        assert _rel(a, _oracle(b, dt, 2)) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_launch_plan_does_not_change_the_bits(prec):
+    """Every face flux is formed from the same differences whatever the tile:
+    rows per task, planes per task, segment length and the x program leave
+    the result bit for bit the same."""
+    b = _box((18, 13, 24), bc=(0, 0, 1), seed=41, amp=2.0)
+    dt = 2e-4
+    ref, _, _ = run_emu([b], dt, 2, prec=prec, x_rows=1, z_chunk=18)
+    for opts in (dict(x_rows=1, z_chunk=4), dict(x_rows=1, z_chunk=5, x_general=1),
+                 dict(x_rows=3, z_chunk=7, seg=5), dict(x_rows=2, z_chunk=1, waves=2)):
+        got, _, _ = run_emu([b], dt, 2, prec=prec, **opts)
+        assert np.array_equal(got[0], ref[0]), opts
