@@ -30,6 +30,7 @@
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #if defined(__HIPCC__)
 #include <hip/hip_runtime.h>
@@ -1428,6 +1429,40 @@ constexpr int line_lanes()
     return 128 / (int)sizeof(A);
 }
 
+// The line passes' 16-byte fast path (below) can be compiled out, so that the
+// host harness can hold it to the element-wise path.
+#ifndef CH_LINE_VEC
+#define CH_LINE_VEC 1
+#endif
+
+// Rows of a y/z tile are filled 8 at a time (see load16_to_lds), so the tile
+// is allocated in whole blocks of 8 rows.
+CH_HD int line_tile_rows(int npos) { return (npos + 7) & ~7; }
+
+// 16 bytes of global memory straight into LDS, without registers: on the GPU
+// the wave's 64 lanes write 64 consecutive 16-byte pieces from `wave_base`
+// (lane L at wave_base + 16 L, which must be the same for the whole wave),
+// so one instruction fills eight 128-byte tile rows.  The host runs the same
+// per lane.  Waited for by wait_loads().
+template <typename T>
+CH_HD void load16_to_lds(const T* g, unsigned char* wave_base, int lane)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    (void)lane;
+    __builtin_amdgcn_global_load_lds(
+        g, (__attribute__((address_space(3))) void*)(wave_base), 16, 0, 0);
+#else
+    memcpy(wave_base + 16 * lane, g, 16);
+#endif
+}
+
+// 16 bytes of T as one vector (the aligned loads and stores of the line
+// passes' fast path)
+template <typename T>
+struct Vec16 {
+    typedef T type __attribute__((vector_size(16)));
+};
+
 template <typename T, typename A, class X>
 CH_HD void pass_line_program(X& ex, LineState<A>* st, const BoxDesc& bd, const PassArgs& pa,
                              int pass, int task, const T* __restrict__ Qin,
@@ -1446,9 +1481,33 @@ CH_HD void pass_line_program(X& ex, LineState<A>* st, const BoxDesc& bd, const P
     const int qstep = nth / Lw;
     const int span = (LB - 1) * qstep;
     const int64_t dstep = (int64_t)qstep * t.stride;
+    // Fast path: the field holds the solve's precision, the task's 32 (FP32)
+    // or 16 (FP64) columns are all in the box, and rows start on 16 bytes:
+    // rows go to LDS by 16-byte direct loads and come back as 16-byte vectors.
+    constexpr int EPV = 16 / (int)sizeof(T);   // elements per 16 bytes
+    const bool vec = CH_LINE_VEC && sizeof(T) == sizeof(A) && nlive == Lw && nth % 64 == 0 &&
+                     ((t.base * (int64_t)sizeof(T)) & 15) == 0 &&
+                     ((t.stride * (int64_t)sizeof(T)) & 15) == 0;
     // stage the segment with its halos; tile row q holds line position
-    // s0 + q - tw.  A batch inside [0, n) walks one column pointer; a batch
-    // that reaches a halo outside the line maps every position.
+    // s0 + q - tw.
+    if (vec) {
+        // wave w fills the blocks of 8 rows w, w + waves, ...; lane L takes
+        // row L / 8 of the block and its 16-byte piece L % 8.  The padding
+        // rows of the last block repeat the last position.
+        ex.phase([&](int tid) {
+            const int wave = tid / 64, lane = tid % 64, nwave = nth / 64;
+            const T* colb = Qin + t.base + (lane % 8) * EPV;
+            const int nblk = line_tile_rows(npos) / 8;
+            for (int b = wave; b < nblk; b += nwave) {
+                int q = b * 8 + lane / 8;
+                if (q >= npos) q = npos - 1;
+                const int pos = map_idx(t.s0 + q - tw, t.n, t.bc);
+                load16_to_lds<T>(colb + (int64_t)pos * t.stride,
+                                 reinterpret_cast<unsigned char*>(tile + b * 8 * Lw), lane);
+            }
+            wait_loads();
+        });
+    } else
     ex.phase([&](int tid) {
         const int l = tid % Lw;
         const bool on = l < nlive;
@@ -1497,6 +1556,38 @@ CH_HD void pass_line_program(X& ex, LineState<A>* st, const BoxDesc& bd, const P
     });
     // write the segment back (pass Z: C += dC); only the last batch of a
     // thread can reach past the segment
+    if (vec) {
+        // lane L of a wave takes row L / 8 of a block of 8 and its 16-byte
+        // piece L % 8; four blocks per round, their loads of C in flight
+        // together
+        typedef typename Vec16<T>::type V;
+        ex.phase([&](int tid) {
+            const int wave = tid / 64, lane = tid % 64, nwave = nth / 64;
+            const int r = lane / 8, e0 = (lane % 8) * EPV;
+            const int nblk = line_tile_rows(t.len) / 8;
+            T* colb = Qout + t.base + e0;
+            for (int b0 = wave; b0 < nblk; b0 += 4 * nwave) {
+                V c[4];
+                if (pass == PASS_Z) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int q = (b0 + j * nwave) * 8 + r;
+                        if (q < t.len)
+                            c[j] = *reinterpret_cast<const V*>(colb + (int64_t)(t.s0 + q) * t.stride);
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int q = (b0 + j * nwave) * 8 + r;
+                    if (q >= t.len) continue;
+                    V d = *reinterpret_cast<const V*>(tile + (q + tw) * Lw + e0);
+                    if (pass == PASS_Z) d = c[j] + d;
+                    *reinterpret_cast<V*>(colb + (int64_t)(t.s0 + q) * t.stride) = d;
+                }
+            }
+        });
+        return;
+    }
     ex.phase([&](int tid) {
         const int l = tid % Lw;
         if (l >= nlive) return;

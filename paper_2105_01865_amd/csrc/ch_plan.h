@@ -370,8 +370,8 @@ inline ch_status plan_dt(Plan& P, double dt)
     }
     for (int p = 0; p < 3; ++p) P.ntask[p] = (int)t0[p];
     P.lds[0] = xlds(R, zc);
-    P.lds[1] = (size_t)(P.seg_max[0] + 2 * P.tw_max) * P.lanes * sA;
-    P.lds[2] = (size_t)(P.seg_max[1] + 2 * P.tw_max) * P.lanes * sA;
+    P.lds[1] = (size_t)chd::line_tile_rows(P.seg_max[0] + 2 * P.tw_max) * P.lanes * sA;
+    P.lds[2] = (size_t)chd::line_tile_rows(P.seg_max[1] + 2 * P.tw_max) * P.lanes * sA;
     for (int p = 1; p < 3; ++p)
         if (P.lds[p] > LDS_HARD) return P.fail(CH_EUNSUPPORTED, "line segment too long for LDS");
     P.dt = dt;

@@ -7,19 +7,20 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "tests", "cpu_harness", "emu.cpp")
-_EXE = None
+_EXE = {}
 
 
-def emu_exe():
-    global _EXE
-    if _EXE is None:
+def emu_exe(line_vec=True):
+    """The harness binary; line_vec=False compiles out the line passes'
+    16-byte fast path."""
+    if line_vec not in _EXE:
         d = tempfile.mkdtemp(prefix="ch_emu_")
         exe = os.path.join(d, "emu")
         subprocess.run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
                         "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
-                        "-o", exe, SRC], check=True)
-        _EXE = exe
-    return _EXE
+                        f"-DCH_LINE_VEC={1 if line_vec else 0}", "-o", exe, SRC], check=True)
+        _EXE[line_vec] = exe
+    return _EXE[line_vec]
 
 
 def pack(arrays):
@@ -27,7 +28,7 @@ def pack(arrays):
 
 
 def run_emu(boxes, dt, nsteps, prec=0, kappa=4.0, eps=1e-6, solve=0, x_rows=0, seg=0,
-            waves=0, z_chunk=0, mode=0, x_general=0):
+            waves=0, z_chunk=0, mode=0, x_general=0, line_vec=True):
     """boxes: list of dicts with C, u, v, w, h, Cn, Pe, bc.  Returns (list of
     C arrays, masses, plan dict)."""
     with tempfile.TemporaryDirectory() as d:
@@ -43,7 +44,7 @@ def run_emu(boxes, dt, nsteps, prec=0, kappa=4.0, eps=1e-6, solve=0, x_rows=0, s
             pack([b[name] for b in boxes]).tofile(os.path.join(d, name + ".bin"))
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                    UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
-        r = subprocess.run([emu_exe(), os.path.join(d, "params.txt"), d, d], env=env,
+        r = subprocess.run([emu_exe(line_vec), os.path.join(d, "params.txt"), d, d], env=env,
                            capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"emu failed ({r.returncode}):\n{r.stderr[-4000:]}")

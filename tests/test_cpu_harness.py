@@ -231,3 +231,20 @@ def test_launch_plan_does_not_change_the_bits(prec):
                  dict(x_rows=3, z_chunk=7, seg=5), dict(x_rows=2, z_chunk=1, waves=2)):
         got, _, _ = run_emu([b], dt, 2, prec=prec, **opts)
         assert np.array_equal(got[0], ref[0]), opts
+
+
+@pytest.mark.parametrize("prec,solve", [(0, 0), (1, 0), (1, 1)])
+@pytest.mark.parametrize("shape,bc,opts", [
+    ((20, 24, 64), (0, 0, 0), dict(seg=7)),          # full 32-column tasks, short segments
+    ((19, 17, 96), (0, 1, 1), dict(seg=11, waves=2)),  # walls in y and z, 2 waves per task
+    ((12, 9, 40), (0, 0, 1), {}),                     # 32 + 8 columns: one full task, one partial
+])
+def test_line_fast_path_equals_the_elementwise_path(shape, bc, opts, prec, solve):
+    """The y/z passes' 16-byte path (rows straight into LDS, vector
+    write-back) against the element-wise path, bit for bit, and the oracle."""
+    b = _box(shape, bc=bc, seed=51, amp=2.0)
+    dt = 2e-4
+    fast, mf, _ = run_emu([b], dt, 2, prec=prec, solve=solve, **opts)
+    slow, ms, _ = run_emu([b], dt, 2, prec=prec, solve=solve, line_vec=False, **opts)
+    assert np.array_equal(fast[0], slow[0]) and mf == ms
+    assert _rel(fast[0], _oracle(b, dt, 2)) < (1e-12 if prec == 0 else 2e-6)
