@@ -1091,40 +1091,47 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
 }
 
 // ---------------------------------------------------------------------------
-// Pass X with one row per task (the same arithmetic as pass_x_program, which
-// the plan takes instead whenever a task holds one x-line and the fields
-// fit the addressing below).
+// Pass X with one cell per thread and the y stencil in registers (the same
+// arithmetic as pass_x_program, which the plan takes instead where this one
+// does not apply: see plan_dt).
 //
-// With one row per work-group the y-direction stencil of a cell is its own
-// column: the six halo rows of C go straight into the thread's registers,
-// and the y differences, both y face fluxes and the y neighbours of psi'(C)
-// are formed there.  LDS carries only the owned row (C and psi'(C) with
-// their x halos), the x face fluxes and the solve tile.  Each field of the
-// box is one buffer resource with 32-bit byte offsets (every field of every
-// box under 4 GiB): the plane goes into the scalar offset, the cell into the
-// lane offset, so no address is formed per plane and lane.  Threads past the
-// row's end read the last cell and store nothing.
+// A task is `rows` complete x-lines (rows = 1 whenever a line fills a
+// work-group; narrow boxes of an ensemble take several) over nzc planes.
+// Every thread owns one cell and marches it up through the planes.  The
+// y-direction stencil of a cell is its own column, so the six halo rows of C
+// go straight into the thread's registers, and the y differences, both y
+// face fluxes and the y neighbours of psi'(C) are formed there: no row
+// exchanges y data through LDS.  LDS carries the owned rows (C and psi'(C)
+// with their x halos), the x face fluxes and the solve tile.  Each field of
+// the box is one buffer resource with 32-bit byte offsets (every field of
+// every box under 4 GiB): the plane goes into the scalar offset.  With one
+// row per task (MR false) every row offset is uniform and goes there too;
+// with several (MR true) the row offsets are per thread.  Threads past the
+// task's cells read its last cell and store nothing.
 //
-// LDS (launch-wide):
-//   cr: nx_max + 6 T       C of the owned row, columns -3 .. nx+2
-//   mr: nx_max + 2 T       psi'(C) of the owned row, columns -1 .. nx
-//   fr: nx_max + 1 T       flux through x face f
-//   tb: (nx_max + 2 tw_max) x (zcmax + 1) A    RHS -> solve tile, line zs
+// LDS of a box (launch size: the largest over boxes):
+//   cr: rows x (nx + 6) T      C of the owned rows, columns -3 .. nx+2
+//   mr: rows x (nx + 2) T      psi'(C) of the owned rows, columns -1 .. nx
+//   fr: rows x (nx + 1) T      flux through x face f of each row
+//   tb: (nx + 2 tw_max) x (rows zc + 1) A    RHS -> solve tile, line zs rows + r
 // ---------------------------------------------------------------------------
 struct XRowLayout {
     size_t cr, mr, fr, tb, total;   // byte offsets and total size
-    int tbp;                        // pitch of the solve tile (elements)
+    int crp, mrp, frp, tbp;         // pitches (elements)
 };
 
-CH_HD XRowLayout x_row_layout(int nx_max, int zcmax, int tw_max, int sT, int sA)
+CH_HD XRowLayout x_row_layout(int nx, int rows, int zc, int tw_max, int sT, int sA)
 {
     XRowLayout L;
-    L.tbp = zcmax + 1;
+    L.crp = nx + 6;
+    L.mrp = nx + 2;
+    L.frp = nx + 1;
+    L.tbp = rows * zc + 1;
     L.cr = 0;
-    L.mr = al16(L.cr + (size_t)(nx_max + 6) * sT);
-    L.fr = al16(L.mr + (size_t)(nx_max + 2) * sT);
-    L.tb = al16(L.fr + (size_t)(nx_max + 1) * sT);
-    L.total = al16(L.tb + (size_t)(nx_max + 2 * tw_max) * L.tbp * sA);
+    L.mr = al16(L.cr + (size_t)rows * L.crp * sT);
+    L.fr = al16(L.mr + (size_t)rows * L.mrp * sT);
+    L.tb = al16(L.fr + (size_t)rows * L.frp * sT);
+    L.total = al16(L.tb + (size_t)(nx + 2 * tw_max) * L.tbp * sA);
     return L;
 }
 
@@ -1141,27 +1148,33 @@ struct XRowState {
     T nc, nu, nvl, nvh, nwh, ne, nyh[6];   // the next plane's loads
     int cxp, cxm;             // halo columns of the C and psi' rows fed by the
                               // owned column (or the column itself)
+    int r, x;                 // the owned cell (several rows per task)
+    bool live;
+    uint32_t ro, rou, rvt;    // byte offsets in a plane of its row of C (v, w, E, q),
+                              // of u, and of v's high face
+    uint32_t ho[6];           // and of its six halo rows
     LineState<A> ls;
 };
 
-template <typename T, typename A, class X, bool VCONST = false>
+template <typename T, typename A, bool MR, class X, bool VCONST = false>
 CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, const PassArgs& pa,
                               int task, const T* __restrict__ C, const T* __restrict__ U,
                               const T* __restrict__ V, const T* __restrict__ W,
                               T* __restrict__ E, T* __restrict__ Q, unsigned char* smem)
 {
-    const XZTask t = xz_task(bd, task);   // one row: t.rows == 1
+    const XZTask t = xz_task(bd, task);
     const int nx = bd.n[0], ny = bd.n[1], nz = bd.n[2];
     const int fx = bd.nf[0], fy = bd.nf[1], fz = bd.nf[2];
     const int bcx = bd.bc[0];
     const int k = pa.k, tw = bd.tw[k];
     const int nth = ex.nth;
-    const XRowLayout L = x_row_layout(pa.nx_max, pa.zcmax, pa.tw_max, (int)sizeof(T),
+    const int rows = MR ? t.rows : 1;
+    const XRowLayout L = x_row_layout(nx, MR ? bd.x_rows : 1, bd.zc, pa.tw_max, (int)sizeof(T),
                                       (int)sizeof(A));
     constexpr uint32_t sT = sizeof(T);
-    T* cr = reinterpret_cast<T*>(smem + L.cr) + 3;   // cr[x], -3 <= x < nx + 3
-    T* mr = reinterpret_cast<T*>(smem + L.mr) + 1;   // mr[x], -1 <= x < nx + 1
-    T* fr = reinterpret_cast<T*>(smem + L.fr);       // fr[f], 0 <= f <= nx
+    T* crb = reinterpret_cast<T*>(smem + L.cr) + 3;   // row r: crb[r crp + x], -3 <= x < nx + 3
+    T* mrb = reinterpret_cast<T*>(smem + L.mr) + 1;   // row r: mrb[r mrp + x], -1 <= x < nx + 1
+    T* frb = reinterpret_cast<T*>(smem + L.fr);       // row r: frb[r frp + f], 0 <= f <= nx
     A* tb = reinterpret_cast<A*>(smem + L.tb);
     const int tbp = L.tbp;
     // bytes of a plane of C (E, q and w too), of u and of v
@@ -1191,49 +1204,97 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
         in_vgpr(mu.c3);
     }
     const A a1 = A(bd.a1[k]), a2 = A(bd.a2[k]), ic = A(bd.ic[k]);
-    const int y = t.y0;
     const int z0 = t.z0, nzc = t.nzc;
-    // byte offsets within a plane: the owned row of C (and v, w), of u, the
-    // row of the high y face (periodic wrap, or the wall face ny), the halo rows
-    const uint32_t yoff = (uint32_t)(y * nx) * sT;
-    const uint32_t yoffu = (uint32_t)(y * fx) * sT;
-    const uint32_t vtop = (uint32_t)((y + 1 == ny && bd.bc[1] == 0 ? 0 : y + 1) * nx) * sT;
+    // byte offsets within a plane of row y: of C (and v, w), of u, of the
+    // row of v's high face (periodic wrap, or the wall face ny), and of
+    // halo row hr (y-3, y-2, y-1, y+1, y+2, y+3)
+    auto row_off = [&](int y) { return (uint32_t)(y * nx) * sT; };
+    auto row_offu = [&](int y) { return (uint32_t)(y * fx) * sT; };
+    auto row_vtop = [&](int y) {
+        return (uint32_t)((y + 1 == ny && bd.bc[1] == 0 ? 0 : y + 1) * nx) * sT;
+    };
+    auto halo_off = [&](int y, int hr) {
+        return (uint32_t)(map_idx(y + (hr < 3 ? hr - 3 : hr - 2), ny, bd.bc[1]) * nx) * sT;
+    };
+    // one row per task: these are uniform
+    const uint32_t yoff = row_off(t.y0), yoffu = row_offu(t.y0), vtop = row_vtop(t.y0);
     uint32_t hoff[6];
 #pragma unroll
-    for (int hr = 0; hr < 6; ++hr)
-        hoff[hr] = (uint32_t)(map_idx(y + (hr < 3 ? hr - 3 : hr - 2), ny, bd.bc[1]) * nx) * sT;
+    for (int hr = 0; hr < 6; ++hr) hoff[hr] = halo_off(t.y0, hr);
     auto cplane = [&](int z) { return (uint32_t)map_idx(z, nz, bd.bc[2]) * pbytes; };
+    // the owned cell of thread tid: row, column, and whether it is a cell
+    auto cell = [&](const XRowState<T, A>& s, int tid, int* r, int* x) {
+        if constexpr (MR) {
+            *r = s.r;
+            *x = s.x;
+            return s.live;
+        } else {
+            (void)s;
+            *r = 0;
+            *x = tid < nx ? tid : nx - 1;
+            return tid < nx;
+        }
+    };
 
     // all global loads of plane z
-    auto fetch = [&](XRowState<T, A>& s, int xb, int z) {
+    auto fetch = [&](XRowState<T, A>& s, uint32_t xb, int z) {
         const uint32_t zo = (uint32_t)z * pbytes;
-        s.nc = Cr(xb + yoff, cplane(z + 3));
-        s.nu = Ur(xb + yoffu, (uint32_t)z * ubytes);
-        s.nvl = Vr(xb + yoff, (uint32_t)z * vbytes);
-        s.nvh = Vr(xb, (uint32_t)z * vbytes + vtop);
-        s.nwh = Wr(xb + yoff, (uint32_t)((z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1) * pbytes);
-        s.ne = pa.e_mode != 0 ? Er(xb + yoff, zo) : T(0);
+        const uint32_t wo = (uint32_t)((z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1) * pbytes;
+        if constexpr (MR) {
+            s.nc = Cr(xb + s.ro, cplane(z + 3));
+            s.nu = Ur(xb + s.rou, (uint32_t)z * ubytes);
+            s.nvl = Vr(xb + s.ro, (uint32_t)z * vbytes);
+            s.nvh = Vr(xb + s.rvt, (uint32_t)z * vbytes);
+            s.nwh = Wr(xb + s.ro, wo);
+            s.ne = pa.e_mode != 0 ? Er(xb + s.ro, zo) : T(0);
 #pragma unroll
-        for (int hr = 0; hr < 6; ++hr) s.nyh[hr] = Cr(xb, zo + hoff[hr]);
+            for (int hr = 0; hr < 6; ++hr) s.nyh[hr] = Cr(xb + s.ho[hr], zo);
+        } else {
+            s.nc = Cr(xb + yoff, cplane(z + 3));
+            s.nu = Ur(xb + yoffu, (uint32_t)z * ubytes);
+            s.nvl = Vr(xb + yoff, (uint32_t)z * vbytes);
+            s.nvh = Vr(xb, (uint32_t)z * vbytes + vtop);
+            s.nwh = Wr(xb + yoff, wo);
+            s.ne = pa.e_mode != 0 ? Er(xb + yoff, zo) : T(0);
+#pragma unroll
+            for (int hr = 0; hr < 6; ++hr) s.nyh[hr] = Cr(xb, zo + hoff[hr]);
+        }
     };
     // RHS of plane zs of the owned cell into the solve tile (and E out)
-    auto rhs_plane = [&](XRowState<T, A>& s, int x, bool live, int zs) {
+    auto rhs_plane = [&](XRowState<T, A>& s, int r, int x, bool live, int zs) {
+        const T* fr = frb + r * L.frp;
         const T fhi = x + 1 < nx ? fr[x + 1] : fr[bcx == 0 ? 0 : nx];
         const T adv = ((fhi - fr[x]) + s.py) + s.pz;
         const T e = -adv * inv_h + s.plap * lap_s;
         T rhs = gdt * e - bdt * s.pb4;
         if (pa.e_mode != 0) rhs += rdt * s.eold;
         if (live) {
-            if (pa.e_mode != 2) Er.store((uint32_t)x * sT + yoff, (uint32_t)(z0 + zs) * pbytes, e);
-            tb[(x + tw) * tbp + zs] = A(rhs);
+            if (pa.e_mode != 2)
+                Er.store((uint32_t)x * sT + (MR ? s.ro : yoff), (uint32_t)(z0 + zs) * pbytes, e);
+            tb[(x + tw) * tbp + zs * rows + r] = A(rhs);
         }
     };
 
-    // the thread's halo columns, the column below the first plane, its loads
+    // the thread's cell and halo columns, the column below the first plane,
+    // its loads
     ex.phase([&](int tid) {
         XRowState<T, A>& s = st[ex.slot(tid)];
-        const int x = tid < nx ? tid : nx - 1;
+        if constexpr (MR) {
+            s.live = tid < rows * nx;
+            const int item = s.live ? tid : rows * nx - 1;
+            s.r = item / nx;
+            s.x = item - s.r * nx;
+            const int y = t.y0 + s.r;
+            s.ro = row_off(y);
+            s.rou = row_offu(y);
+            s.rvt = row_vtop(y);
+#pragma unroll
+            for (int hr = 0; hr < 6; ++hr) s.ho[hr] = halo_off(y, hr);
+        }
+        int r, x;
+        cell(s, tid, &r, &x);
         const uint32_t xb = (uint32_t)x * sT;
+        const uint32_t ro = MR ? s.ro : yoff;
         s.cxp = x;
         s.cxm = x;
         for (int q = 0; q < 6; ++q) {
@@ -1244,12 +1305,12 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
             }
         }
 #pragma unroll
-        for (int q = 1; q < 7; ++q) s.c[q] = Cr(xb + yoff, cplane(z0 - 4 + q));
+        for (int q = 1; q < 7; ++q) s.c[q] = Cr(xb + ro, cplane(z0 - 4 + q));
         s.mq[1] = mu(s.c[3]);   // psi'(C) at z0-2 .. z0 after the first shift
         s.mq[2] = mu(s.c[4]);
-        s.wh = Wr(xb + yoff, (uint32_t)z0 * pbytes);   // becomes the low face of z0
+        s.wh = Wr(xb + ro, (uint32_t)z0 * pbytes);   // becomes the low face of z0
         wait_loads();
-        fetch(s, (int)xb, z0);
+        fetch(s, xb, z0);
     });
 
     for (int zs = 0; zs < nzc; ++zs) {
@@ -1258,8 +1319,8 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
         //      the plane below, the owned row into LDS
         ex.phase([&](int tid) {
             XRowState<T, A>& s = st[ex.slot(tid)];
-            const bool live = tid < nx;
-            const int x = live ? tid : nx - 1;
+            int r, x;
+            const bool live = cell(s, tid, &r, &x);
 #pragma unroll
             for (int q = 0; q < 6; ++q) s.c[q] = s.c[q + 1];
             s.c[6] = s.nc;
@@ -1271,13 +1332,15 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
 #pragma unroll
             for (int hr = 0; hr < 6; ++hr) s.yh[hr] = s.nyh[hr];
             const T e_here = s.ne;
-            if (zs + 1 < nzc) fetch(s, (int)((uint32_t)x * sT), z + 1);
-            if (zs > 0) rhs_plane(s, x, live, zs - 1);
+            if (zs + 1 < nzc) fetch(s, (uint32_t)x * sT, z + 1);
+            if (zs > 0) rhs_plane(s, r, x, live, zs - 1);
             s.eold = e_here;
             s.mq[0] = s.mq[1];
             s.mq[1] = s.mq[2];
             s.mq[2] = mu(s.c[4]);
             if (live) {
+                T* cr = crb + r * L.crp;
+                T* mr = mrb + r * L.mrp;
                 cr[x] = s.c[3];
                 cr[s.cxp] = s.c[3];
                 mr[x] = s.mq[1];
@@ -1287,9 +1350,11 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
         // ---- face fluxes, Laplacian of psi'(C), fourth differences
         ex.phase([&](int tid) {
             XRowState<T, A>& s = st[ex.slot(tid)];
-            const bool live = tid < nx;
-            const int x = live ? tid : nx - 1;
-            const T* row = cr + x;   // row[o] = C(x + o)
+            int r, x;
+            const bool live = cell(s, tid, &r, &x);
+            const T* row = crb + r * L.crp + x;   // row[o] = C(x + o)
+            const T* mrow = mrb + r * L.mrp + x;  // mrow[o] = psi'(C)(x + o)
+            T* fr = frb + r * L.frp;
             {
                 const T dX[5] = {row[-2] - row[-3], row[-1] - row[-2], row[0] - row[-1],
                                  row[1] - row[0], row[2] - row[1]};
@@ -1300,7 +1365,8 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
             }
             if (bcx != 0 && live && x == nx - 1) {
                 // the wall face nx (its normal velocity is zero by the interface's rule)
-                const T uw = Ur((uint32_t)(x + 1) * sT + yoffu, (uint32_t)z * ubytes);
+                const T uw = Ur((uint32_t)(x + 1) * sT + (MR ? s.rou : yoffu),
+                                (uint32_t)z * ubytes);
                 fr[nx] = uw * face_weno<T>(uw, row[-2], row[-1], row[0], row[1], row[2], row[3],
                                            epsw);
             }
@@ -1333,19 +1399,22 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
                 s.fzl = fzh;
                 s.pb4 += d4_d<T>(dZ[0], dZ[1], dZ[2], dZ[3]);
             }
-            s.plap = ((mr[x + 1] + mr[x - 1]) + (mu(s.yh[3]) + mu(s.yh[2])))
+            s.plap = ((mrow[1] + mrow[-1]) + (mu(s.yh[3]) + mu(s.yh[2])))
                    + (s.mq[2] + s.mq[0]) - T(6) * s.mq[1];
         });
     }
     // ---- RHS of the last plane
     ex.phase([&](int tid) {
-        const bool live = tid < nx;
-        rhs_plane(st[ex.slot(tid)], live ? tid : nx - 1, live, nzc - 1);
+        XRowState<T, A>& s = st[ex.slot(tid)];
+        int r, x;
+        const bool live = cell(s, tid, &r, &x);
+        rhs_plane(s, r, x, live, nzc - 1);
     });
+    const int nlines = rows * nzc;
     // ---- halos of the solve tile (periodic or reflected continuation)
     ex.phase([&](int tid) {
         const int span = 2 * tw;
-        for (int j = tid; j < nzc * span; j += nth) {
+        for (int j = tid; j < nlines * span; j += nth) {
             const int ln = j / span, q = j - ln * span;
             const int pp = q < tw ? q - tw : nx + q - tw;
             tb[(pp + tw) * tbp + ln] = tb[(map_idx(pp, nx, bcx) + tw) * tbp + ln];
@@ -1353,27 +1422,29 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
     });
     // ---- x solve of the task's lines
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nzc, nx, tw, X_CHAINS);
+        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
         line_f1<A>(ch, tb, tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nzc, nx, tw, X_CHAINS);
+        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
         line_f2<A>(ch, tb, tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nzc, nx, tw, X_CHAINS);
+        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
         line_b1<A>(ch, tb, tbp, tw, a1, a2, st[ex.slot(tid)].ls);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nzc, nx, tw, X_CHAINS);
+        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
         line_b2<A>(ch, tb, tbp, tw, a1, a2, st[ex.slot(tid)].ls);
     });
     // ---- q out, plane by plane
     ex.phase([&](int tid) {
-        if (tid >= nx) return;
-        const uint32_t o = (uint32_t)tid * sT + yoff;
+        const XRowState<T, A>& s = st[ex.slot(tid)];
+        int r, x;
+        if (!cell(s, tid, &r, &x)) return;
+        const uint32_t o = (uint32_t)x * sT + (MR ? s.ro : yoff);
         for (int zs = 0; zs < nzc; ++zs)
-            Qr.store(o, (uint32_t)(z0 + zs) * pbytes, T(tb[(tid + tw) * tbp + zs]));
+            Qr.store(o, (uint32_t)(z0 + zs) * pbytes, T(tb[(x + tw) * tbp + zs * rows + r]));
     });
 }
 

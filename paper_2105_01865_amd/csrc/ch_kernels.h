@@ -15,7 +15,7 @@ template <typename T, typename A>
 hipError_t launch_pass_x(int mi, int nwg, int nth, size_t lds, hipStream_t st,
                          const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
                          const void* C, const void* U, const void* V, const void* W, void* E,
-                         void* Q, bool e25, bool row1);
+                         void* Q, bool e25, bool xrow, bool xrow_multi);
 
 template <typename T, typename A>
 hipError_t launch_pass_line(int pass, int nwg, int nthreads, size_t lds, hipStream_t st,

@@ -58,8 +58,9 @@ k_pass_x(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
                                                              W, E, Q, smem);
 }
 
-// The one-row x-pass program (pass_x_row_program); NT bounds the group size.
-template <typename T, typename A, int NT>
+// The row x-pass program (pass_x_row_program); NT bounds the group size, MR
+// selects several rows per task.
+template <typename T, typename A, int NT, bool MR>
 __global__ void __launch_bounds__(NT)
 k_pass_x_row(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
              const T* __restrict__ C, const T* __restrict__ U, const T* __restrict__ V,
@@ -70,8 +71,8 @@ k_pass_x_row(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
     const int b = chd::find_box(boxes, nbox, chd::PASS_X, task);
     chd::GpuExec ex{(int)threadIdx.x, (int)blockDim.x};
     chd::XRowState<T, A> st;
-    chd::pass_x_row_program<T, A, chd::GpuExec>(ex, &st, boxes[b], pa, task, C, U, V, W, E, Q,
-                                                smem);
+    chd::pass_x_row_program<T, A, MR, chd::GpuExec>(ex, &st, boxes[b], pa, task, C, U, V, W, E,
+                                                    Q, smem);
 }
 
 template <typename T, typename A, int PASS>
@@ -1084,34 +1085,46 @@ static hipError_t launch_x_mode(int mi, int nwg, int nth, size_t lds, hipStream_
     return launch_x<T, A, 2, 1024, E25>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
 }
 
-template <typename T, typename A, int NT>
+template <typename T, typename A, int NT, bool MR>
 static hipError_t launch_x_row(int nwg, int nth, size_t lds, hipStream_t st,
                                const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
                                const void* C, const void* U, const void* V, const void* W,
                                void* E, void* Q)
 {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)&k_pass_x_row<T, A, NT>,
+        hipError_t e = hipFuncSetAttribute((const void*)&k_pass_x_row<T, A, NT, MR>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_pass_x_row<T, A, NT>), dim3(nwg), dim3(nth), lds, st, boxes, nbox, pa,
-                       (const T*)C, (const T*)U, (const T*)V, (const T*)W, (T*)E, (T*)Q);
+    hipLaunchKernelGGL((k_pass_x_row<T, A, NT, MR>), dim3(nwg), dim3(nth), lds, st, boxes, nbox,
+                       pa, (const T*)C, (const T*)U, (const T*)V, (const T*)W, (T*)E, (T*)Q);
     return hipGetLastError();
+}
+
+template <typename T, typename A, bool MR>
+static hipError_t launch_x_row_nt(int nwg, int nth, size_t lds, hipStream_t st,
+                                  const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
+                                  const void* C, const void* U, const void* V, const void* W,
+                                  void* E, void* Q)
+{
+    if (nth <= 256)
+        return launch_x_row<T, A, 256, MR>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    if (nth <= 512)
+        return launch_x_row<T, A, 512, MR>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    return launch_x_row<T, A, 1024, MR>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
 }
 
 template <typename T, typename A>
 hipError_t launch_pass_x(int mi, int nwg, int nth, size_t lds, hipStream_t st,
                          const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
                          const void* C, const void* U, const void* V, const void* W, void* E,
-                         void* Q, bool e25, bool row1)
+                         void* Q, bool e25, bool xrow, bool xrow_multi)
 {
-    if (row1 && !e25 && mi == 1) {
-        if (nth <= 256)
-            return launch_x_row<T, A, 256>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
-        if (nth <= 512)
-            return launch_x_row<T, A, 512>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
-        return launch_x_row<T, A, 1024>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    if (xrow && !e25 && mi == 1) {
+        if (xrow_multi)
+            return launch_x_row_nt<T, A, true>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E,
+                                               Q);
+        return launch_x_row_nt<T, A, false>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
     }
     if constexpr (std::is_same<T, A>::value) {
         if (e25)
@@ -1326,7 +1339,7 @@ hipError_t launch_press_update(hipStream_t st, const PressArgs& a, const void* C
                                             const chd::BoxDesc*, int,                           \
                                             const chd::PassArgs&, const void*, const void*,     \
                                             const void*, const void*, void*, void*, bool,       \
-                                            bool);                                              \
+                                            bool, bool);                                        \
     template hipError_t launch_pass_line<T, A>(int, int, int, size_t, hipStream_t,              \
                                                const chd::BoxDesc*, int, const chd::PassArgs&,  \
                                                const void*, void*);

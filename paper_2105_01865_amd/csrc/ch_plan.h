@@ -31,6 +31,9 @@ constexpr size_t LDS_HARD = 160 * 1024;    // gfx950 LDS per CU
 // many waves make room for.
 constexpr int X_WAVES_F32 = 5;
 constexpr int X_WAVES_F64 = 3;
+// the same for the row program (78 VGPRs in single precision, 123 in double)
+constexpr int XROW_WAVES_F32 = 6;
+constexpr int XROW_WAVES_F64 = 4;
 constexpr int X_MAX_THREADS = 1024;        // largest x-pass work-group
 
 // cells of an x-pass plane tile per thread: one, two for very long x lines
@@ -99,7 +102,8 @@ struct Plan {
     double dt = NAN;
     bool acc64 = true;
     bool e25 = false;   // explicit 25-point scheme: no line solves, one row per x task
-    bool row1 = false;  // the x pass runs the one-row program
+    bool xrow = false;        // the x pass runs the one-cell-per-thread row program
+    bool xrow_multi = false;  // ... with several rows in some task
     int tw_max = 0;
     int x_rows = 0, x_threads = 256, zc = 1, mi = 1, lanes = 32, yz_threads = 256, seg_cap = 0;
     int ntask[3] = {0, 0, 0};
@@ -287,13 +291,34 @@ inline ch_status plan_dt(Plan& P, double dt)
                  (double)d.nf[0] * n1 * n2 * s < 4294967296.0 &&
                  n0 * d.nf[1] * n2 * s < 4294967296.0 && n0 * n1 * d.nf[2] * s < 4294967296.0;
     }
+    auto threads_for = [&](int R) { return ((R * nxm + P.mi - 1) / P.mi + 63) / 64 * 64; };
+    // rows per task of box b in the row program with `threads` threads: as
+    // many as fill the group, so narrow boxes of an ensemble keep it busy
+    // (an explicit z_chunk caps them so that every line of a task keeps its
+    // chunks' threads)
+    auto rows_row = [&](int b, int threads) {
+        int r = std::min(P.boxes[b].n[1], threads / P.boxes[b].n[0]);
+        if (P.opt.z_chunk > 0)
+            r = std::min(r, threads / (std::min(P.opt.z_chunk, P.boxes[b].n[2]) *
+                                       nch_x(P.boxes[b].n[0])));
+        return std::max(1, r);
+    };
     auto xlds = [&](int R, int zc) {
-        if (R == 1 && row_ok) return chd::x_row_layout(nxm, zc, P.tw_max, (int)sT, (int)sA).total;
+        if (row_ok) {
+            size_t m = 0;
+            const int th = threads_for(R);
+            for (int b = 0; b < P.nbox; ++b)
+                m = std::max(m, chd::x_row_layout(P.boxes[b].n[0], rows_row(b, th),
+                                                  std::min(zc, P.boxes[b].n[2]), P.tw_max,
+                                                  (int)sT, (int)sA).total);
+            return m;
+        }
         return chd::x_layout(nxm, R, zc, P.tw_max, (int)sT, (int)sA, P.e25).total;
     };
-    const int xwaves = sT == 4 ? X_WAVES_F32 : X_WAVES_F64;
+    const int xwaves = row_ok ? (sT == 4 ? XROW_WAVES_F32 : XROW_WAVES_F64)
+                              : (sT == 4 ? X_WAVES_F32 : X_WAVES_F64);
     auto xbudget_for = [&](int R) {
-        const int threads = ((R * nxm + P.mi - 1) / P.mi + 63) / 64 * 64;
+        const int threads = threads_for(R);
         const int per_simd = (threads / 64 + 3) / 4;   // waves of one group per SIMD
         const int groups = std::max(1, xwaves / std::max(1, per_simd));
         // measured on gfx950: five groups of the single-precision kernel
@@ -309,14 +334,20 @@ inline ch_status plan_dt(Plan& P, double dt)
     }
     if (R * nxm > xcap) return P.fail(CH_EINVAL, "x_rows too large for the x extent");
     P.x_rows = R;
-    P.row1 = row_ok && R == 1;
-    P.x_threads = ((R * nxm + P.mi - 1) / P.mi + 63) / 64 * 64;
+    P.x_threads = threads_for(R);
     if (P.x_threads > X_MAX_THREADS) return P.fail(CH_EINVAL, "x_rows too large for the x extent");
+    P.xrow = row_ok;
+    P.xrow_multi = false;
+    auto rows_of = [&](int b) {
+        return row_ok ? rows_row(b, P.x_threads) : std::min(R, P.boxes[b].n[1]);
+    };
+    for (int b = 0; b < P.nbox && row_ok; ++b) P.xrow_multi = P.xrow_multi || rows_of(b) > 1;
     // planes per task: every line of a task needs its chunks' threads
     int zlim = 64;
+    // (a box takes min(z_chunk, nz) planes, so one whose nz fits sets no limit)
     for (int b = 0; b < P.nbox && !P.e25; ++b) {
-        const int rb = std::min(R, P.boxes[b].n[1]);
-        zlim = std::min(zlim, P.x_threads / (rb * nch_x(P.boxes[b].n[0])));
+        const int lim = P.x_threads / (rows_of(b) * nch_x(P.boxes[b].n[0]));
+        if (P.boxes[b].n[2] > lim) zlim = std::min(zlim, lim);
     }
     int zc = P.opt.z_chunk;
     if (zc == 0) {
@@ -350,7 +381,7 @@ inline ch_status plan_dt(Plan& P, double dt)
     for (int b = 0; b < P.nbox; ++b) {
         chd::BoxDesc& d = P.boxes[b];
         const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
-        d.x_rows = std::min(R, ny);
+        d.x_rows = rows_of(b);
         d.zc = std::min(zc, nz);
         d.seg[0] = std::min(seg, ny);
         d.seg[1] = std::min(seg, nz);

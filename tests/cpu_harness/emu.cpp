@@ -13,7 +13,9 @@
 //           factorised implicit scheme, 1 the explicit 25-point scheme
 //   IN_DIR/{C,u,v,w}.bin: packed float64 arrays (the library's layout)
 //   OUT_DIR/C.bin: packed float64 result; OUT_DIR/mass.txt: per-box mass;
-//   OUT_DIR/plan.txt: x_rows seg_cap chains tw_max acc64 ntask0..2 lds0..2 z_chunk row1
+//   OUT_DIR/plan.txt: x_rows seg_cap chains tw_max acc64 ntask0..2 lds0..2 z_chunk xrow
+//           (xrow: 0 general x program, 1 row program, 2 row program with
+//           several rows in some task)
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -74,7 +76,12 @@ static void run_xrow(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T
         unsigned char* lds = (unsigned char*)malloc(P.lds[0]);
         memset(lds, 0xff, P.lds[0]);
         const int b = chd::find_box(boxes, P.nbox, chd::PASS_X, task);
-        chd::pass_x_row_program<T, A>(ex, st.data(), boxes[b], pa, task, C, u, v, w, E, qa, lds);
+        if (P.xrow_multi)
+            chd::pass_x_row_program<T, A, true>(ex, st.data(), boxes[b], pa, task, C, u, v, w, E,
+                                                qa, lds);
+        else
+            chd::pass_x_row_program<T, A, false>(ex, st.data(), boxes[b], pa, task, C, u, v, w, E,
+                                                 qa, lds);
         free(lds);
     }
 }
@@ -87,7 +94,7 @@ static void run(chp::Plan& P, T* C, T* E, T* qa, T* qb, const T* u, const T* v, 
     for (int s = 0; s < nsteps; ++s)
         for (int k = 0; k < 3; ++k) {
             // pass x
-            if (P.row1) run_xrow<T, A>(P, k, C, E, qa, u, v, w);
+            if (P.xrow) run_xrow<T, A>(P, k, C, E, qa, u, v, w);
             else if (P.mi == 1) run_x<T, A, 1>(P, k, C, E, qa, u, v, w);
             else run_x<T, A, 2>(P, k, C, E, qa, u, v, w);
             // passes y, z
@@ -180,7 +187,7 @@ static int go(chp::Plan& P, const std::string& in, const std::string& out, int n
     f = fopen((out + "/plan.txt").c_str(), "w");
     fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu %d %d\n", P.x_rows, P.seg_cap, P.yz_threads,
             P.tw_max, P.acc64 ? 1 : 0, P.ntask[0], P.ntask[1], P.ntask[2], P.lds[0], P.lds[1],
-            P.lds[2], P.zc, P.row1 ? 1 : 0);
+            P.lds[2], P.zc, P.xrow ? (P.xrow_multi ? 2 : 1) : 0);
     fclose(f);
     free(C); free(E); free(qa); free(qb); free(u); free(v); free(w);
     return 0;

@@ -188,9 +188,10 @@ def test_explicit25_matches_oracle(shape, bc, zc):
     ((1, 9, 20), (0, 1, 0), 1),        # degenerate z
     ((14, 8, 8), (1, 1, 0), 7),        # the shortest x line
 ])
-def test_one_row_program_equals_the_general_one(shape, bc, zc):
-    """One x-line per task: the one-row x program (y stencil in registers)
-    and the general one give the same bits, and both the oracle's step."""
+def test_row_program_equals_the_general_one(shape, bc, zc):
+    """The row x program (one cell per thread, the y stencil in registers;
+    as many rows per task as fill the group) and the general one give the
+    same bits, and both the oracle's step."""
     b = _box(shape, bc=bc, seed=23, amp=2.0, drops=min(shape) > 4)
     dt = 2e-4
     ref = _oracle(b, dt, 2)
@@ -199,21 +200,23 @@ def test_one_row_program_equals_the_general_one(shape, bc, zc):
         for xg in (0, 1):
             o, m, plan = run_emu([b], dt, 2, prec=prec, solve=solve, x_rows=1, z_chunk=zc,
                                  x_general=xg)
-            assert plan["row1"] == (1 - xg)
+            assert (plan["xrow"] > 0) == (xg == 0)
             out[xg] = (o[0], m[0])
         assert np.array_equal(out[0][0], out[1][0])
         assert out[0][1] == out[1][1]
         assert _rel(out[0][0], ref) < tol
 
 
-def test_one_row_program_in_a_batch():
-    # boxes of different widths in one launch: the narrow ones leave threads idle
+@pytest.mark.parametrize("x_rows", [1, 2])
+def test_row_program_in_a_batch(x_rows):
+    # boxes of different widths in one launch: the narrow ones take several
+    # rows per task (ragged last tasks), the widest one or two
     boxes = [_box((16, 12, 40), seed=31), _box((10, 9, 8), seed=32, bc=(0, 0, 0)),
-             _box((12, 14, 33), seed=33)]
+             _box((12, 14, 33), seed=33), _box((9, 9, 13), seed=34, bc=(0, 1, 1))]
     dt = 3e-4
-    got, masses, plan = run_emu(boxes, dt, 2, x_rows=1)
-    assert plan["row1"] == 1
-    gen, _, _ = run_emu(boxes, dt, 2, x_rows=1, x_general=1)
+    got, masses, plan = run_emu(boxes, dt, 2, x_rows=x_rows)
+    assert plan["xrow"] == 2
+    gen, _, _ = run_emu(boxes, dt, 2, x_rows=x_rows, x_general=1)
     for a, g, b in zip(got, gen, boxes):
         assert np.array_equal(a, g)
         assert _rel(a, _oracle(b, dt, 2)) < 1e-12
