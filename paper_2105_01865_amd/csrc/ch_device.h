@@ -51,6 +51,8 @@ struct BoxDesc {
     int32_t nf[3];      // faces stored along x (u), y (v), z (w)
     int32_t x_rows;     // rows of one x-pass task
     int32_t zc;         // planes one x-pass task marches over
+    int32_t xs;         // x segment of the segmented x program (0: whole lines)
+    int32_t nxs;        // its segments per line
     int64_t c_off;      // first element of this box in C, E, q
     int64_t u_off, v_off, w_off;
     double inv_h, inv_h2, inv_pe, eps;
@@ -612,12 +614,22 @@ CH_HD XLayout x_layout(int nx_max, int rmax, int zcmax, int tw_max, int sT, int 
 
 struct XZTask {
     int z0, nzc, y0, rows;
+    int x0, xlen;   // x segment (the whole line unless the box is segmented)
 };
 
+// Task order: x segments fastest, then rows, then chunks of planes.
 CH_HD XZTask xz_task(const BoxDesc& bd, int task)
 {
     XZTask t;
-    const int local = task - bd.task0[PASS_X];
+    int local = task - bd.task0[PASS_X];
+    t.x0 = 0;
+    t.xlen = bd.n[0];
+    if (bd.xs > 0) {
+        const int sg = local % bd.nxs;
+        local /= bd.nxs;
+        t.x0 = sg * bd.xs;
+        t.xlen = bd.n[0] - t.x0 < bd.xs ? bd.n[0] - t.x0 : bd.xs;
+    }
     const int R = bd.x_rows;
     const int nyb = (bd.n[1] + R - 1) / R;
     const int zc = local / nyb;
@@ -1445,6 +1457,263 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
         const uint32_t o = (uint32_t)x * sT + (MR ? s.ro : yoff);
         for (int zs = 0; zs < nzc; ++zs)
             Qr.store(o, (uint32_t)(z0 + zs) * pbytes, T(tb[(x + tw) * tbp + zs * rows + r]));
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Pass X over one row and one x segment per task, for periodic lines too long
+// for one work-group (the arithmetic of pass_x_row_program, cell by cell).
+//
+// The segment [x0, x0 + S) is solved from the RHS of the segment extended by
+// tw_max cells on each side (the recurrences' warm-ups), so a task computes
+// the explicit terms of NE = S + 2 tw_max cells, and thread NE + 1 only the x
+// face above the last one.  Extended position q (0 <= q <= NE) is the cell
+// x0 - tw_max + q, wrapped.  The six C values beyond the extended range that
+// its x stencils reach are loaded by threads 0..5.  E of the previous
+// substage is read from Ein and the new one written to Eout, a different
+// array: a task reads E at the cells of its neighbours' segments.  Only the
+// segment's own cells are written (E and q).  Fields are addressed per plane
+// (a buffer resource for each plane), so they may exceed 4 GiB.  Threads:
+// x_seg_threads (positions 0 .. NE).
+//
+// LDS (launch-wide: S the longest segment):
+//   cr: NE + 7 T    C at extended positions -3 .. NE + 3
+//   mr: NE + 3 T    psi'(C) at -1 .. NE + 1
+//   fr: NE + 1 T    flux through the low x face of position q, 0 .. NE
+//   tb: (S + 2 tw_max) x (zc + 1) A    RHS -> solve tile, line zs
+// ---------------------------------------------------------------------------
+struct XSegLayout {
+    size_t cr, mr, fr, tb, total;   // byte offsets and total size
+    int tbp;                        // pitch of the solve tile (elements)
+};
+
+CH_HD XSegLayout x_seg_layout(int S, int zc, int tw_max, int sT, int sA)
+{
+    const int ne = S + 2 * tw_max;
+    XSegLayout L;
+    L.tbp = zc + 1;
+    L.cr = 0;
+    L.mr = al16(L.cr + (size_t)(ne + 7) * sT);
+    L.fr = al16(L.mr + (size_t)(ne + 3) * sT);
+    L.tb = al16(L.fr + (size_t)(ne + 1) * sT);
+    L.total = al16(L.tb + (size_t)(S + 2 * tw_max) * L.tbp * sA);
+    return L;
+}
+
+// threads of a segment of S cells
+CH_HD int x_seg_threads(int S, int tw_max) { return S + 2 * tw_max + 1; }
+
+template <typename T, typename A>
+struct XSegState {
+    T c[7];                   // C at z-3 .. z+3 of the cell
+    T mq[3];                  // psi'(C) at z-1, z, z+1
+    T yh[6];                  // C of this plane at rows y-3, y-2, y-1, y+1, y+2, y+3
+    T ul, vl, vh, wl, wh;     // face velocities (as in XRowState)
+    T fzl;                    // flux through the low z face
+    T eold;                   // E of the previous substage at the plane whose RHS is next
+    T py, pz, plap, pb4;      // y and z flux differences, Laplacian of psi', sum of D4
+    T xh;                     // threads 0..5: C beyond the extended range, this plane
+    T nc, nu, nvl, nvh, nwh, ne, nyh[6], nxh;   // the next plane's loads
+    LineState<A> ls;
+};
+
+template <typename T, typename A, class X>
+CH_HD void pass_x_seg_program(X& ex, XSegState<T, A>* st, const BoxDesc& bd, const PassArgs& pa,
+                              int task, const T* __restrict__ C, const T* __restrict__ U,
+                              const T* __restrict__ V, const T* __restrict__ W,
+                              const T* __restrict__ Ein, T* __restrict__ Eout,
+                              T* __restrict__ Q, unsigned char* smem)
+{
+    const XZTask t = xz_task(bd, task);   // one row, one segment
+    const int nx = bd.n[0], ny = bd.n[1], nz = bd.n[2];
+    const int fx = bd.nf[0], fy = bd.nf[1];
+    const int k = pa.k, tw = bd.tw[k], twm = pa.tw_max;
+    const int S = t.xlen, x0 = t.x0;
+    const int NE = S + 2 * twm;
+    const XSegLayout L = x_seg_layout(bd.xs, bd.zc, twm, (int)sizeof(T), (int)sizeof(A));
+    constexpr uint32_t sT = sizeof(T);
+    T* cr = reinterpret_cast<T*>(smem + L.cr) + 3;   // cr[q], -3 <= q <= NE + 3
+    T* mr = reinterpret_cast<T*>(smem + L.mr) + 1;   // mr[q], -1 <= q <= NE + 1
+    T* fr = reinterpret_cast<T*>(smem + L.fr);       // fr[q], 0 <= q <= NE
+    A* tb = reinterpret_cast<A*>(smem + L.tb);
+    const int tbp = L.tbp;
+    const int64_t plane = (int64_t)nx * ny;
+    const uint32_t pbytes = (uint32_t)(plane * sT);
+    const uint32_t ubytes = (uint32_t)((int64_t)ny * fx * sT);
+    const uint32_t vbytes = (uint32_t)((int64_t)fy * nx * sT);
+    const T* Cb = C + bd.c_off;
+    const T* Ub = U + bd.u_off;
+    const T* Vb = V + bd.v_off;
+    const T* Wb = W + bd.w_off;
+    const T* Eib = Ein + bd.c_off;
+    T* Eob = Eout + bd.c_off;
+    T* Qb = Q + bd.c_off;
+    auto Cp = [&](int z) { return PlaneRef<T>(Cb + (int64_t)z * plane, pbytes); };
+    const T epsw = T(bd.eps * (12.0 / 13.0));
+    const T gdt = T(bd.gdt[k]), rdt = T(bd.rdt[k]), bdt = T(bd.bdt[k]);
+    const T inv_h = T(bd.inv_h), lap_s = T(bd.inv_h2 * bd.inv_pe);
+    const Cubic<T> mu = cubic<T>(bd.psi);
+    const A a1 = A(bd.a1[k]), a2 = A(bd.a2[k]), ic = A(bd.ic[k]);
+    const int y = t.y0;
+    const int z0 = t.z0, nzc = t.nzc;
+    const uint32_t yoff = (uint32_t)(y * nx) * sT;
+    const uint32_t yoffu = (uint32_t)(y * fx) * sT;
+    const uint32_t vtop = (uint32_t)((y + 1 == ny && bd.bc[1] == 0 ? 0 : y + 1) * nx) * sT;
+    uint32_t hoff[6];
+#pragma unroll
+    for (int hr = 0; hr < 6; ++hr)
+        hoff[hr] = (uint32_t)(map_idx(y + (hr < 3 ? hr - 3 : hr - 2), ny, bd.bc[1]) * nx) * sT;
+    // extended position of a thread (threads past NE + 1 repeat the last one)
+    auto pos = [&](int tid) { return tid <= NE ? tid : NE; };
+    auto cellb = [&](int q) { return (uint32_t)map_idx(x0 - twm + q, nx, 0) * sT; };
+    // threads 0..5: the C beyond the extended range, at cr index hq
+    auto hq = [&](int tid) { return tid < 3 ? tid - 3 : NE + 1 + (tid - 3); };
+
+    auto fetch = [&](XSegState<T, A>& s, int tid, uint32_t xb, int z) {
+        s.nc = Cp(map_idx(z + 3, nz, bd.bc[2]))(xb + yoff);
+        s.nu = PlaneRef<T>(Ub + (int64_t)z * ny * fx, ubytes)(xb + yoffu);
+        const PlaneRef<T> Vz(Vb + (int64_t)z * fy * nx, vbytes);
+        s.nvl = Vz(xb + yoff);
+        s.nvh = Vz(xb, vtop);
+        s.nwh = PlaneRef<T>(Wb + (int64_t)((z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1) * plane,
+                            pbytes)(xb + yoff);
+        s.ne = pa.e_mode != 0 ? PlaneRef<T>(Eib + (int64_t)z * plane, pbytes)(xb + yoff) : T(0);
+        const PlaneRef<T> Cz = Cp(z);
+#pragma unroll
+        for (int hr = 0; hr < 6; ++hr) s.nyh[hr] = Cz(xb, hoff[hr]);
+        if (tid < 6) s.nxh = Cz(cellb(hq(tid)) + yoff);
+    };
+    // RHS of plane zs at extended position q into the solve tile (and E out
+    // at the segment's own cells)
+    auto rhs_plane = [&](XSegState<T, A>& s, int tid, int q, int zs) {
+        const T adv = ((fr[q + 1] - fr[q]) + s.py) + s.pz;
+        const T e = -adv * inv_h + s.plap * lap_s;
+        T rhs = gdt * e - bdt * s.pb4;
+        if (pa.e_mode != 0) rhs += rdt * s.eold;
+        const int rel = q - twm;   // position in the segment
+        if (tid == q && rel >= -tw && rel < S + tw) {
+            if (pa.e_mode != 2 && rel >= 0 && rel < S)
+                PlaneRef<T>(Eob + (int64_t)(z0 + zs) * plane, pbytes).store(cellb(q) + yoff, e);
+            tb[(rel + tw) * tbp + zs] = A(rhs);
+        }
+    };
+
+    ex.phase([&](int tid) {
+        XSegState<T, A>& s = st[ex.slot(tid)];
+        const uint32_t xb = cellb(pos(tid));
+#pragma unroll
+        for (int q = 1; q < 7; ++q) s.c[q] = Cp(map_idx(z0 - 4 + q, nz, bd.bc[2]))(xb + yoff);
+        s.mq[1] = mu(s.c[3]);
+        s.mq[2] = mu(s.c[4]);
+        s.wh = PlaneRef<T>(Wb + (int64_t)z0 * plane, pbytes)(xb + yoff);
+        wait_loads();
+        fetch(s, tid, xb, z0);
+    });
+
+    for (int zs = 0; zs < nzc; ++zs) {
+        const int z = z0 + zs;
+        ex.phase([&](int tid) {
+            XSegState<T, A>& s = st[ex.slot(tid)];
+            const int q = pos(tid);
+#pragma unroll
+            for (int j = 0; j < 6; ++j) s.c[j] = s.c[j + 1];
+            s.c[6] = s.nc;
+            s.ul = s.nu;
+            s.vl = s.nvl;
+            s.vh = s.nvh;
+            s.wl = s.wh;
+            s.wh = s.nwh;
+#pragma unroll
+            for (int hr = 0; hr < 6; ++hr) s.yh[hr] = s.nyh[hr];
+            s.xh = s.nxh;
+            const T e_here = s.ne;
+            if (zs + 1 < nzc) fetch(s, tid, cellb(q), z + 1);
+            if (zs > 0 && q < NE) rhs_plane(s, tid, q, zs - 1);
+            s.eold = e_here;
+            s.mq[0] = s.mq[1];
+            s.mq[1] = s.mq[2];
+            s.mq[2] = mu(s.c[4]);
+            if (tid == q) {
+                cr[q] = s.c[3];
+                mr[q] = s.mq[1];
+            }
+            if (tid < 6) {
+                cr[hq(tid)] = s.xh;
+                if (tid == 2) mr[-1] = mu(s.xh);
+                if (tid == 3) mr[NE + 1] = mu(s.xh);
+            }
+        });
+        ex.phase([&](int tid) {
+            XSegState<T, A>& s = st[ex.slot(tid)];
+            const int q = pos(tid);
+            const T* row = cr + q;
+            {
+                const T dX[5] = {row[-2] - row[-3], row[-1] - row[-2], row[0] - row[-1],
+                                 row[1] - row[0], row[2] - row[1]};
+                const T f = flux_weno_d<T>(s.ul, dX[0], dX[1], dX[2], dX[3], dX[4], row[-1],
+                                           row[0], epsw);
+                if (tid == q) fr[q] = f;
+                s.pb4 = d4_d<T>(dX[1], dX[2], dX[3], dX[4]);
+            }
+            {
+                const T yc[7] = {s.yh[0], s.yh[1], s.yh[2], s.c[3], s.yh[3], s.yh[4], s.yh[5]};
+                T dY[6];
+#pragma unroll
+                for (int j = 0; j < 6; ++j) dY[j] = yc[j + 1] - yc[j];
+                const T fyl =
+                    flux_weno_d<T>(s.vl, dY[0], dY[1], dY[2], dY[3], dY[4], yc[2], yc[3], epsw);
+                const T fyh =
+                    flux_weno_d<T>(s.vh, dY[1], dY[2], dY[3], dY[4], dY[5], yc[3], yc[4], epsw);
+                s.py = fyh - fyl;
+                s.pb4 += d4_d<T>(dY[1], dY[2], dY[3], dY[4]);
+            }
+            {
+                const T* c = s.c;
+                T dZ[5];
+#pragma unroll
+                for (int j = 0; j < 5; ++j) dZ[j] = c[j + 2] - c[j + 1];
+                if (zs == 0)
+                    s.fzl = flux_weno_d<T>(s.wl, c[1] - c[0], c[2] - c[1], c[3] - c[2],
+                                           c[4] - c[3], c[5] - c[4], c[2], c[3], epsw);
+                const T fzh =
+                    flux_weno_d<T>(s.wh, dZ[0], dZ[1], dZ[2], dZ[3], dZ[4], c[3], c[4], epsw);
+                s.pz = fzh - s.fzl;
+                s.fzl = fzh;
+                s.pb4 += d4_d<T>(dZ[0], dZ[1], dZ[2], dZ[3]);
+            }
+            s.plap = ((mr[q + 1] + mr[q - 1]) + (mu(s.yh[3]) + mu(s.yh[2])))
+                   + (s.mq[2] + s.mq[0]) - T(6) * s.mq[1];
+        });
+    }
+    ex.phase([&](int tid) {
+        const int q = pos(tid);
+        if (q < NE) rhs_plane(st[ex.slot(tid)], tid, q, nzc - 1);
+    });
+    // ---- solve the segment's lines from the computed warm-ups
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nzc, S, tw, X_CHAINS);
+        line_f1<A>(ch, tb, tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nzc, S, tw, X_CHAINS);
+        line_f2<A>(ch, tb, tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nzc, S, tw, X_CHAINS);
+        line_b1<A>(ch, tb, tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+    });
+    ex.phase([&](int tid) {
+        const Chunk ch = line_chunk(tid, nzc, S, tw, X_CHAINS);
+        line_b2<A>(ch, tb, tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+    });
+    // ---- q out at the segment's cells
+    ex.phase([&](int tid) {
+        const int rel = tid - twm;
+        if (rel < 0 || rel >= S) return;
+        const uint32_t o = cellb(tid) + yoff;
+        for (int zs = 0; zs < nzc; ++zs)
+            PlaneRef<T>(Qb + (int64_t)(z0 + zs) * plane, pbytes)
+                .store(o, T(tb[(rel + tw) * tbp + zs]));
     });
 }
 

@@ -17,6 +17,14 @@ hipError_t launch_pass_x(int mi, int nwg, int nth, size_t lds, hipStream_t st,
                          const void* C, const void* U, const void* V, const void* W, void* E,
                          void* Q, bool e25, bool xrow, bool xrow_multi);
 
+// The segmented x-pass program: the previous substage's E from Ein, the new
+// one into Eout (different arrays).
+template <typename T, typename A>
+hipError_t launch_pass_x_seg(int nwg, int nth, size_t lds, hipStream_t st,
+                             const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
+                             const void* C, const void* U, const void* V, const void* W,
+                             const void* Ein, void* Eout, void* Q);
+
 template <typename T, typename A>
 hipError_t launch_pass_line(int pass, int nwg, int nthreads, size_t lds, hipStream_t st,
                             const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,

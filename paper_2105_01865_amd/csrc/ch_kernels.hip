@@ -75,6 +75,24 @@ k_pass_x_row(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
                                                     Q, smem);
 }
 
+// The segmented x-pass program (pass_x_seg_program): E read from Ein, the
+// new one written to Eout.
+template <typename T, typename A>
+__global__ void __launch_bounds__(256)
+k_pass_x_seg(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
+             const T* __restrict__ C, const T* __restrict__ U, const T* __restrict__ V,
+             const T* __restrict__ W, const T* __restrict__ Ein, T* __restrict__ Eout,
+             T* __restrict__ Q)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int task = xcd_task(blockIdx.x, gridDim.x);
+    const int b = chd::find_box(boxes, nbox, chd::PASS_X, task);
+    chd::GpuExec ex{(int)threadIdx.x, (int)blockDim.x};
+    chd::XSegState<T, A> st;
+    chd::pass_x_seg_program<T, A, chd::GpuExec>(ex, &st, boxes[b], pa, task, C, U, V, W, Ein,
+                                                Eout, Q, smem);
+}
+
 template <typename T, typename A, int PASS>
 __global__ void __launch_bounds__(512)
 k_pass_line(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
@@ -1137,6 +1155,24 @@ hipError_t launch_pass_x(int mi, int nwg, int nth, size_t lds, hipStream_t st,
 }
 
 template <typename T, typename A>
+hipError_t launch_pass_x_seg(int nwg, int nth, size_t lds, hipStream_t st,
+                             const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
+                             const void* C, const void* U, const void* V, const void* W,
+                             const void* Ein, void* Eout, void* Q)
+{
+    if (nth > 256) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)&k_pass_x_seg<T, A>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_pass_x_seg<T, A>), dim3(nwg), dim3(nth), lds, st, boxes, nbox, pa,
+                       (const T*)C, (const T*)U, (const T*)V, (const T*)W, (const T*)Ein, (T*)Eout,
+                       (T*)Q);
+    return hipGetLastError();
+}
+
+template <typename T, typename A>
 hipError_t launch_pass_line(int pass, int nwg, int nthreads, size_t lds, hipStream_t st,
                             const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
                             const void* Qin, void* Qout)
@@ -1340,6 +1376,10 @@ hipError_t launch_press_update(hipStream_t st, const PressArgs& a, const void* C
                                             const chd::PassArgs&, const void*, const void*,     \
                                             const void*, const void*, void*, void*, bool,       \
                                             bool, bool);                                        \
+    template hipError_t launch_pass_x_seg<T, A>(int, int, size_t, hipStream_t,                  \
+                                                const chd::BoxDesc*, int, const chd::PassArgs&, \
+                                                const void*, const void*, const void*,          \
+                                                const void*, const void*, void*, void*);        \
     template hipError_t launch_pass_line<T, A>(int, int, int, size_t, hipStream_t,              \
                                                const chd::BoxDesc*, int, const chd::PassArgs&,  \
                                                const void*, void*);

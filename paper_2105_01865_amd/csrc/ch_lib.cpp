@@ -84,6 +84,7 @@ struct Engine {
     chd::BoxDesc* d_boxes = nullptr;
     void* C = nullptr;
     void* E = nullptr;
+    void* E2 = nullptr;   // the segmented x program's second E (allocated when used)
     void* qa = nullptr;
     void* qb = nullptr;
     double* d_partial = nullptr;
@@ -123,8 +124,8 @@ void free_engine(Engine& e)
         (void)hipEventDestroy(p.second.second);
     }
     for (auto ev : e.ev_pool) (void)hipEventDestroy(ev);
-    void* bufs[] = {e.C, e.E, e.qa, e.qb, e.d_partial, e.d_h3, e.d_mass, e.d_flags, e.d_boxes,
-                    e.fu, e.fv, e.fw, e.d_lab, e.d_cnt, e.d_list};
+    void* bufs[] = {e.C, e.E, e.E2, e.qa, e.qb, e.d_partial, e.d_h3, e.d_mass, e.d_flags,
+                    e.d_boxes, e.fu, e.fv, e.fw, e.d_lab, e.d_cnt, e.d_list};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
 }
@@ -170,6 +171,15 @@ ch_status set_dt(Engine& e, double dt, bool e25 = false)
         return fail(st, "%s", e.P.err.c_str());
     }
     HIP_TRY(hipStreamSynchronize(e.stream));
+    if (e.P.xseg && !e.E2) {
+        const size_t bytes = (size_t)e.P.tot[0] * chp::esize(e.P.prec);
+        if (hipMalloc(&e.E2, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            e.E2 = nullptr;
+            e.P.dt = NAN;
+            return fail(CH_ENOMEM, "cannot allocate %zu bytes", bytes);
+        }
+    }
     HIP_TRY(hipMemcpy(e.d_boxes, e.P.boxes.data(), sizeof(chd::BoxDesc) * e.P.nbox,
                       hipMemcpyHostToDevice));
     if (e.gexec) {
@@ -204,7 +214,12 @@ hipError_t enqueue_substage(Engine& e, int k, const void* u, const void* v, cons
         }
         hipError_t err;
         const chd::PassArgs pa = chp::pass_args(e.P, k, p);
-        if (p == 0)
+        if (p == 0 && e.P.xseg)
+            // substage 1 writes E, 2 reads it and writes E2, 3 reads E2
+            err = chk::launch_pass_x_seg<T, A>(e.P.ntask[0], e.P.x_threads, e.P.lds[0],
+                                               e.stream, e.d_boxes, e.P.nbox, pa, e.C, u, v, w,
+                                               k == 2 ? e.E2 : e.E, k == 1 ? e.E2 : e.E, e.qa);
+        else if (p == 0)
             err = chk::launch_pass_x<T, A>(e.P.mi, e.P.ntask[0], e.P.x_threads, e.P.lds[0],
                                            e.stream, e.d_boxes, e.P.nbox, pa,
                                            e.C, u, v, w, e.E, e.qa, false, e.P.xrow,

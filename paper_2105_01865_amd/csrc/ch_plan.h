@@ -34,6 +34,8 @@ constexpr int X_WAVES_F64 = 3;
 // the same for the row program (78 VGPRs in single precision, 123 in double)
 constexpr int XROW_WAVES_F32 = 6;
 constexpr int XROW_WAVES_F64 = 4;
+// work-group size the segmented x program aims at (segment + warm-ups + 1)
+constexpr int SEG_THREADS = 256;
 constexpr int X_MAX_THREADS = 1024;        // largest x-pass work-group
 
 // cells of an x-pass plane tile per thread: one, two for very long x lines
@@ -104,6 +106,7 @@ struct Plan {
     bool e25 = false;   // explicit 25-point scheme: no line solves, one row per x task
     bool xrow = false;        // the x pass runs the one-cell-per-thread row program
     bool xrow_multi = false;  // ... with several rows in some task
+    bool xseg = false;        // the x pass runs the segmented program (long lines)
     int tw_max = 0;
     int x_rows = 0, x_threads = 256, zc = 1, mi = 1, lanes = 32, yz_threads = 256, seg_cap = 0;
     int ntask[3] = {0, 0, 0};
@@ -280,6 +283,55 @@ inline ch_status plan_dt(Plan& P, double dt)
     // ---- x pass: rows per task and planes per task
     // chunks per x line (fixed by the line: see line_chunk_len)
     auto nch_x = [](int n) { return std::max(1, std::min(n / 16, chd::X_CHAINS)); };
+    // Lines longer than a work-group, periodic in x: the segmented program,
+    // one row and one segment of at most SEG_THREADS - 2 tw_max - 1 cells per
+    // task, segments of a line balanced.
+    bool seg_ok = !P.e25 && P.opt.x_general == 0 && nxm > X_MAX_THREADS;
+    for (int b = 0; b < P.nbox && seg_ok; ++b) seg_ok = P.boxes[b].bc[0] == CH_PERIODIC;
+    P.xseg = false;
+    if (seg_ok) {
+        const int smax = SEG_THREADS - 2 * P.tw_max - 1;
+        if (smax >= 64) {
+            int S = 0;
+            for (int b = 0; b < P.nbox; ++b) {
+                chd::BoxDesc& d = P.boxes[b];
+                d.nxs = (d.n[0] + smax - 1) / smax;
+                d.xs = (d.n[0] + d.nxs - 1) / d.nxs;
+                S = std::max(S, d.xs);
+            }
+            P.xseg = true;
+            P.mi = 1;
+            P.xrow = P.xrow_multi = false;
+            P.x_rows = 1;
+            P.x_threads = (chd::x_seg_threads(S, P.tw_max) + 63) / 64 * 64;
+            int zlim = 64;
+            for (int b = 0; b < P.nbox; ++b) {
+                const int lim = P.x_threads / nch_x(P.boxes[b].xs);
+                if (P.boxes[b].n[2] > lim) zlim = std::min(zlim, lim);
+            }
+            const int xwaves = sT == 4 ? XROW_WAVES_F32 : XROW_WAVES_F64;
+            const int groups = std::max(1, xwaves / std::max(1, (P.x_threads / 64 + 3) / 4));
+            const size_t xbudget = LDS_HARD / (size_t)groups;
+            auto slds = [&](int zc) {
+                return chd::x_seg_layout(S, zc, P.tw_max, (int)sT, (int)sA).total;
+            };
+            int zc = P.opt.z_chunk;
+            if (zc == 0) {
+                int64_t tasks = 0;
+                for (int b = 0; b < P.nbox; ++b)
+                    tasks += (int64_t)P.boxes[b].n[1] * P.boxes[b].n[2] * P.boxes[b].nxs;
+                zc = (int)std::max<int64_t>(1, std::min<int64_t>(16, tasks / 2048));
+                zc = std::min(zc, zlim);
+                while (zc > 1 && slds(zc) > xbudget) --zc;
+            }
+            if (zc > zlim) return P.fail(CH_EINVAL, "z_chunk too large for this x segment");
+            if (slds(zc) > LDS_HARD) return P.fail(CH_EUNSUPPORTED, "x tile too large for LDS");
+            P.zc = zc;
+        }
+    }
+    if (!P.xseg)
+        for (int b = 0; b < P.nbox; ++b) P.boxes[b].xs = P.boxes[b].nxs = 0;
+    if (!P.xseg) {
     // the one-row x program: every box's columns feed at most one halo
     // column each (nx >= 6), and every field of every box is under 4 GiB
     // (32-bit byte offsets from one buffer resource per field)
@@ -362,6 +414,9 @@ inline ch_status plan_dt(Plan& P, double dt)
     if (zc > zlim) return P.fail(CH_EINVAL, "z_chunk too large for this x extent");
     if (xlds(R, zc) > LDS_HARD) return P.fail(CH_EUNSUPPORTED, "x tile too large for LDS");
     P.zc = zc;
+    for (int b = 0; b < P.nbox; ++b) P.boxes[b].x_rows = rows_of(b);
+    P.lds[0] = xlds(R, zc);
+    }   // !P.xseg
     // ---- y/z passes: lanes of 128 bytes, whole lines when they fit
     P.lanes = (int)(128 / sA);
     // at least YZ_CHAINS threads per lane column (see line_chunk)
@@ -381,14 +436,15 @@ inline ch_status plan_dt(Plan& P, double dt)
     for (int b = 0; b < P.nbox; ++b) {
         chd::BoxDesc& d = P.boxes[b];
         const int nx = d.n[0], ny = d.n[1], nz = d.n[2];
-        d.x_rows = rows_of(b);
-        d.zc = std::min(zc, nz);
+        if (P.xseg) d.x_rows = 1;
+        d.zc = std::min(P.zc, nz);
         d.seg[0] = std::min(seg, ny);
         d.seg[1] = std::min(seg, nz);
         P.seg_max[0] = std::max(P.seg_max[0], d.seg[0]);
         P.seg_max[1] = std::max(P.seg_max[1], d.seg[1]);
         const int64_t nxb = (nx + P.lanes - 1) / P.lanes;
-        const int64_t tt[3] = {(int64_t)((nz + d.zc - 1) / d.zc) * ((ny + d.x_rows - 1) / d.x_rows),
+        const int64_t tt[3] = {(int64_t)((nz + d.zc - 1) / d.zc) * ((ny + d.x_rows - 1) / d.x_rows) *
+                                   (P.xseg ? d.nxs : 1),
                                (int64_t)nz * nxb * ((ny + d.seg[0] - 1) / d.seg[0]),
                                (int64_t)ny * nxb * ((nz + d.seg[1] - 1) / d.seg[1])};
         for (int p = 0; p < 3; ++p) {
@@ -400,7 +456,11 @@ inline ch_status plan_dt(Plan& P, double dt)
         }
     }
     for (int p = 0; p < 3; ++p) P.ntask[p] = (int)t0[p];
-    P.lds[0] = xlds(R, zc);
+    if (P.xseg) {
+        int S = 0;
+        for (int b = 0; b < P.nbox; ++b) S = std::max(S, P.boxes[b].xs);
+        P.lds[0] = chd::x_seg_layout(S, P.zc, P.tw_max, (int)sT, (int)sA).total;
+    }
     P.lds[1] = (size_t)chd::line_tile_rows(P.seg_max[0] + 2 * P.tw_max) * P.lanes * sA;
     P.lds[2] = (size_t)chd::line_tile_rows(P.seg_max[1] + 2 * P.tw_max) * P.lanes * sA;
     for (int p = 1; p < 3; ++p)

@@ -15,7 +15,7 @@
 //   OUT_DIR/C.bin: packed float64 result; OUT_DIR/mass.txt: per-box mass;
 //   OUT_DIR/plan.txt: x_rows seg_cap chains tw_max acc64 ntask0..2 lds0..2 z_chunk xrow
 //           (xrow: 0 general x program, 1 row program, 2 row program with
-//           several rows in some task)
+//           several rows in some task, 3 segmented program)
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -86,15 +86,35 @@ static void run_xrow(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T
     }
 }
 
+// the segmented x-pass program: E read from Ein, written to Eout
+template <typename T, typename A>
+static void run_xseg(chp::Plan& P, int k, T* C, const T* Ein, T* Eout, T* qa, const T* u,
+                     const T* v, const T* w)
+{
+    const chd::BoxDesc* boxes = P.boxes.data();
+    const chd::PassArgs pa = chp::pass_args(P, k, 0);
+    chd::CpuExec ex{P.x_threads};
+    std::vector<chd::XSegState<T, A>> st(ex.nth);
+    for (int task = 0; task < P.ntask[0]; ++task) {
+        unsigned char* lds = (unsigned char*)malloc(P.lds[0]);
+        memset(lds, 0xff, P.lds[0]);
+        const int b = chd::find_box(boxes, P.nbox, chd::PASS_X, task);
+        chd::pass_x_seg_program<T, A>(ex, st.data(), boxes[b], pa, task, C, u, v, w, Ein, Eout,
+                                      qa, lds);
+        free(lds);
+    }
+}
+
 template <typename T, typename A>
 static void run(chp::Plan& P, T* C, T* E, T* qa, T* qb, const T* u, const T* v, const T* w,
-                int nsteps)
+                int nsteps, T* E2)
 {
     const chd::BoxDesc* boxes = P.boxes.data();
     for (int s = 0; s < nsteps; ++s)
         for (int k = 0; k < 3; ++k) {
             // pass x
-            if (P.xrow) run_xrow<T, A>(P, k, C, E, qa, u, v, w);
+            if (P.xseg) run_xseg<T, A>(P, k, C, k == 2 ? E2 : E, k == 1 ? E2 : E, qa, u, v, w);
+            else if (P.xrow) run_xrow<T, A>(P, k, C, E, qa, u, v, w);
             else if (P.mi == 1) run_x<T, A, 1>(P, k, C, E, qa, u, v, w);
             else run_x<T, A, 2>(P, k, C, E, qa, u, v, w);
             // passes y, z
@@ -166,15 +186,16 @@ static int go(chp::Plan& P, const std::string& in, const std::string& out, int n
     T* C = dev_copy<T>(C0);
     std::vector<double> zero(P.tot[0], 0.0);
     T* E = dev_copy<T>(zero);
+    T* E2 = dev_copy<T>(zero);
     T* qa = dev_copy<T>(zero);
     T* qb = dev_copy<T>(zero);
     T* u = dev_copy<T>(read_bin(in + "/u.bin", P.tot[1]));
     T* v = dev_copy<T>(read_bin(in + "/v.bin", P.tot[2]));
     T* w = dev_copy<T>(read_bin(in + "/w.bin", P.tot[3]));
     if (P.e25) run_e25<T>(P, C, E, qa, u, v, w, nsteps);
-    else if (P.prec == CH_FP64) run<T, T>(P, C, E, qa, qb, u, v, w, nsteps);
-    else if (P.acc64) run<T, double>(P, C, E, qa, qb, u, v, w, nsteps);
-    else run<T, float>(P, C, E, qa, qb, u, v, w, nsteps);
+    else if (P.prec == CH_FP64) run<T, T>(P, C, E, qa, qb, u, v, w, nsteps, E2);
+    else if (P.acc64) run<T, double>(P, C, E, qa, qb, u, v, w, nsteps, E2);
+    else run<T, float>(P, C, E, qa, qb, u, v, w, nsteps, E2);
     std::vector<double> res(P.tot[0]);
     for (int64_t i = 0; i < P.tot[0]; ++i) res[i] = double(C[i]);
     FILE* f = fopen((out + "/C.bin").c_str(), "wb");
@@ -187,9 +208,9 @@ static int go(chp::Plan& P, const std::string& in, const std::string& out, int n
     f = fopen((out + "/plan.txt").c_str(), "w");
     fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu %d %d\n", P.x_rows, P.seg_cap, P.yz_threads,
             P.tw_max, P.acc64 ? 1 : 0, P.ntask[0], P.ntask[1], P.ntask[2], P.lds[0], P.lds[1],
-            P.lds[2], P.zc, P.xrow ? (P.xrow_multi ? 2 : 1) : 0);
+            P.lds[2], P.zc, P.xseg ? 3 : P.xrow ? (P.xrow_multi ? 2 : 1) : 0);
     fclose(f);
-    free(C); free(E); free(qa); free(qb); free(u); free(v); free(w);
+    free(C); free(E); free(E2); free(qa); free(qb); free(u); free(v); free(w);
     return 0;
 }
 

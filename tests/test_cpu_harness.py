@@ -251,3 +251,33 @@ def test_line_fast_path_equals_the_elementwise_path(shape, bc, opts, prec, solve
     slow, ms, _ = run_emu([b], dt, 2, prec=prec, solve=solve, line_vec=False, **opts)
     assert np.array_equal(fast[0], slow[0]) and mf == ms
     assert _rel(fast[0], _oracle(b, dt, 2)) < (1e-12 if prec == 0 else 2e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape,dt,zc", [
+    ((8, 8, 1100), 2e-6, 0),       # five segments of 220
+    ((9, 8, 1093), 4e-5, 3),       # long warm-ups: shorter, more segments, ragged last one
+    ((8, 1, 1200), 1e-6, 2),       # degenerate y
+])
+def test_segmented_program_for_long_lines(shape, dt, zc, prec):
+    """x lines longer than a work-group (periodic x): one row and one x
+    segment per task, solved from computed warm-ups, E double-buffered; against
+    the oracle and the general program (two cells per thread)."""
+    b = _box(shape, seed=61, amp=1.0, drops=False)
+    ref = _oracle(b, dt, 2)
+    seg, ms, plan = run_emu([b], dt, 2, prec=prec, z_chunk=zc)
+    assert plan["xrow"] == 3
+    gen, mg, plan_g = run_emu([b], dt, 2, prec=prec, z_chunk=zc, x_general=1)
+    assert plan_g["xrow"] == 0
+    tol = 1e-12 if prec == 0 else 2e-6
+    assert _rel(seg[0], ref) < tol and _rel(gen[0], ref) < tol
+    if prec == 0:
+        assert _rel(seg[0], gen[0]) < 1e-13
+        assert abs(ms[0] - oracle.mass(ref, b["h"])) < 1e-12 * abs(ms[0])
+
+
+def test_long_lines_with_x_walls_take_the_general_program():
+    b = _box((8, 8, 1100), bc=(1, 0, 0), seed=62, amp=1.0, drops=False)
+    out, _, plan = run_emu([b], 2e-6, 1)
+    assert plan["xrow"] == 0
+    assert _rel(out[0], _oracle(b, 2e-6, 1)) < 1e-12
