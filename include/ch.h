@@ -373,6 +373,15 @@ ch_status ch_batch_profile_read(ch_batch* b, int kernel, double* total_ms, int64
  * over. */
 ch_status ch_get_config(const ch_state* s, int cfg[8]);
 
+/* Which x-pass program the plan of a state (batch) runs, for reports and
+ * tests (the arithmetic is the same in all): *kind = 0 the general program,
+ * 1 the row program (one cell per thread, the y stencil in registers), 2 the
+ * row program with several rows in some task, 3 the segmented program (x
+ * lines longer than a work-group).  CH_EINVAL before the first plan (no
+ * step yet and no dt_hint) or on a null output. */
+ch_status ch_get_x_program(const ch_state* s, int* kind);
+ch_status ch_batch_get_x_program(const ch_batch* b, int* kind);
+
 #ifdef __cplusplus
 }
 #endif

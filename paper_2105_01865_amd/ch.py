@@ -122,7 +122,12 @@ SIGNATURES = {
     "ch_batch_profile_enable": (_I, [_VP, _I]),
     "ch_batch_profile_read": (_I, [_VP, _I, _PD, _PI64]),
     "ch_get_config": (_I, [_VP, ctypes.POINTER(ctypes.c_int)]),
+    "ch_get_x_program": (_I, [_VP, ctypes.POINTER(ctypes.c_int)]),
+    "ch_batch_get_x_program": (_I, [_VP, ctypes.POINTER(ctypes.c_int)]),
 }
+
+# x-pass program kinds reported by ch_get_x_program
+X_PROGRAMS = {0: "general", 1: "row", 2: "row, several rows per task", 3: "segmented"}
 
 
 def lib():
@@ -379,6 +384,12 @@ class State(_StreamMixin):
         return dict(x_rows=cfg[0], seg=cfg[1], yz_threads=cfg[2], tw=list(cfg[3:6]),
                     acc64=bool(cfg[6]), z_chunk=cfg[7])
 
+    def x_program(self):
+        """The x-pass program of the current plan (a key of X_PROGRAMS)."""
+        k = ctypes.c_int()
+        _check(lib().ch_get_x_program(self._h, ctypes.byref(k)))
+        return k.value
+
     def close(self):
         if getattr(self, "_h", None):
             lib().ch_destroy(self._h)
@@ -512,6 +523,12 @@ class Batch(_StreamMixin):
         _check(lib().ch_batch_profile_read(self._h, KERNELS.get(kernel, kernel),
                                            ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def x_program(self):
+        """The x-pass program of the current plan (a key of X_PROGRAMS)."""
+        k = ctypes.c_int()
+        _check(lib().ch_batch_get_x_program(self._h, ctypes.byref(k)))
+        return k.value
 
     def close(self):
         if getattr(self, "_h", None):

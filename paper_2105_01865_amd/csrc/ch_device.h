@@ -388,14 +388,15 @@ CH_HD T d4_d(T D1, T D2, T D3, T D4)
 //   b1: backward warm-up over [e, e + tw) (reads w)       -> state
 //   b2: backward over the chunk, w -> y in place
 // ---------------------------------------------------------------------------
-template <typename A>
-struct LineState {
-    A s1, s2;
-};
-
 struct Chunk {
     int l, c0, fend, bend;
     bool live;
+};
+
+template <typename A>
+struct LineState {
+    A s1, s2;
+    Chunk ch;   // the thread's (line, chunk), where a pass keeps it across phases
 };
 
 // most chunks per line: every x-pass work-group has at least nx threads per
@@ -435,17 +436,54 @@ CH_HD Chunk line_chunk(int tid, int nl, int n, int tw, int cap)
     return line_chunk_k(tid, nl, n, tw, line_chunk_len(n, tw, cap));
 }
 
+// Line pitch of an x solve tile whose lines hold `span` positions: odd, so
+// that lanes walking different lines at the same position hit different
+// LDS banks.
+CH_HD int x_tile_pitch(int span) { return span | 1; }
+
+// Halo positions -tw .. -1 and n .. n+tw-1 of the nl lines of an x solve tile
+// (element (p, l) at tile[l * pitch + p + tw], a line contiguous) from the
+// periodic or reflected continuation: lane q of each wave maps halo position
+// q (and q + 64, ...) once, and the waves split the lines.
+template <typename A>
+CH_HD void x_tile_halos(int tid, int nth, A* tile, int pitch, int nl, int n, int tw, int bc)
+{
+    const int lane = tid & 63, wv = tid >> 6, nw = (nth + 63) >> 6;
+    for (int q = lane; q < 2 * tw; q += 64) {
+        const int pp = q < tw ? q - tw : n + q - tw;
+        const int src = map_idx(pp, n, bc) + tw;
+        for (int l = wv; l < nl; l += nw) tile[l * pitch + pp + tw] = tile[l * pitch + src];
+    }
+}
+
 // The recurrences walk the tile in batches of LB values: the batch's loads
 // are independent of the chain and go out together.
 constexpr int LB = 8;
 
-template <typename A>
+// Tile layouts of the line recurrences.  PS == 0: element (p, l) at
+// tile[(p + tw) * pitch + l] (the lines across the fastest index: the y / z
+// passes' column tiles).  PS > 0: element (p, l) at
+// tile[l * pitch + (p + tw) * PS] (a line contiguous: the x solve tiles,
+// whose position steps then fold into the LDS instructions' offsets).
+template <int PS>
+CH_HD int line_origin(int l, int tw, int pitch)
+{
+    return PS == 0 ? tw * pitch + l : l * pitch + tw * PS;
+}
+template <int PS>
+CH_HD int line_step(int pitch)
+{
+    return PS == 0 ? pitch : PS;
+}
+
+template <typename A, int PS = 0>
 CH_HD void line_f1(const Chunk& ch, const A* tile, int pitch, int tw, A a1, A a2, A ic,
                    LineState<A>& st)
 {
     A w1 = A(0), w2 = A(0);
     if (ch.live) {
-        const A* base = tile + tw * pitch + ch.l;
+        const A* base = tile + line_origin<PS>(ch.l, tw, pitch);
+        pitch = line_step<PS>(pitch);
         int p = ch.c0 - tw;
         for (; p + LB <= ch.c0; p += LB) {
             A v[LB];
@@ -468,13 +506,14 @@ CH_HD void line_f1(const Chunk& ch, const A* tile, int pitch, int tw, A a1, A a2
     st.s2 = w2;
 }
 
-template <typename A>
+template <typename A, int PS = 0>
 CH_HD void line_f2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2, A ic,
                    const LineState<A>& st)
 {
     if (!ch.live) return;
     A w1 = st.s1, w2 = st.s2;
-    A* base = tile + tw * pitch + ch.l;
+    A* base = tile + line_origin<PS>(ch.l, tw, pitch);
+    pitch = line_step<PS>(pitch);
     int p = ch.c0;
     for (; p + LB <= ch.fend; p += LB) {
         A v[LB];
@@ -498,13 +537,14 @@ CH_HD void line_f2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2, A ic
     }
 }
 
-template <typename A>
+template <typename A, int PS = 0>
 CH_HD void line_b1(const Chunk& ch, const A* tile, int pitch, int tw, A a1, A a2,
                    LineState<A>& st)
 {
     A y1 = A(0), y2 = A(0);
     if (ch.live) {
-        const A* base = tile + tw * pitch + ch.l;
+        const A* base = tile + line_origin<PS>(ch.l, tw, pitch);
+        pitch = line_step<PS>(pitch);
         int p = ch.bend + tw - 1;
         for (; p - LB + 1 >= ch.bend; p -= LB) {
             A v[LB];
@@ -527,13 +567,14 @@ CH_HD void line_b1(const Chunk& ch, const A* tile, int pitch, int tw, A a1, A a2
     st.s2 = y2;
 }
 
-template <typename A>
+template <typename A, int PS = 0>
 CH_HD void line_b2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2,
                    const LineState<A>& st)
 {
     if (!ch.live) return;
     A y1 = st.s1, y2 = st.s2;
-    A* base = tile + tw * pitch + ch.l;
+    A* base = tile + line_origin<PS>(ch.l, tw, pitch);
+    pitch = line_step<PS>(pitch);
     int p = ch.bend - 1;
     for (; p - LB + 1 >= ch.c0; p -= LB) {
         A v[LB];
@@ -575,8 +616,9 @@ CH_HD void line_b2(const Chunk& ch, A* tile, int pitch, int tw, A a1, A a2,
 //                                    columns -3 .. nx+2
 //   fx: rmax x (nx_max + 1) T        flux through x face f of each row
 //   fy: (rmax + 1) x nx_max T        flux through y face y0 + r
-//   tb: (nx_max + 2 tw_max) x (rmax zcmax + 1) A   RHS -> solve tile, line
-//                                    zs * rows + r at column zs * rows + r
+//   tb: rmax zcmax x pitch A         RHS -> solve tile: line zs * rows + r,
+//                                    positions -tw .. nx+tw-1 contiguous
+//                                    (pitch: nx_max + 2 tw_max, made odd)
 // ---------------------------------------------------------------------------
 struct XLayout {
     size_t pb, mb, fx, fy, tb, zm, zp, total;  // byte offsets and total size
@@ -595,7 +637,7 @@ CH_HD XLayout x_layout(int nx_max, int rmax, int zcmax, int tw_max, int sT, int 
     L.mbp = nx_max + 2;
     L.fxp = nx_max + 1;
     L.fyp = nx_max;
-    L.tbp = rmax * zcmax + 1;
+    L.tbp = x_tile_pitch(nx_max + 2 * tw_max);
     L.pb = 0;
     L.mb = al16(L.pb + (size_t)(rmax + 6) * L.pbp * sT);
     L.fx = al16(L.mb + (size_t)(rmax + 2) * L.mbp * sT);
@@ -607,7 +649,7 @@ CH_HD XLayout x_layout(int nx_max, int rmax, int zcmax, int tw_max, int sT, int 
         L.total = al16(L.zp + (size_t)L.mbp * sT);
     } else {
         L.zm = L.zp = 0;
-        L.total = al16(L.tb + (size_t)(nx_max + 2 * tw_max) * L.tbp * sA);
+        L.total = al16(L.tb + (size_t)rmax * zcmax * L.tbp * sA);
     }
     return L;
 }
@@ -823,7 +865,7 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
                 T rhs = gdt * e - bdt * s.pb4[m];
                 if (pa.e_mode != 0) rhs += rdt * s.eold[m];
                 if (pa.e_mode != 2) Ez.store(s.col[m], e);
-                tb[(x + tw) * L.tbp + zs * rows + r] = A(rhs);
+                tb[(zs * rows + r) * L.tbp + x + tw] = A(rhs);
             }
         }
     };
@@ -1061,31 +1103,27 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
         rhs_plane(s, t.nzc - 1, yz, cc);
     });
     if constexpr (E25) return;   // no solve: the new C is written
-    // ---- halos of the solve tile
+    // ---- halos of the solve tile; each thread's (line, chunk) of the solve
     ex.phase([&](int tid) {
-        const int span = 2 * tw;
-        for (int j = tid; j < nlines * span; j += nth) {
-            const int ln = j / span, q = j - ln * span;
-            const int pp = q < tw ? q - tw : nx + q - tw;
-            tb[(pp + tw) * L.tbp + ln] = tb[(map_idx(pp, nx, bcx) + tw) * L.tbp + ln];
-        }
+        x_tile_halos<A>(tid, nth, tb, L.tbp, nlines, nx, tw, bcx);
+        st[ex.slot(tid)].ls.ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
     });
     // ---- x solve of all lines at once
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
-        line_f1<A>(ch, tb, L.tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+        LineState<A>& ls = st[ex.slot(tid)].ls;
+        line_f1<A, 1>(ls.ch, tb, L.tbp, tw, a1, a2, ic, ls);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
-        line_f2<A>(ch, tb, L.tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+        LineState<A>& ls = st[ex.slot(tid)].ls;
+        line_f2<A, 1>(ls.ch, tb, L.tbp, tw, a1, a2, ic, ls);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
-        line_b1<A>(ch, tb, L.tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+        LineState<A>& ls = st[ex.slot(tid)].ls;
+        line_b1<A, 1>(ls.ch, tb, L.tbp, tw, a1, a2, ls);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
-        line_b2<A>(ch, tb, L.tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+        LineState<A>& ls = st[ex.slot(tid)].ls;
+        line_b2<A, 1>(ls.ch, tb, L.tbp, tw, a1, a2, ls);
     });
     // ---- store q, plane by plane, x fastest
     ex.phase([&](int tid) {
@@ -1096,7 +1134,7 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
             for (int m = 0; m < MI; ++m) {
                 if (s.rx[m] < 0) continue;
                 const int r = s.rx[m] >> 16, x = s.rx[m] & 0xffff;
-                Qz.store(s.col[m], T(tb[(x + tw) * L.tbp + zs * rows + r]));
+                Qz.store(s.col[m], T(tb[(zs * rows + r) * L.tbp + x + tw]));
             }
         }
     });
@@ -1125,7 +1163,9 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
 //   cr: rows x (nx + 6) T      C of the owned rows, columns -3 .. nx+2
 //   mr: rows x (nx + 2) T      psi'(C) of the owned rows, columns -1 .. nx
 //   fr: rows x (nx + 1) T      flux through x face f of each row
-//   tb: (nx + 2 tw_max) x (rows zc + 1) A    RHS -> solve tile, line zs rows + r
+//   tb: rows zc x pitch A      RHS -> solve tile: line zs rows + r, positions
+//                              -tw .. nx+tw-1 contiguous (pitch nx + 2 tw_max,
+//                              made odd)
 // ---------------------------------------------------------------------------
 struct XRowLayout {
     size_t cr, mr, fr, tb, total;   // byte offsets and total size
@@ -1138,12 +1178,12 @@ CH_HD XRowLayout x_row_layout(int nx, int rows, int zc, int tw_max, int sT, int 
     L.crp = nx + 6;
     L.mrp = nx + 2;
     L.frp = nx + 1;
-    L.tbp = rows * zc + 1;
+    L.tbp = x_tile_pitch(nx + 2 * tw_max);
     L.cr = 0;
     L.mr = al16(L.cr + (size_t)rows * L.crp * sT);
     L.fr = al16(L.mr + (size_t)rows * L.mrp * sT);
     L.tb = al16(L.fr + (size_t)rows * L.frp * sT);
-    L.total = al16(L.tb + (size_t)(nx + 2 * tw_max) * L.tbp * sA);
+    L.total = al16(L.tb + (size_t)rows * zc * L.tbp * sA);
     return L;
 }
 
@@ -1283,7 +1323,7 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
         if (live) {
             if (pa.e_mode != 2)
                 Er.store((uint32_t)x * sT + (MR ? s.ro : yoff), (uint32_t)(z0 + zs) * pbytes, e);
-            tb[(x + tw) * tbp + zs * rows + r] = A(rhs);
+            tb[(zs * rows + r) * tbp + x + tw] = A(rhs);
         }
     };
 
@@ -1423,31 +1463,28 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
         rhs_plane(s, r, x, live, nzc - 1);
     });
     const int nlines = rows * nzc;
-    // ---- halos of the solve tile (periodic or reflected continuation)
+    // ---- halos of the solve tile (periodic or reflected continuation); each
+    //      thread's (line, chunk) of the x solve
     ex.phase([&](int tid) {
-        const int span = 2 * tw;
-        for (int j = tid; j < nlines * span; j += nth) {
-            const int ln = j / span, q = j - ln * span;
-            const int pp = q < tw ? q - tw : nx + q - tw;
-            tb[(pp + tw) * tbp + ln] = tb[(map_idx(pp, nx, bcx) + tw) * tbp + ln];
-        }
+        x_tile_halos<A>(tid, nth, tb, tbp, nlines, nx, tw, bcx);
+        st[ex.slot(tid)].ls.ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
     });
     // ---- x solve of the task's lines
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
-        line_f1<A>(ch, tb, tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+        LineState<A>& ls = st[ex.slot(tid)].ls;
+        line_f1<A, 1>(ls.ch, tb, tbp, tw, a1, a2, ic, ls);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
-        line_f2<A>(ch, tb, tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+        LineState<A>& ls = st[ex.slot(tid)].ls;
+        line_f2<A, 1>(ls.ch, tb, tbp, tw, a1, a2, ic, ls);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
-        line_b1<A>(ch, tb, tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+        LineState<A>& ls = st[ex.slot(tid)].ls;
+        line_b1<A, 1>(ls.ch, tb, tbp, tw, a1, a2, ls);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nlines, nx, tw, X_CHAINS);
-        line_b2<A>(ch, tb, tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+        LineState<A>& ls = st[ex.slot(tid)].ls;
+        line_b2<A, 1>(ls.ch, tb, tbp, tw, a1, a2, ls);
     });
     // ---- q out, plane by plane
     ex.phase([&](int tid) {
@@ -1456,7 +1493,7 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
         if (!cell(s, tid, &r, &x)) return;
         const uint32_t o = (uint32_t)x * sT + (MR ? s.ro : yoff);
         for (int zs = 0; zs < nzc; ++zs)
-            Qr.store(o, (uint32_t)(z0 + zs) * pbytes, T(tb[(x + tw) * tbp + zs * rows + r]));
+            Qr.store(o, (uint32_t)(z0 + zs) * pbytes, T(tb[(zs * rows + r) * tbp + x + tw]));
     });
 }
 
@@ -1480,7 +1517,8 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
 //   cr: NE + 7 T    C at extended positions -3 .. NE + 3
 //   mr: NE + 3 T    psi'(C) at -1 .. NE + 1
 //   fr: NE + 1 T    flux through the low x face of position q, 0 .. NE
-//   tb: (S + 2 tw_max) x (zc + 1) A    RHS -> solve tile, line zs
+//   tb: zc x pitch A    RHS -> solve tile: line zs, positions -tw .. S+tw-1
+//                       contiguous (pitch S + 2 tw_max, made odd)
 // ---------------------------------------------------------------------------
 struct XSegLayout {
     size_t cr, mr, fr, tb, total;   // byte offsets and total size
@@ -1491,12 +1529,12 @@ CH_HD XSegLayout x_seg_layout(int S, int zc, int tw_max, int sT, int sA)
 {
     const int ne = S + 2 * tw_max;
     XSegLayout L;
-    L.tbp = zc + 1;
+    L.tbp = x_tile_pitch(S + 2 * tw_max);
     L.cr = 0;
     L.mr = al16(L.cr + (size_t)(ne + 7) * sT);
     L.fr = al16(L.mr + (size_t)(ne + 3) * sT);
     L.tb = al16(L.fr + (size_t)(ne + 1) * sT);
-    L.total = al16(L.tb + (size_t)(S + 2 * tw_max) * L.tbp * sA);
+    L.total = al16(L.tb + (size_t)zc * L.tbp * sA);
     return L;
 }
 
@@ -1594,7 +1632,7 @@ CH_HD void pass_x_seg_program(X& ex, XSegState<T, A>* st, const BoxDesc& bd, con
         if (tid == q && rel >= -tw && rel < S + tw) {
             if (pa.e_mode != 2 && rel >= 0 && rel < S)
                 PlaneRef<T>(Eob + (int64_t)(z0 + zs) * plane, pbytes).store(cellb(q) + yoff, e);
-            tb[(rel + tw) * tbp + zs] = A(rhs);
+            tb[zs * tbp + rel + tw] = A(rhs);
         }
     };
 
@@ -1691,20 +1729,21 @@ CH_HD void pass_x_seg_program(X& ex, XSegState<T, A>* st, const BoxDesc& bd, con
     });
     // ---- solve the segment's lines from the computed warm-ups
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nzc, S, tw, X_CHAINS);
-        line_f1<A>(ch, tb, tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+        LineState<A>& ls = st[ex.slot(tid)].ls;
+        ls.ch = line_chunk(tid, nzc, S, tw, X_CHAINS);
+        line_f1<A, 1>(ls.ch, tb, tbp, tw, a1, a2, ic, ls);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nzc, S, tw, X_CHAINS);
-        line_f2<A>(ch, tb, tbp, tw, a1, a2, ic, st[ex.slot(tid)].ls);
+        LineState<A>& ls = st[ex.slot(tid)].ls;
+        line_f2<A, 1>(ls.ch, tb, tbp, tw, a1, a2, ic, ls);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nzc, S, tw, X_CHAINS);
-        line_b1<A>(ch, tb, tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+        LineState<A>& ls = st[ex.slot(tid)].ls;
+        line_b1<A, 1>(ls.ch, tb, tbp, tw, a1, a2, ls);
     });
     ex.phase([&](int tid) {
-        const Chunk ch = line_chunk(tid, nzc, S, tw, X_CHAINS);
-        line_b2<A>(ch, tb, tbp, tw, a1, a2, st[ex.slot(tid)].ls);
+        LineState<A>& ls = st[ex.slot(tid)].ls;
+        line_b2<A, 1>(ls.ch, tb, tbp, tw, a1, a2, ls);
     });
     // ---- q out at the segment's cells
     ex.phase([&](int tid) {
@@ -1713,7 +1752,7 @@ CH_HD void pass_x_seg_program(X& ex, XSegState<T, A>* st, const BoxDesc& bd, con
         const uint32_t o = cellb(tid) + yoff;
         for (int zs = 0; zs < nzc; ++zs)
             PlaneRef<T>(Qb + (int64_t)(z0 + zs) * plane, pbytes)
-                .store(o, T(tb[(rel + tw) * tbp + zs]));
+                .store(o, T(tb[zs * tbp + rel + tw]));
     });
 }
 

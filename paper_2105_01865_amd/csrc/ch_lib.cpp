@@ -1118,6 +1118,20 @@ ch_status ch_get_config(const ch_state* s, int cfg[8])
     return CH_OK;
 }
 
+static ch_status x_program(const chp::Plan& P, int* kind)
+{
+    if (!kind) return fail(CH_EINVAL, "null output");
+    if (std::isnan(P.dt)) return fail(CH_EINVAL, "no plan yet: step once or pass dt_hint");
+    *kind = P.xseg ? 3 : P.xrow ? (P.xrow_multi ? 2 : 1) : 0;
+    return CH_OK;
+}
+
+ch_status ch_get_x_program(const ch_state* s, int* kind)
+{
+    CHECK_STATE(s);
+    return x_program(s->e.P, kind);
+}
+
 // ---- batch -----------------------------------------------------------------
 ch_status ch_batch_create(int nbox, const ch_grid* g, const double* Cn, const double* Pe,
                           const ch_psi* psi, const ch_bc* bc, const ch_opts* opt,
@@ -1211,6 +1225,12 @@ ch_status ch_batch_profile_read(ch_batch* b, int kernel, double* total_ms, int64
 {
     CHECK_STATE(b);
     return profile_read(b->e, kernel, total_ms, launches);
+}
+
+ch_status ch_batch_get_x_program(const ch_batch* b, int* kind)
+{
+    CHECK_STATE(b);
+    return x_program(b->e.P, kind);
 }
 
 // ---- multiple resolution -----------------------------------------------------

@@ -115,6 +115,22 @@ def test_fp64_parity_tiles_walls_ragged(shape, bc, opts):
         assert rel(got32, ref) <= 5e-6
 
 
+def test_x_program_reported():
+    """ch_get_x_program names the x program of the plan (the same arithmetic
+    in all of them): general, row, several rows per task, segmented."""
+    cases = [((8, 8, 256), {}, 1), ((8, 12, 24), {}, 2), ((8, 8, 1100), {}, 3),
+             ((8, 8, 256), dict(x_general=True), 0)]
+    for shape, opts, kind in cases:
+        C, u, v, w, h = _case(shape, seed=7)
+        s = ch.State(shape, h, h, 0.9 / h, stream=torch.cuda.Stream(), **opts)
+        with pytest.raises(ch.CHError):
+            s.x_program()   # no plan before the first step
+        s.set_field(dev(C))
+        s.step(dev(u), dev(v), dev(w), 1e-6, 1)
+        assert s.x_program() == kind, (shape, opts)
+        s.close()
+
+
 def test_fp64_parity_large_dt_long_warmup():
     C, u, v, w, h = _case((32, 32, 32), seed=3, amp=0.5)
     got, cfg = run_gpu(C, u, v, w, h, h, 0.9 / h, 0.02, 1)
