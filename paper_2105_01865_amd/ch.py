@@ -127,7 +127,8 @@ SIGNATURES = {
 }
 
 # x-pass program kinds reported by ch_get_x_program
-X_PROGRAMS = {0: "general", 1: "row", 2: "row, several rows per task", 3: "segmented"}
+X_PROGRAMS = {0: "general", 1: "row", 2: "row, several rows per task", 3: "segmented",
+              4: "row, one-row and several-row boxes in two launches"}
 
 
 def lib():

@@ -1163,13 +1163,15 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
 //   cr: rows x (nx + 6) T      C of the owned rows, columns -3 .. nx+2
 //   mr: rows x (nx + 2) T      psi'(C) of the owned rows, columns -1 .. nx
 //   fr: rows x (nx + 1) T      flux through x face f of each row
+//   fy: rows x nx T            (several rows) flux through the low y face of
+//                              each cell, which is the high face of the row below
 //   tb: rows zc x pitch A      RHS -> solve tile: line zs rows + r, positions
 //                              -tw .. nx+tw-1 contiguous (pitch nx + 2 tw_max,
 //                              made odd)
 // ---------------------------------------------------------------------------
 struct XRowLayout {
-    size_t cr, mr, fr, tb, total;   // byte offsets and total size
-    int crp, mrp, frp, tbp;         // pitches (elements)
+    size_t cr, mr, fr, fy, tb, total;   // byte offsets and total size
+    int crp, mrp, frp, tbp;             // pitches (elements)
 };
 
 CH_HD XRowLayout x_row_layout(int nx, int rows, int zc, int tw_max, int sT, int sA)
@@ -1182,7 +1184,8 @@ CH_HD XRowLayout x_row_layout(int nx, int rows, int zc, int tw_max, int sT, int 
     L.cr = 0;
     L.mr = al16(L.cr + (size_t)rows * L.crp * sT);
     L.fr = al16(L.mr + (size_t)rows * L.mrp * sT);
-    L.tb = al16(L.fr + (size_t)rows * L.frp * sT);
+    L.fy = al16(L.fr + (size_t)rows * L.frp * sT);
+    L.tb = al16(L.fy + (rows > 1 ? (size_t)rows * nx * sT : 0));
     L.total = al16(L.tb + (size_t)rows * zc * L.tbp * sA);
     return L;
 }
@@ -1197,6 +1200,8 @@ struct XRowState {
     T fzl;                    // flux through the low z face
     T eold;                   // E of the previous substage at the plane whose RHS is next
     T py, pz, plap, pb4;      // y and z flux differences, Laplacian of psi', sum of D4
+    T fyl, fyh;               // several rows per task: the fluxes through the low y
+                              // face and (last row of the task) the high one
     T nc, nu, nvl, nvh, nwh, ne, nyh[6];   // the next plane's loads
     int cxp, cxm;             // halo columns of the C and psi' rows fed by the
                               // owned column (or the column itself)
@@ -1227,6 +1232,7 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
     T* crb = reinterpret_cast<T*>(smem + L.cr) + 3;   // row r: crb[r crp + x], -3 <= x < nx + 3
     T* mrb = reinterpret_cast<T*>(smem + L.mr) + 1;   // row r: mrb[r mrp + x], -1 <= x < nx + 1
     T* frb = reinterpret_cast<T*>(smem + L.fr);       // row r: frb[r frp + f], 0 <= f <= nx
+    T* fyb = reinterpret_cast<T*>(smem + L.fy);       // row r: fyb[r nx + x] (MR)
     A* tb = reinterpret_cast<A*>(smem + L.tb);
     const int tbp = L.tbp;
     // bytes of a plane of C (E, q and w too), of u and of v
@@ -1312,10 +1318,13 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
             for (int hr = 0; hr < 6; ++hr) s.nyh[hr] = Cr(xb, zo + hoff[hr]);
         }
     };
-    // RHS of plane zs of the owned cell into the solve tile (and E out)
+    // RHS of plane zs of the owned cell into the solve tile (and E out); with
+    // several rows per task the high y face of a row below the last is the
+    // low face of the row above, formed there
     auto rhs_plane = [&](XRowState<T, A>& s, int r, int x, bool live, int zs) {
         const T* fr = frb + r * L.frp;
         const T fhi = x + 1 < nx ? fr[x + 1] : fr[bcx == 0 ? 0 : nx];
+        if constexpr (MR) s.py = (r + 1 < rows ? fyb[(r + 1) * nx + x] : s.fyh) - s.fyl;
         const T adv = ((fhi - fr[x]) + s.py) + s.pz;
         const T e = -adv * inv_h + s.plap * lap_s;
         T rhs = gdt * e - bdt * s.pb4;
@@ -1422,7 +1431,9 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
                 fr[nx] = uw * face_weno<T>(uw, row[-2], row[-1], row[0], row[1], row[2], row[3],
                                            epsw);
             }
-            // y: the owned column from the halo registers
+            // y: the owned column from the halo registers (with several rows per
+            // task, the high face only in the task's last row: the others take
+            // the low face of the row above from LDS when they form the RHS)
             {
                 const T yc[7] = {s.yh[0], s.yh[1], s.yh[2], s.c[3], s.yh[3], s.yh[4], s.yh[5]};
                 T dY[6];
@@ -1430,9 +1441,17 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
                 for (int j = 0; j < 6; ++j) dY[j] = yc[j + 1] - yc[j];
                 const T fyl =
                     flux_weno_d<T>(s.vl, dY[0], dY[1], dY[2], dY[3], dY[4], yc[2], yc[3], epsw);
-                const T fyh =
-                    flux_weno_d<T>(s.vh, dY[1], dY[2], dY[3], dY[4], dY[5], yc[3], yc[4], epsw);
-                s.py = fyh - fyl;
+                if constexpr (MR) {
+                    s.fyl = fyl;
+                    if (live) fyb[r * nx + x] = fyl;
+                    if (r + 1 == rows)
+                        s.fyh = flux_weno_d<T>(s.vh, dY[1], dY[2], dY[3], dY[4], dY[5], yc[3],
+                                               yc[4], epsw);
+                } else {
+                    const T fyh = flux_weno_d<T>(s.vh, dY[1], dY[2], dY[3], dY[4], dY[5], yc[3],
+                                                 yc[4], epsw);
+                    s.py = fyh - fyl;
+                }
                 s.pb4 += d4_d<T>(dY[1], dY[2], dY[3], dY[4]);
             }
             // z: planes z-1 .. z+3; the high face (the low one carries over)

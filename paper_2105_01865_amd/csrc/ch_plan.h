@@ -107,6 +107,15 @@ struct Plan {
     bool xrow = false;        // the x pass runs the one-cell-per-thread row program
     bool xrow_multi = false;  // ... with several rows in some task
     bool xseg = false;        // the x pass runs the segmented program (long lines)
+    // The x pass of a batch in which the row program gives some boxes one row
+    // per task and others several runs as two launches (nxl = 2): the
+    // one-row boxes in the one-cell-per-thread kernel, the others in the
+    // several-rows kernel, each over a box table of its own whose x tasks are
+    // numbered from 0 (the y and z passes keep the whole table).
+    int nxl = 1;
+    std::vector<chd::BoxDesc> xbox[2];
+    int x_ntask[2] = {0, 0};
+    size_t x_lds[2] = {0, 0};
     int tw_max = 0;
     int x_rows = 0, x_threads = 256, zc = 1, mi = 1, lanes = 32, yz_threads = 256, seg_cap = 0;
     int ntask[3] = {0, 0, 0};
@@ -456,6 +465,27 @@ inline ch_status plan_dt(Plan& P, double dt)
         }
     }
     for (int p = 0; p < 3; ++p) P.ntask[p] = (int)t0[p];
+    P.nxl = 1;
+    if (P.xrow && P.xrow_multi) {
+        for (int g = 0; g < 2; ++g) {
+            P.xbox[g].clear();
+            P.x_ntask[g] = 0;
+            P.x_lds[g] = 0;
+        }
+        for (int b = 0; b < P.nbox; ++b)
+            P.xbox[P.boxes[b].x_rows == 1 ? 0 : 1].push_back(P.boxes[b]);
+        if (!P.xbox[0].empty() && !P.xbox[1].empty()) {
+            P.nxl = 2;
+            for (int g = 0; g < 2; ++g)
+                for (chd::BoxDesc& d : P.xbox[g]) {
+                    d.task0[0] = P.x_ntask[g];
+                    P.x_ntask[g] += d.ntask[0];
+                    P.x_lds[g] = std::max(P.x_lds[g],
+                                          chd::x_row_layout(d.n[0], d.x_rows, d.zc, P.tw_max,
+                                                            (int)sT, (int)sA).total);
+                }
+        }
+    }
     if (P.xseg) {
         int S = 0;
         for (int b = 0; b < P.nbox; ++b) S = std::max(S, P.boxes[b].xs);

@@ -15,7 +15,8 @@
 //   OUT_DIR/C.bin: packed float64 result; OUT_DIR/mass.txt: per-box mass;
 //   OUT_DIR/plan.txt: x_rows seg_cap chains tw_max acc64 ntask0..2 lds0..2 z_chunk xrow
 //           (xrow: 0 general x program, 1 row program, 2 row program with
-//           several rows in some task, 3 segmented program)
+//           several rows in some task, 3 segmented program, 4 row program in
+//           two launches: one-row boxes and several-row boxes)
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -72,6 +73,26 @@ static void run_xrow(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T
     const chd::PassArgs pa = chp::pass_args(P, k, 0);
     chd::CpuExec ex{P.x_threads};
     std::vector<chd::XRowState<T, A>> st(ex.nth);
+    if (P.nxl == 2) {
+        // two launches: the one-row boxes, then those with several rows per task
+        for (int g = 0; g < 2; ++g) {
+            const chd::BoxDesc* gb = P.xbox[g].data();
+            const int nb = (int)P.xbox[g].size();
+            for (int task = 0; task < P.x_ntask[g]; ++task) {
+                unsigned char* lds = (unsigned char*)malloc(P.x_lds[g]);
+                memset(lds, 0xff, P.x_lds[g]);
+                const int b = chd::find_box(gb, nb, chd::PASS_X, task);
+                if (g == 1)
+                    chd::pass_x_row_program<T, A, true>(ex, st.data(), gb[b], pa, task, C, u, v,
+                                                        w, E, qa, lds);
+                else
+                    chd::pass_x_row_program<T, A, false>(ex, st.data(), gb[b], pa, task, C, u, v,
+                                                         w, E, qa, lds);
+                free(lds);
+            }
+        }
+        return;
+    }
     for (int task = 0; task < P.ntask[0]; ++task) {
         unsigned char* lds = (unsigned char*)malloc(P.lds[0]);
         memset(lds, 0xff, P.lds[0]);
@@ -208,7 +229,7 @@ static int go(chp::Plan& P, const std::string& in, const std::string& out, int n
     f = fopen((out + "/plan.txt").c_str(), "w");
     fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu %d %d\n", P.x_rows, P.seg_cap, P.yz_threads,
             P.tw_max, P.acc64 ? 1 : 0, P.ntask[0], P.ntask[1], P.ntask[2], P.lds[0], P.lds[1],
-            P.lds[2], P.zc, P.xseg ? 3 : P.xrow ? (P.xrow_multi ? 2 : 1) : 0);
+            P.lds[2], P.zc, P.xseg ? 3 : P.nxl == 2 ? 4 : P.xrow ? (P.xrow_multi ? 2 : 1) : 0);
     fclose(f);
     free(C); free(E); free(E2); free(qa); free(qb); free(u); free(v); free(w);
     return 0;

@@ -215,7 +215,8 @@ def test_row_program_in_a_batch(x_rows):
              _box((12, 14, 33), seed=33), _box((9, 9, 13), seed=34, bc=(0, 1, 1))]
     dt = 3e-4
     got, masses, plan = run_emu(boxes, dt, 2, x_rows=x_rows)
-    assert plan["xrow"] == 2
+    # the 40- and 33-wide boxes take one row per task at x_rows 1: two launches
+    assert plan["xrow"] == (4 if x_rows == 1 else 2)
     gen, _, _ = run_emu(boxes, dt, 2, x_rows=x_rows, x_general=1)
     for a, g, b in zip(got, gen, boxes):
         assert np.array_equal(a, g)
