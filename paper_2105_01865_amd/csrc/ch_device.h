@@ -330,6 +330,11 @@ struct GpuExec {
         __syncthreads();
     }
     __device__ __forceinline__ int slot(int) const { return 0; }
+    // the first thread of tid's wave, as a wave-uniform value
+    __device__ __forceinline__ int wave_base(int t) const
+    {
+        return __builtin_amdgcn_readfirstlane(t & ~63);
+    }
 };
 #endif
 
@@ -341,6 +346,7 @@ struct CpuExec {
         for (int t = 0; t < nth; ++t) f(t);
     }
     int slot(int t) const { return t; }
+    int wave_base(int t) const { return t & ~63; }
 };
 
 // upwinded WENO value on a face from the six values c[0..5] of cells
@@ -1149,15 +1155,21 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
 // work-group; narrow boxes of an ensemble take several) over nzc planes.
 // Every thread owns one cell and marches it up through the planes.  The
 // y-direction stencil of a cell is its own column, so the six halo rows of C
-// go straight into the thread's registers, and the y differences, both y
-// face fluxes and the y neighbours of psi'(C) are formed there: no row
-// exchanges y data through LDS.  LDS carries the owned rows (C and psi'(C)
-// with their x halos), the x face fluxes and the solve tile.  Each field of
-// the box is one buffer resource with 32-bit byte offsets (every field of
-// every box under 4 GiB): the plane goes into the scalar offset.  With one
-// row per task (MR false) every row offset is uniform and goes there too;
-// with several (MR true) the row offsets are per thread.  Threads past the
-// task's cells read its last cell and store nothing.
+// go straight into the thread's registers, and the y differences, the y face
+// fluxes and the y neighbours of psi'(C) are formed there.  LDS carries the
+// owned rows (C and psi'(C) with their x halos), the x face fluxes, the y
+// face fluxes that the rows of a task share, and the solve tile.  Each field
+// of the box is one buffer resource with 32-bit byte offsets (every field of
+// every box under 4 GiB): the plane goes into the scalar offset.  The row
+// mode RM says where the row offsets live:
+//   XR_ONE     one row per task: every row offset is uniform and goes there
+//              too;
+//   XR_THREAD  several rows per task, the row offsets per thread;
+//   XR_WAVE    several rows per task, each of whole waves (nx a multiple of
+//              64, or one row per task): the row is read from the wave's
+//              first thread, so its offsets are uniform per wave.
+// XR_THREAD and XR_WAVE map threads to cells alike and give the same bits.
+// Threads past the task's cells read its last cell and store nothing.
 //
 // LDS of a box (launch size: the largest over boxes):
 //   cr: rows x (nx + 6) T      C of the owned rows, columns -3 .. nx+2
@@ -1169,6 +1181,8 @@ CH_HD void pass_x_program(X& ex, XState<T, A, MI>* st, const BoxDesc& bd, const 
 //                              -tw .. nx+tw-1 contiguous (pitch nx + 2 tw_max,
 //                              made odd)
 // ---------------------------------------------------------------------------
+enum : int { XR_ONE = 0, XR_THREAD = 1, XR_WAVE = 2 };
+
 struct XRowLayout {
     size_t cr, mr, fr, fy, tb, total;   // byte offsets and total size
     int crp, mrp, frp, tbp;             // pitches (elements)
@@ -1200,8 +1214,9 @@ struct XRowState {
     T fzl;                    // flux through the low z face
     T eold;                   // E of the previous substage at the plane whose RHS is next
     T py, pz, plap, pb4;      // y and z flux differences, Laplacian of psi', sum of D4
-    T fyl, fyh;               // several rows per task: the fluxes through the low y
-                              // face and (last row of the task) the high one
+                              // (several rows per task, below the last row: py is
+                              // minus the low y face's flux until the RHS adds the
+                              // high one, which the row above forms)
     T nc, nu, nvl, nvh, nwh, ne, nyh[6];   // the next plane's loads
     int cxp, cxm;             // halo columns of the C and psi' rows fed by the
                               // owned column (or the column itself)
@@ -1213,12 +1228,13 @@ struct XRowState {
     LineState<A> ls;
 };
 
-template <typename T, typename A, bool MR, class X, bool VCONST = false>
+template <typename T, typename A, int RM, class X, bool VCONST = false>
 CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, const PassArgs& pa,
                               int task, const T* __restrict__ C, const T* __restrict__ U,
                               const T* __restrict__ V, const T* __restrict__ W,
                               T* __restrict__ E, T* __restrict__ Q, unsigned char* smem)
 {
+    constexpr bool MR = RM != XR_ONE;
     const XZTask t = xz_task(bd, task);
     const int nx = bd.n[0], ny = bd.n[1], nz = bd.n[2];
     const int fx = bd.nf[0], fy = bd.nf[1], fz = bd.nf[2];
@@ -1324,7 +1340,8 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
     auto rhs_plane = [&](XRowState<T, A>& s, int r, int x, bool live, int zs) {
         const T* fr = frb + r * L.frp;
         const T fhi = x + 1 < nx ? fr[x + 1] : fr[bcx == 0 ? 0 : nx];
-        if constexpr (MR) s.py = (r + 1 < rows ? fyb[(r + 1) * nx + x] : s.fyh) - s.fyl;
+        if constexpr (MR)
+            if (r + 1 < rows) s.py = fyb[(r + 1) * nx + x] + s.py;
         const T adv = ((fhi - fr[x]) + s.py) + s.pz;
         const T e = -adv * inv_h + s.plap * lap_s;
         T rhs = gdt * e - bdt * s.pb4;
@@ -1343,7 +1360,12 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
         if constexpr (MR) {
             s.live = tid < rows * nx;
             const int item = s.live ? tid : rows * nx - 1;
-            s.r = item / nx;
+            if constexpr (RM == XR_WAVE) {
+                const int w0 = ex.wave_base(tid);
+                s.r = (w0 < rows * nx ? w0 : rows * nx - 1) / nx;
+            } else {
+                s.r = item / nx;
+            }
             s.x = item - s.r * nx;
             const int y = t.y0 + s.r;
             s.ro = row_off(y);
@@ -1442,11 +1464,13 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
                 const T fyl =
                     flux_weno_d<T>(s.vl, dY[0], dY[1], dY[2], dY[3], dY[4], yc[2], yc[3], epsw);
                 if constexpr (MR) {
-                    s.fyl = fyl;
                     if (live) fyb[r * nx + x] = fyl;
                     if (r + 1 == rows)
-                        s.fyh = flux_weno_d<T>(s.vh, dY[1], dY[2], dY[3], dY[4], dY[5], yc[3],
-                                               yc[4], epsw);
+                        s.py = flux_weno_d<T>(s.vh, dY[1], dY[2], dY[3], dY[4], dY[5], yc[3],
+                                              yc[4], epsw) -
+                               fyl;
+                    else
+                        s.py = -fyl;   // a + (-b) is a - b, bit for bit
                 } else {
                     const T fyh = flux_weno_d<T>(s.vh, dY[1], dY[2], dY[3], dY[4], dY[5], yc[3],
                                                  yc[4], epsw);

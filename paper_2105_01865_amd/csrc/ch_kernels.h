@@ -15,7 +15,7 @@ template <typename T, typename A>
 hipError_t launch_pass_x(int mi, int nwg, int nth, size_t lds, hipStream_t st,
                          const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
                          const void* C, const void* U, const void* V, const void* W, void* E,
-                         void* Q, bool e25, bool xrow, bool xrow_multi);
+                         void* Q, bool e25, bool xrow, int xrm);
 
 // The segmented x-pass program: the previous substage's E from Ein, the new
 // one into Eout (different arrays).

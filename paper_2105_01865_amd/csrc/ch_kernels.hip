@@ -58,9 +58,10 @@ k_pass_x(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
                                                              W, E, Q, smem);
 }
 
-// The row x-pass program (pass_x_row_program); NT bounds the group size, MR
-// selects several rows per task.
-template <typename T, typename A, int NT, bool MR>
+// The row x-pass program (pass_x_row_program); NT bounds the group size, RM
+// is the row mode (one row per task, several with per-thread row offsets, or
+// several of whole waves).
+template <typename T, typename A, int NT, int RM>
 __global__ void __launch_bounds__(NT)
 k_pass_x_row(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
              const T* __restrict__ C, const T* __restrict__ U, const T* __restrict__ V,
@@ -71,7 +72,7 @@ k_pass_x_row(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
     const int b = chd::find_box(boxes, nbox, chd::PASS_X, task);
     chd::GpuExec ex{(int)threadIdx.x, (int)blockDim.x};
     chd::XRowState<T, A> st;
-    chd::pass_x_row_program<T, A, MR, chd::GpuExec>(ex, &st, boxes[b], pa, task, C, U, V, W, E,
+    chd::pass_x_row_program<T, A, RM, chd::GpuExec>(ex, &st, boxes[b], pa, task, C, U, V, W, E,
                                                     Q, smem);
 }
 
@@ -1103,46 +1104,50 @@ static hipError_t launch_x_mode(int mi, int nwg, int nth, size_t lds, hipStream_
     return launch_x<T, A, 2, 1024, E25>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
 }
 
-template <typename T, typename A, int NT, bool MR>
+template <typename T, typename A, int NT, int RM>
 static hipError_t launch_x_row(int nwg, int nth, size_t lds, hipStream_t st,
                                const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
                                const void* C, const void* U, const void* V, const void* W,
                                void* E, void* Q)
 {
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)&k_pass_x_row<T, A, NT, MR>,
+        hipError_t e = hipFuncSetAttribute((const void*)&k_pass_x_row<T, A, NT, RM>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_pass_x_row<T, A, NT, MR>), dim3(nwg), dim3(nth), lds, st, boxes, nbox,
+    hipLaunchKernelGGL((k_pass_x_row<T, A, NT, RM>), dim3(nwg), dim3(nth), lds, st, boxes, nbox,
                        pa, (const T*)C, (const T*)U, (const T*)V, (const T*)W, (T*)E, (T*)Q);
     return hipGetLastError();
 }
 
-template <typename T, typename A, bool MR>
+template <typename T, typename A, int RM>
 static hipError_t launch_x_row_nt(int nwg, int nth, size_t lds, hipStream_t st,
                                   const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
                                   const void* C, const void* U, const void* V, const void* W,
                                   void* E, void* Q)
 {
     if (nth <= 256)
-        return launch_x_row<T, A, 256, MR>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+        return launch_x_row<T, A, 256, RM>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
     if (nth <= 512)
-        return launch_x_row<T, A, 512, MR>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
-    return launch_x_row<T, A, 1024, MR>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+        return launch_x_row<T, A, 512, RM>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+    return launch_x_row<T, A, 1024, RM>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
 }
 
 template <typename T, typename A>
 hipError_t launch_pass_x(int mi, int nwg, int nth, size_t lds, hipStream_t st,
                          const chd::BoxDesc* boxes, int nbox, const chd::PassArgs& pa,
                          const void* C, const void* U, const void* V, const void* W, void* E,
-                         void* Q, bool e25, bool xrow, bool xrow_multi)
+                         void* Q, bool e25, bool xrow, int xrm)
 {
     if (xrow && !e25 && mi == 1) {
-        if (xrow_multi)
-            return launch_x_row_nt<T, A, true>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E,
-                                               Q);
-        return launch_x_row_nt<T, A, false>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V, W, E, Q);
+        if (xrm == chd::XR_WAVE)
+            return launch_x_row_nt<T, A, chd::XR_WAVE>(nwg, nth, lds, st, boxes, nbox, pa, C, U,
+                                                       V, W, E, Q);
+        if (xrm == chd::XR_THREAD)
+            return launch_x_row_nt<T, A, chd::XR_THREAD>(nwg, nth, lds, st, boxes, nbox, pa, C,
+                                                         U, V, W, E, Q);
+        return launch_x_row_nt<T, A, chd::XR_ONE>(nwg, nth, lds, st, boxes, nbox, pa, C, U, V,
+                                                  W, E, Q);
     }
     if constexpr (std::is_same<T, A>::value) {
         if (e25)
@@ -1375,7 +1380,7 @@ hipError_t launch_press_update(hipStream_t st, const PressArgs& a, const void* C
                                             const chd::BoxDesc*, int,                           \
                                             const chd::PassArgs&, const void*, const void*,     \
                                             const void*, const void*, void*, void*, bool,       \
-                                            bool, bool);                                        \
+                                            bool, int);                                         \
     template hipError_t launch_pass_x_seg<T, A>(int, int, size_t, hipStream_t,                  \
                                                 const chd::BoxDesc*, int, const chd::PassArgs&, \
                                                 const void*, const void*, const void*,          \

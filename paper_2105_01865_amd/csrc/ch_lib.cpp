@@ -234,12 +234,12 @@ hipError_t enqueue_substage(Engine& e, int k, const void* u, const void* v, cons
                 err = chk::launch_pass_x<T, A>(e.P.mi, e.P.x_ntask[g], e.P.x_threads,
                                                e.P.x_lds[g], e.stream, e.d_xbox[g],
                                                (int)e.P.xbox[g].size(), pa, e.C, u, v, w, e.E,
-                                               e.qa, false, true, g == 1);
+                                               e.qa, false, true, e.P.x_rm[g]);
         } else if (p == 0)
             err = chk::launch_pass_x<T, A>(e.P.mi, e.P.ntask[0], e.P.x_threads, e.P.lds[0],
                                            e.stream, e.d_boxes, e.P.nbox, pa,
                                            e.C, u, v, w, e.E, e.qa, false, e.P.xrow,
-                                           e.P.xrow_multi);
+                                           e.P.xrm);
         else if (p == 1)
             err = chk::launch_pass_line<T, A>(chd::PASS_Y, e.P.ntask[1], e.P.yz_threads,
                                               e.P.lds[1], e.stream, e.d_boxes, e.P.nbox, pa, e.qa,
@@ -271,7 +271,7 @@ hipError_t enqueue_substage_e25(Engine& e, int k, const void* u, const void* v, 
     const chd::PassArgs pa = chp::pass_args(e.P, k, 0);
     hipError_t err = chk::launch_pass_x<T, T>(e.P.mi, e.P.ntask[0], e.P.x_threads, e.P.lds[0],
                                               e.stream, e.d_boxes, e.P.nbox, pa, e.C, u, v, w,
-                                              e.E, e.qa, true, false, false);
+                                              e.E, e.qa, true, false, chd::XR_ONE);
     if (e.prof && a && b) {
         (void)hipEventRecord(b, e.stream);
         e.ev_pending.push_back({0, {a, b}});

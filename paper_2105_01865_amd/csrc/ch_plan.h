@@ -106,6 +106,7 @@ struct Plan {
     bool e25 = false;   // explicit 25-point scheme: no line solves, one row per x task
     bool xrow = false;        // the x pass runs the one-cell-per-thread row program
     bool xrow_multi = false;  // ... with several rows in some task
+    int xrm = 0;              // its row mode (chd::XR_ONE, XR_THREAD or XR_WAVE)
     bool xseg = false;        // the x pass runs the segmented program (long lines)
     // The x pass of a batch in which the row program gives some boxes one row
     // per task and others several runs as two launches (nxl = 2): the
@@ -116,6 +117,7 @@ struct Plan {
     std::vector<chd::BoxDesc> xbox[2];
     int x_ntask[2] = {0, 0};
     size_t x_lds[2] = {0, 0};
+    int x_rm[2] = {0, 0};   // row mode of each launch
     int tw_max = 0;
     int x_rows = 0, x_threads = 256, zc = 1, mi = 1, lanes = 32, yz_threads = 256, seg_cap = 0;
     int ntask[3] = {0, 0, 0};
@@ -465,6 +467,19 @@ inline ch_status plan_dt(Plan& P, double dt)
         }
     }
     for (int p = 0; p < 3; ++p) P.ntask[p] = (int)t0[p];
+    // the row mode of an x launch of the row program over boxes bs: several
+    // rows of whole waves when every box with several rows per task has a
+    // multiple of 64 cells in x (then no wave holds cells of two rows)
+    auto row_mode = [&](const std::vector<chd::BoxDesc>& bs) {
+        bool multi = false, wave = true;
+        for (const chd::BoxDesc& d : bs)
+            if (d.x_rows > 1) {
+                multi = true;
+                wave = wave && d.n[0] % 64 == 0;
+            }
+        return !multi ? chd::XR_ONE : wave ? chd::XR_WAVE : chd::XR_THREAD;
+    };
+    P.xrm = P.xrow ? row_mode(P.boxes) : chd::XR_ONE;
     P.nxl = 1;
     if (P.xrow && P.xrow_multi) {
         for (int g = 0; g < 2; ++g) {
@@ -484,6 +499,7 @@ inline ch_status plan_dt(Plan& P, double dt)
                                           chd::x_row_layout(d.n[0], d.x_rows, d.zc, P.tw_max,
                                                             (int)sT, (int)sA).total);
                 }
+            for (int g = 0; g < 2; ++g) P.x_rm[g] = row_mode(P.xbox[g]);
         }
     }
     if (P.xseg) {

@@ -14,9 +14,13 @@
 //   IN_DIR/{C,u,v,w}.bin: packed float64 arrays (the library's layout)
 //   OUT_DIR/C.bin: packed float64 result; OUT_DIR/mass.txt: per-box mass;
 //   OUT_DIR/plan.txt: x_rows seg_cap chains tw_max acc64 ntask0..2 lds0..2 z_chunk xrow
+//           xrm0 xrm1
 //           (xrow: 0 general x program, 1 row program, 2 row program with
 //           several rows in some task, 3 segmented program, 4 row program in
-//           two launches: one-row boxes and several-row boxes)
+//           two launches: one-row boxes and several-row boxes; xrm0, xrm1: the
+//           row mode of the row program's launch, or of its two launches:
+//           0 one row, 1 several rows with per-thread offsets, 2 several rows
+//           of whole waves)
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -65,7 +69,22 @@ static void run_x(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T* v
     }
 }
 
-// the one-row x-pass program
+// one task of the row x-pass program in row mode rm
+template <typename T, typename A>
+static void xrow_task(int rm, chd::CpuExec& ex, chd::XRowState<T, A>* st, const chd::BoxDesc& bd,
+                      const chd::PassArgs& pa, int task, const T* C, const T* u, const T* v,
+                      const T* w, T* E, T* qa, unsigned char* lds)
+{
+    if (rm == chd::XR_WAVE)
+        chd::pass_x_row_program<T, A, chd::XR_WAVE>(ex, st, bd, pa, task, C, u, v, w, E, qa, lds);
+    else if (rm == chd::XR_THREAD)
+        chd::pass_x_row_program<T, A, chd::XR_THREAD>(ex, st, bd, pa, task, C, u, v, w, E, qa,
+                                                      lds);
+    else
+        chd::pass_x_row_program<T, A, chd::XR_ONE>(ex, st, bd, pa, task, C, u, v, w, E, qa, lds);
+}
+
+// the row x-pass program
 template <typename T, typename A>
 static void run_xrow(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T* v, const T* w)
 {
@@ -82,12 +101,7 @@ static void run_xrow(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T
                 unsigned char* lds = (unsigned char*)malloc(P.x_lds[g]);
                 memset(lds, 0xff, P.x_lds[g]);
                 const int b = chd::find_box(gb, nb, chd::PASS_X, task);
-                if (g == 1)
-                    chd::pass_x_row_program<T, A, true>(ex, st.data(), gb[b], pa, task, C, u, v,
-                                                        w, E, qa, lds);
-                else
-                    chd::pass_x_row_program<T, A, false>(ex, st.data(), gb[b], pa, task, C, u, v,
-                                                         w, E, qa, lds);
+                xrow_task<T, A>(P.x_rm[g], ex, st.data(), gb[b], pa, task, C, u, v, w, E, qa, lds);
                 free(lds);
             }
         }
@@ -97,12 +111,7 @@ static void run_xrow(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T
         unsigned char* lds = (unsigned char*)malloc(P.lds[0]);
         memset(lds, 0xff, P.lds[0]);
         const int b = chd::find_box(boxes, P.nbox, chd::PASS_X, task);
-        if (P.xrow_multi)
-            chd::pass_x_row_program<T, A, true>(ex, st.data(), boxes[b], pa, task, C, u, v, w, E,
-                                                qa, lds);
-        else
-            chd::pass_x_row_program<T, A, false>(ex, st.data(), boxes[b], pa, task, C, u, v, w, E,
-                                                 qa, lds);
+        xrow_task<T, A>(P.xrm, ex, st.data(), boxes[b], pa, task, C, u, v, w, E, qa, lds);
         free(lds);
     }
 }
@@ -227,9 +236,11 @@ static int go(chp::Plan& P, const std::string& in, const std::string& out, int n
     for (double x : m) fprintf(f, "%.17g\n", x);
     fclose(f);
     f = fopen((out + "/plan.txt").c_str(), "w");
-    fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu %d %d\n", P.x_rows, P.seg_cap, P.yz_threads,
-            P.tw_max, P.acc64 ? 1 : 0, P.ntask[0], P.ntask[1], P.ntask[2], P.lds[0], P.lds[1],
-            P.lds[2], P.zc, P.xseg ? 3 : P.nxl == 2 ? 4 : P.xrow ? (P.xrow_multi ? 2 : 1) : 0);
+    fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu %d %d %d %d\n", P.x_rows, P.seg_cap,
+            P.yz_threads, P.tw_max, P.acc64 ? 1 : 0, P.ntask[0], P.ntask[1], P.ntask[2], P.lds[0],
+            P.lds[1], P.lds[2], P.zc,
+            P.xseg ? 3 : P.nxl == 2 ? 4 : P.xrow ? (P.xrow_multi ? 2 : 1) : 0,
+            P.nxl == 2 ? P.x_rm[0] : P.xrm, P.nxl == 2 ? P.x_rm[1] : P.xrm);
     fclose(f);
     free(C); free(E); free(E2); free(qa); free(qb); free(u); free(v); free(w);
     return 0;

@@ -223,6 +223,34 @@ def test_row_program_in_a_batch(x_rows):
         assert _rel(a, _oracle(b, dt, 2)) < 1e-12
 
 
+@pytest.mark.parametrize("boxes,x_rows,xrm", [
+    # rows of whole waves: 3 rows of 64 per task, the last task one row (two
+    # idle waves); 2 rows of 128 with y and z walls, the last task one row
+    ([((12, 10, 64), (0, 0, 0))], 3, [2, 2]),
+    ([((9, 9, 128), (0, 1, 1))], 2, [2, 2]),
+    # a batch: the 256-wide box one row per task, the 64- and 128-wide ones
+    # several rows of whole waves (two launches)
+    ([((8, 8, 256), (0, 0, 0)), ((10, 9, 64), (0, 0, 1)), ((8, 11, 128), (0, 0, 0))], 0,
+     [0, 2]),
+    # a 48-wide box among them: per-thread row offsets in the second launch
+    ([((8, 8, 256), (0, 0, 0)), ((10, 9, 48), (0, 0, 0)), ((8, 11, 128), (0, 0, 0))], 0,
+     [0, 1]),
+])
+def test_wave_rows(boxes, x_rows, xrm):
+    """Several rows per task whose rows are whole waves (the row offsets
+    uniform per wave) give the bits of the general program, and the
+    oracle's step."""
+    bs = [_box(sh, bc=bc, seed=71 + i, amp=2.0) for i, (sh, bc) in enumerate(boxes)]
+    dt = 2e-4
+    for prec, tol in ((0, 1e-12), (1, 2e-6)):
+        got, _, plan = run_emu(bs, dt, 2, prec=prec, x_rows=x_rows)
+        assert plan["xrm"] == xrm
+        gen, _, _ = run_emu(bs, dt, 2, prec=prec, x_rows=x_rows, x_general=1)
+        for a, g, b in zip(got, gen, bs):
+            assert np.array_equal(a, g)
+            assert _rel(a, _oracle(b, dt, 2)) < tol
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_launch_plan_does_not_change_the_bits(prec):
     """Every face flux is formed from the same differences whatever the tile:

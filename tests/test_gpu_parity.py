@@ -100,6 +100,12 @@ def test_32cube_fp64_one_step_and_ten_steps():
     ((8, 11, 13), (1, 1, 0), dict(x_rows=5, seg_len=3, waves_yz=2)),
     ((40, 33, 72), (1, 1, 1), {}),
     ((64, 48, 56), (1, 1, 0), dict(x_rows=2, z_chunk=5)),
+    # several rows per task, each of whole waves (row offsets uniform per
+    # wave): a last task of fewer rows (idle waves), 512-thread groups, walls
+    ((12, 9, 128), (0, 0, 0), dict(x_rows=2, z_chunk=5)),
+    ((12, 9, 256), (0, 0, 0), dict(x_rows=2, z_chunk=4)),
+    ((10, 11, 64), (0, 1, 1), dict(x_rows=3, z_chunk=4)),
+    ((9, 10, 128), (1, 1, 0), dict(x_rows=2, z_chunk=3)),
 ])
 def test_fp64_parity_tiles_walls_ragged(shape, bc, opts):
     C, u, v, w, h = _case(shape, bc, seed=sum(shape), amp=2.0)
@@ -108,7 +114,7 @@ def test_fp64_parity_tiles_walls_ragged(shape, bc, opts):
     ref = oracle.step(C, u, v, w, h, h, 0.9 / h, dt, 1, bc=bc)
     print(f"  cfg={cfg} rel={rel(got, ref):.3e}")
     assert rel(got, ref) <= TOL64
-    if bc[0] or bc[1]:
+    if bc[0] or bc[1] or shape[2] % 64 == 0 and opts.get("x_rows", 1) > 1:
         # FP32 storage in the same launch shapes
         got32, _ = run_gpu(C, u, v, w, h, h, 0.9 / h, dt, 1, bc=bc, precision="fp32", **opts)
         print(f"  fp32 rel={rel(got32, ref):.3e}")
