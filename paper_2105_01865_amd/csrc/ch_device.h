@@ -228,6 +228,30 @@ CH_HD void in_vgpr(T& v)
 #endif
 }
 
+// Form v here: an empty asm statement takes it as an operand, so the
+// compiler neither sinks its computation below this point nor recomputes it
+// later (either would keep its inputs alive past here).
+template <typename T>
+CH_HD void pin(T& v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+v"(v));
+#else
+    (void)v;
+#endif
+}
+
+// A value the same in every lane, marked so (the compiler keeps it, and
+// what is computed from it, in scalar registers).
+CH_HD int uniform_i(int v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_readfirstlane(v);
+#else
+    return v;
+#endif
+}
+
 // Wait until every global load the wave has issued has landed (vmcnt(0);
 // expcnt and lgkmcnt untouched).  Used at the end of a loop's prologue: a load
 // left pending there makes the compiler's conservative merge at the loop
@@ -1217,7 +1241,7 @@ struct XRowState {
                               // (several rows per task, below the last row: py is
                               // minus the low y face's flux until the RHS adds the
                               // high one, which the row above forms)
-    T nc, nu, nvl, nvh, nwh, ne, nyh[6];   // the next plane's loads
+    T nc;                     // C at z+4 of the owned cell (the next plane's c[6])
     int cxp, cxm;             // halo columns of the C and psi' rows fed by the
                               // owned column (or the column itself)
     int r, x;                 // the owned cell (several rows per task)
@@ -1310,29 +1334,36 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
         }
     };
 
-    // all global loads of plane z
-    auto fetch = [&](XRowState<T, A>& s, uint32_t xb, int z) {
+    // The global loads of plane z go straight into the registers that hold
+    // them while the plane is computed, each group issued after the last use
+    // of the previous plane's values (behind a scheduling fence, so that the
+    // two never live at once): u after the x face, v and the y halo rows
+    // after the y faces, w after the z face, the old E after the RHS that
+    // reads it.  Each has about one plane of work to arrive.  On the task's
+    // last plane they load that plane again (just read, so from L2) rather
+    // than branch: a load under a branch keeps the old value alive beside
+    // the new one.
+    auto load_u = [&](XRowState<T, A>& s, uint32_t xb, int z) {
+        s.ul = Ur(xb + (MR ? s.rou : yoffu), (uint32_t)z * ubytes);
+    };
+    auto load_vy = [&](XRowState<T, A>& s, uint32_t xb, int z) {
         const uint32_t zo = (uint32_t)z * pbytes;
-        const uint32_t wo = (uint32_t)((z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1) * pbytes;
         if constexpr (MR) {
-            s.nc = Cr(xb + s.ro, cplane(z + 3));
-            s.nu = Ur(xb + s.rou, (uint32_t)z * ubytes);
-            s.nvl = Vr(xb + s.ro, (uint32_t)z * vbytes);
-            s.nvh = Vr(xb + s.rvt, (uint32_t)z * vbytes);
-            s.nwh = Wr(xb + s.ro, wo);
-            s.ne = pa.e_mode != 0 ? Er(xb + s.ro, zo) : T(0);
+            s.vl = Vr(xb + s.ro, (uint32_t)z * vbytes);
+            s.vh = Vr(xb + s.rvt, (uint32_t)z * vbytes);
 #pragma unroll
-            for (int hr = 0; hr < 6; ++hr) s.nyh[hr] = Cr(xb + s.ho[hr], zo);
+            for (int hr = 0; hr < 6; ++hr) s.yh[hr] = Cr(xb + s.ho[hr], zo);
         } else {
-            s.nc = Cr(xb + yoff, cplane(z + 3));
-            s.nu = Ur(xb + yoffu, (uint32_t)z * ubytes);
-            s.nvl = Vr(xb + yoff, (uint32_t)z * vbytes);
-            s.nvh = Vr(xb, (uint32_t)z * vbytes + vtop);
-            s.nwh = Wr(xb + yoff, wo);
-            s.ne = pa.e_mode != 0 ? Er(xb + yoff, zo) : T(0);
+            s.vl = Vr(xb + yoff, (uint32_t)z * vbytes);
+            s.vh = Vr(xb, (uint32_t)z * vbytes + vtop);
 #pragma unroll
-            for (int hr = 0; hr < 6; ++hr) s.nyh[hr] = Cr(xb, zo + hoff[hr]);
+            for (int hr = 0; hr < 6; ++hr) s.yh[hr] = Cr(xb, zo + hoff[hr]);
         }
+    };
+    // w on the high face of plane z (periodic wrap, or the wall face nz)
+    auto load_wh = [&](XRowState<T, A>& s, uint32_t xb, int z) {
+        const uint32_t wo = (uint32_t)((z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1) * pbytes;
+        s.wh = Wr(xb + (MR ? s.ro : yoff), wo);
     };
     // RHS of plane zs of the owned cell into the solve tile (and E out); with
     // several rows per task the high y face of a row below the last is the
@@ -1391,9 +1422,12 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
         for (int q = 1; q < 7; ++q) s.c[q] = Cr(xb + ro, cplane(z0 - 4 + q));
         s.mq[1] = mu(s.c[3]);   // psi'(C) at z0-2 .. z0 after the first shift
         s.mq[2] = mu(s.c[4]);
-        s.wh = Wr(xb + ro, (uint32_t)z0 * pbytes);   // becomes the low face of z0
         wait_loads();
-        fetch(s, xb, z0);
+        s.nc = Cr(xb + ro, cplane(z0 + 3));
+        load_u(s, xb, z0);
+        load_vy(s, xb, z0);
+        s.wl = Wr(xb + ro, (uint32_t)z0 * pbytes);
+        load_wh(s, xb, z0);
     });
 
     for (int zs = 0; zs < nzc; ++zs) {
@@ -1404,20 +1438,14 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
             XRowState<T, A>& s = st[ex.slot(tid)];
             int r, x;
             const bool live = cell(s, tid, &r, &x);
+            const uint32_t xb = (uint32_t)x * sT;
 #pragma unroll
             for (int q = 0; q < 6; ++q) s.c[q] = s.c[q + 1];
             s.c[6] = s.nc;
-            s.ul = s.nu;
-            s.vl = s.nvl;
-            s.vh = s.nvh;
-            s.wl = s.wh;
-            s.wh = s.nwh;
-#pragma unroll
-            for (int hr = 0; hr < 6; ++hr) s.yh[hr] = s.nyh[hr];
-            const T e_here = s.ne;
-            if (zs + 1 < nzc) fetch(s, (uint32_t)x * sT, z + 1);
+            s.nc = Cr(xb + (MR ? s.ro : yoff), cplane(zs + 1 < nzc ? z + 4 : z + 3));
             if (zs > 0) rhs_plane(s, r, x, live, zs - 1);
-            s.eold = e_here;
+            sched_fence();
+            if (pa.e_mode != 0) s.eold = Er(xb + (MR ? s.ro : yoff), (uint32_t)z * pbytes);
             s.mq[0] = s.mq[1];
             s.mq[1] = s.mq[2];
             s.mq[2] = mu(s.c[4]);
@@ -1446,6 +1474,10 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
                 if (live) fr[x] = f;
                 s.pb4 = d4_d<T>(dX[1], dX[2], dX[3], dX[4]);
             }
+            // the plane whose loads go out
+            const int zn = uniform_i(zs + 1 < nzc ? z + 1 : z);
+            sched_fence();
+            load_u(s, (uint32_t)x * sT, zn);
             if (bcx != 0 && live && x == nx - 1) {
                 // the wall face nx (its normal velocity is zero by the interface's rule)
                 const T uw = Ur((uint32_t)(x + 1) * sT + (MR ? s.rou : yoffu),
@@ -1478,6 +1510,13 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
                 }
                 s.pb4 += d4_d<T>(dY[1], dY[2], dY[3], dY[4]);
             }
+            // psi'(C) of the y neighbours (summed as in the Laplacian below);
+            // what the y block formed is pinned before its inputs are reloaded
+            T myy = mu(s.yh[3]) + mu(s.yh[2]);
+            pin(myy);
+            pin(s.py);
+            sched_fence();
+            load_vy(s, (uint32_t)x * sT, zn);
             // z: planes z-1 .. z+3; the high face (the low one carries over)
             {
                 const T* c = s.c;
@@ -1494,8 +1533,11 @@ CH_HD void pass_x_row_program(X& ex, XRowState<T, A>* st, const BoxDesc& bd, con
                 s.fzl = fzh;
                 s.pb4 += d4_d<T>(dZ[0], dZ[1], dZ[2], dZ[3]);
             }
-            s.plap = ((mrow[1] + mrow[-1]) + (mu(s.yh[3]) + mu(s.yh[2])))
-                   + (s.mq[2] + s.mq[0]) - T(6) * s.mq[1];
+            pin(s.pz);
+            sched_fence();
+            s.wl = s.wh;
+            load_wh(s, (uint32_t)x * sT, zn);
+            s.plap = ((mrow[1] + mrow[-1]) + myy) + (s.mq[2] + s.mq[0]) - T(6) * s.mq[1];
         });
     }
     // ---- RHS of the last plane
