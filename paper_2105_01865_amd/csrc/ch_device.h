@@ -1636,7 +1636,8 @@ struct XSegState {
     T eold;                   // E of the previous substage at the plane whose RHS is next
     T py, pz, plap, pb4;      // y and z flux differences, Laplacian of psi', sum of D4
     T xh;                     // threads 0..5: C beyond the extended range, this plane
-    T nc, nu, nvl, nvh, nwh, ne, nyh[6], nxh;   // the next plane's loads
+    T nc;                     // C at z+4 of the cell (the next plane's c[6])
+    uint32_t xb;              // byte offset of the cell in its row
     LineState<A> ls;
 };
 
@@ -1692,19 +1693,25 @@ CH_HD void pass_x_seg_program(X& ex, XSegState<T, A>* st, const BoxDesc& bd, con
     // threads 0..5: the C beyond the extended range, at cr index hq
     auto hq = [&](int tid) { return tid < 3 ? tid - 3 : NE + 1 + (tid - 3); };
 
-    auto fetch = [&](XSegState<T, A>& s, int tid, uint32_t xb, int z) {
-        s.nc = Cp(map_idx(z + 3, nz, bd.bc[2]))(xb + yoff);
-        s.nu = PlaneRef<T>(Ub + (int64_t)z * ny * fx, ubytes)(xb + yoffu);
+    // the loads of plane z, straight into the working registers (as in the
+    // row program: each group after the last use of the previous plane's)
+    auto load_u = [&](XSegState<T, A>& s, int z) {
+        s.ul = PlaneRef<T>(Ub + (int64_t)z * ny * fx, ubytes)(s.xb + yoffu);
+    };
+    auto load_vy = [&](XSegState<T, A>& s, int z) {
         const PlaneRef<T> Vz(Vb + (int64_t)z * fy * nx, vbytes);
-        s.nvl = Vz(xb + yoff);
-        s.nvh = Vz(xb, vtop);
-        s.nwh = PlaneRef<T>(Wb + (int64_t)((z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1) * plane,
-                            pbytes)(xb + yoff);
-        s.ne = pa.e_mode != 0 ? PlaneRef<T>(Eib + (int64_t)z * plane, pbytes)(xb + yoff) : T(0);
+        s.vl = Vz(s.xb + yoff);
+        s.vh = Vz(s.xb, vtop);
         const PlaneRef<T> Cz = Cp(z);
 #pragma unroll
-        for (int hr = 0; hr < 6; ++hr) s.nyh[hr] = Cz(xb, hoff[hr]);
-        if (tid < 6) s.nxh = Cz(cellb(hq(tid)) + yoff);
+        for (int hr = 0; hr < 6; ++hr) s.yh[hr] = Cz(s.xb, hoff[hr]);
+    };
+    auto load_wh = [&](XSegState<T, A>& s, int z) {   // w on the high face of plane z
+        s.wh = PlaneRef<T>(Wb + (int64_t)((z + 1 == nz && bd.bc[2] == 0) ? 0 : z + 1) * plane,
+                           pbytes)(s.xb + yoff);
+    };
+    auto load_xh = [&](XSegState<T, A>& s, int tid, int z) {
+        if (tid < 6) s.xh = Cp(z)(cellb(hq(tid)) + yoff);
     };
     // RHS of plane zs at extended position q into the solve tile (and E out
     // at the segment's own cells)
@@ -1716,21 +1723,25 @@ CH_HD void pass_x_seg_program(X& ex, XSegState<T, A>* st, const BoxDesc& bd, con
         const int rel = q - twm;   // position in the segment
         if (tid == q && rel >= -tw && rel < S + tw) {
             if (pa.e_mode != 2 && rel >= 0 && rel < S)
-                PlaneRef<T>(Eob + (int64_t)(z0 + zs) * plane, pbytes).store(cellb(q) + yoff, e);
+                PlaneRef<T>(Eob + (int64_t)(z0 + zs) * plane, pbytes).store(s.xb + yoff, e);
             tb[zs * tbp + rel + tw] = A(rhs);
         }
     };
 
     ex.phase([&](int tid) {
         XSegState<T, A>& s = st[ex.slot(tid)];
-        const uint32_t xb = cellb(pos(tid));
+        s.xb = cellb(pos(tid));
 #pragma unroll
-        for (int q = 1; q < 7; ++q) s.c[q] = Cp(map_idx(z0 - 4 + q, nz, bd.bc[2]))(xb + yoff);
+        for (int q = 1; q < 7; ++q) s.c[q] = Cp(map_idx(z0 - 4 + q, nz, bd.bc[2]))(s.xb + yoff);
         s.mq[1] = mu(s.c[3]);
         s.mq[2] = mu(s.c[4]);
-        s.wh = PlaneRef<T>(Wb + (int64_t)z0 * plane, pbytes)(xb + yoff);
         wait_loads();
-        fetch(s, tid, xb, z0);
+        s.nc = Cp(map_idx(z0 + 3, nz, bd.bc[2]))(s.xb + yoff);
+        load_u(s, z0);
+        load_vy(s, z0);
+        s.wl = PlaneRef<T>(Wb + (int64_t)z0 * plane, pbytes)(s.xb + yoff);
+        load_wh(s, z0);
+        load_xh(s, tid, z0);
     });
 
     for (int zs = 0; zs < nzc; ++zs) {
@@ -1741,18 +1752,10 @@ CH_HD void pass_x_seg_program(X& ex, XSegState<T, A>* st, const BoxDesc& bd, con
 #pragma unroll
             for (int j = 0; j < 6; ++j) s.c[j] = s.c[j + 1];
             s.c[6] = s.nc;
-            s.ul = s.nu;
-            s.vl = s.nvl;
-            s.vh = s.nvh;
-            s.wl = s.wh;
-            s.wh = s.nwh;
-#pragma unroll
-            for (int hr = 0; hr < 6; ++hr) s.yh[hr] = s.nyh[hr];
-            s.xh = s.nxh;
-            const T e_here = s.ne;
-            if (zs + 1 < nzc) fetch(s, tid, cellb(q), z + 1);
+            s.nc = Cp(map_idx(zs + 1 < nzc ? z + 4 : z + 3, nz, bd.bc[2]))(s.xb + yoff);
             if (zs > 0 && q < NE) rhs_plane(s, tid, q, zs - 1);
-            s.eold = e_here;
+            sched_fence();
+            if (pa.e_mode != 0) s.eold = PlaneRef<T>(Eib + (int64_t)z * plane, pbytes)(s.xb + yoff);
             s.mq[0] = s.mq[1];
             s.mq[1] = s.mq[2];
             s.mq[2] = mu(s.c[4]);
@@ -1765,6 +1768,8 @@ CH_HD void pass_x_seg_program(X& ex, XSegState<T, A>* st, const BoxDesc& bd, con
                 if (tid == 2) mr[-1] = mu(s.xh);
                 if (tid == 3) mr[NE + 1] = mu(s.xh);
             }
+            sched_fence();
+            load_xh(s, tid, uniform_i(zs + 1 < nzc ? z + 1 : z));
         });
         ex.phase([&](int tid) {
             XSegState<T, A>& s = st[ex.slot(tid)];
@@ -1778,6 +1783,10 @@ CH_HD void pass_x_seg_program(X& ex, XSegState<T, A>* st, const BoxDesc& bd, con
                 if (tid == q) fr[q] = f;
                 s.pb4 = d4_d<T>(dX[1], dX[2], dX[3], dX[4]);
             }
+            // the plane whose loads go out (this one again on the task's last)
+            const int zn = uniform_i(zs + 1 < nzc ? z + 1 : z);
+            sched_fence();
+            load_u(s, zn);
             {
                 const T yc[7] = {s.yh[0], s.yh[1], s.yh[2], s.c[3], s.yh[3], s.yh[4], s.yh[5]};
                 T dY[6];
@@ -1790,6 +1799,11 @@ CH_HD void pass_x_seg_program(X& ex, XSegState<T, A>* st, const BoxDesc& bd, con
                 s.py = fyh - fyl;
                 s.pb4 += d4_d<T>(dY[1], dY[2], dY[3], dY[4]);
             }
+            T myy = mu(s.yh[3]) + mu(s.yh[2]);
+            pin(myy);
+            pin(s.py);
+            sched_fence();
+            load_vy(s, zn);
             {
                 const T* c = s.c;
                 T dZ[5];
@@ -1804,8 +1818,11 @@ CH_HD void pass_x_seg_program(X& ex, XSegState<T, A>* st, const BoxDesc& bd, con
                 s.fzl = fzh;
                 s.pb4 += d4_d<T>(dZ[0], dZ[1], dZ[2], dZ[3]);
             }
-            s.plap = ((mr[q + 1] + mr[q - 1]) + (mu(s.yh[3]) + mu(s.yh[2])))
-                   + (s.mq[2] + s.mq[0]) - T(6) * s.mq[1];
+            pin(s.pz);
+            sched_fence();
+            s.wl = s.wh;
+            load_wh(s, zn);
+            s.plap = ((mr[q + 1] + mr[q - 1]) + myy) + (s.mq[2] + s.mq[0]) - T(6) * s.mq[1];
         });
     }
     ex.phase([&](int tid) {
@@ -1834,7 +1851,7 @@ CH_HD void pass_x_seg_program(X& ex, XSegState<T, A>* st, const BoxDesc& bd, con
     ex.phase([&](int tid) {
         const int rel = tid - twm;
         if (rel < 0 || rel >= S) return;
-        const uint32_t o = cellb(tid) + yoff;
+        const uint32_t o = st[ex.slot(tid)].xb + yoff;   // tid <= NE: its own cell
         for (int zs = 0; zs < nzc; ++zs)
             PlaneRef<T>(Qb + (int64_t)(z0 + zs) * plane, pbytes)
                 .store(o, T(tb[zs * tbp + rel + tw]));
