@@ -1946,8 +1946,8 @@ CH_HD void load16_to_lds(const T* g, unsigned char* wave_base, int lane)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
     (void)lane;
-    // non-temporal: a line pass reads each element once (the 256^3 FP32
-    // z pass 43.8 -> 37.9 us; its output stays in L2 for the next pass)
+    // non-temporal: a line pass reads each element once, and leaves the
+    // caches to its output, which the next pass reads
     __builtin_amdgcn_global_load_lds(
         g, (__attribute__((address_space(3))) void*)(wave_base), 16, 0, 2);
 #else

@@ -247,10 +247,10 @@ k_check_velocity(const chd::BoxDesc* __restrict__ boxes, int nbox, const T* __re
 //      target reads its 4 taps.
 // Band, z and y stencil entries are uniform per item and row, so they are
 // read into scalar registers.  Every target element is written once, with
-// non-temporal stores (nothing reads it back before it leaves L2, and
-// streaming it out leaves L2 to the coarse rows, which are read again: 194
-// against 245 us per 512^3 FP32 component); the coarse data is read through
-// the caches about (rows per band / band height) times per target plane.
+// non-temporal stores (nothing reads it back while it is in the caches, and
+// streaming it out leaves them to the coarse rows, which are read again);
+// the coarse data is read through the caches about (rows per band / band
+// height) times per target plane.
 template <typename T, int JB, int MA>
 __global__ void __launch_bounds__(256)
 k_interp(InterpArgs a, const T* __restrict__ src, T* __restrict__ dst,
