@@ -217,6 +217,33 @@ def test_batch_equals_single_boxes_bitwise():
         assert abs(m - oracle.mass(ref, h)) <= 1e-12 * abs(m)
 
 
+def test_batch_in_two_launches_with_rows_of_whole_waves():
+    """A batch whose x pass is two launches: the 256-cell-wide box one row
+    per task, the 64- and 128-cell-wide boxes several rows per task whose
+    rows are whole waves (row offsets uniform per wave).  Each box equals its
+    single-box run bit for bit and the oracle's steps."""
+    cases = [_case((16, 12, 256), seed=21), _case((12, 10, 64), bc=(0, 0, 1), seed=22),
+             _case((10, 9, 128), seed=23)]
+    bcs = [(0, 0, 0), (0, 0, 1), (0, 0, 0)]
+    shapes = [c[0].shape for c in cases]
+    hs = [c[4] for c in cases]
+    for prec, tol in (("fp64", 1e-11), ("fp32", 5e-6)):
+        print(f"[gpu] two-launch batch with wave rows, {prec}", flush=True)
+        st = torch.cuda.Stream()
+        b = ch.Batch(shapes, hs, hs, [0.9 / h for h in hs], bcs=bcs, precision=prec, stream=st)
+        b.set_field(b.pack([c[0] for c in cases], "c"))
+        b.step(b.pack([c[1] for c in cases], "u"), b.pack([c[2] for c in cases], "v"),
+               b.pack([c[3] for c in cases], "w"), 1e-4, 2)
+        assert b.x_program() == 4
+        outs = [o.double().cpu().numpy() for o in b.unpack(b.get_field())]
+        b.close()
+        for (C, u, v, w, h), bc, got in zip(cases, bcs, outs):
+            single, _ = run_gpu(C, u, v, w, h, h, 0.9 / h, 1e-4, 2, bc=bc, precision=prec)
+            assert np.array_equal(got, single)
+            ref = oracle.step(C, u, v, w, h, h, 0.9 / h, 1e-4, 2, bc=bc)
+            assert rel(got, ref) <= tol
+
+
 def test_checkpoint_resume_is_bitwise():
     C, u, v, w, h = _case((32, 32, 32), seed=11)
     full, _ = run_gpu(C, u, v, w, h, h, 0.9 / h, 1e-4, 6)
