@@ -60,9 +60,13 @@ k_pass_x(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
 
 // The row x-pass program (pass_x_row_program); NT bounds the group size, RM
 // is the row mode (one row per task, several with per-thread row offsets, or
-// several of whole waves).
+// several of whole waves).  Single precision with one row of a 512-cell line:
+// at most 64 VGPRs (none spilled), so that four groups of 8 waves share a CU
+// rather than three (the 512^3 x pass 941-955 -> 919-927 us; at 256 threads
+// the same bound adds instructions and gains nothing).
 template <typename T, typename A, int NT, int RM>
 __global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && RM == chd::XR_ONE && NT == 512 ? 8 : 1)))
 k_pass_x_row(const chd::BoxDesc* __restrict__ boxes, int nbox, chd::PassArgs pa,
              const T* __restrict__ C, const T* __restrict__ U, const T* __restrict__ V,
              const T* __restrict__ W, T* __restrict__ E, T* __restrict__ Q)
