@@ -255,7 +255,7 @@ k_check_velocity(const chd::BoxDesc* __restrict__ boxes, int nbox, const T* __re
 // streaming it out leaves them to the coarse rows, which are read again);
 // the coarse data is read through the caches about (rows per band / band
 // height) times per target plane.
-template <typename T, int JB, int MA>
+template <typename T, int JB, int MA, bool PIPE>
 __global__ void __launch_bounds__(256)
 k_interp(InterpArgs a, const T* __restrict__ src, T* __restrict__ dst,
          const int* __restrict__ band, const int* __restrict__ izt, const T* __restrict__ wzt,
@@ -308,6 +308,33 @@ k_interp(InterpArgs a, const T* __restrict__ src, T* __restrict__ dst,
     const int per = (items + a.nwg - 1) / a.nwg;
     const int it0 = xcd_task(blockIdx.x, a.nwg) * per;
     const int it1 = it0 + per < items ? it0 + per : items;
+    // PIPE (one batch of loads covers an item: the coarse row fits the group
+    // and no band is taller than the rows in flight): the next item's coarse
+    // rows are loaded while this item's targets are stored, issued before
+    // phase C and combined into LDS at the top of the next item.
+    constexpr bool pipe = PIPE;
+    T vp[PIPE ? MA : 1][4];
+    auto issue = [&](int item) {   // the item's coarse rows at column tid
+        if constexpr (!PIPE) return;
+        const int k = item / nb, b = item - k * nb;
+        const int base = band[2 * b], span = band[2 * b + 1];
+        const chd::PlaneRef<T> p0(src + (int64_t)izt[4 * k] * a.plane, pbytes);
+        const chd::PlaneRef<T> p1(src + (int64_t)izt[4 * k + 1] * a.plane, pbytes);
+        const chd::PlaneRef<T> p2(src + (int64_t)izt[4 * k + 2] * a.plane, pbytes);
+        const chd::PlaneRef<T> p3(src + (int64_t)izt[4 * k + 3] * a.plane, pbytes);
+        const int cx = tid < sx ? tid : 0;
+#pragma unroll
+        for (int m = 0; m < (PIPE ? MA : 1); ++m) {
+            int rr = base + m;
+            if (rr >= a.sy) rr -= a.sy;
+            const uint32_t boff = (uint32_t)((m < span ? rr * sx + cx : cx) * (int)sizeof(T));
+            vp[m][0] = p0(boff);
+            vp[m][1] = p1(boff);
+            vp[m][2] = p2(boff);
+            vp[m][3] = p3(boff);
+        }
+    };
+    if (pipe && it0 < it1) issue(it0);
     for (int item = it0; item < it1; ++item) {
         const int k = item / nb, b = item - k * nb;
         const int j0 = b * JB;
@@ -315,7 +342,15 @@ k_interp(InterpArgs a, const T* __restrict__ src, T* __restrict__ dst,
         const int base = band[2 * b], span = band[2 * b + 1];
         __syncthreads();   // the previous item's readers are done with the LDS
         // A: coarse rows base .. base + span - 1 (cyclic), z stencil applied
-        {
+        if constexpr (PIPE) {
+            const T w0 = wzt[4 * k], w1 = wzt[4 * k + 1], w2 = wzt[4 * k + 2], w3 = wzt[4 * k + 3];
+            if (tid < sx)
+#pragma unroll
+                for (int m = 0; m < (PIPE ? MA : 1); ++m)
+                    if (m < span)
+                        zr[m * sx + tid] =
+                            ((w0 * vp[m][0] + w1 * vp[m][1]) + w2 * vp[m][2]) + w3 * vp[m][3];
+        } else {
             const chd::PlaneRef<T> p0(src + (int64_t)izt[4 * k] * a.plane, pbytes);
             const chd::PlaneRef<T> p1(src + (int64_t)izt[4 * k + 1] * a.plane, pbytes);
             const chd::PlaneRef<T> p2(src + (int64_t)izt[4 * k + 2] * a.plane, pbytes);
@@ -356,6 +391,7 @@ k_interp(InterpArgs a, const T* __restrict__ src, T* __restrict__ dst,
             }
         }
         __syncthreads();
+        if (pipe && item + 1 < it1) issue(item + 1);
         // C: x stencil, every target point written once
         T* out = dst + ((int64_t)k * a.tny + j0) * a.tnx;
         if (win) {
@@ -1240,20 +1276,29 @@ hipError_t launch_check_velocity(hipStream_t st, const chd::BoxDesc* boxes, int 
     return hipGetLastError();
 }
 
-template <typename T, int JB>
-static hipError_t launch_interp_jb(hipStream_t st, const InterpArgs& a)
+template <typename T, int JB, int MA, bool PIPE>
+static hipError_t launch_interp_k(hipStream_t st, const InterpArgs& a)
 {
-    constexpr int MA = sizeof(T) == 4 ? 20 : 12;  // rows of loads in flight
     if (a.lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)&k_interp<T, JB, MA>,
+        hipError_t e = hipFuncSetAttribute((const void*)&k_interp<T, JB, MA, PIPE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)a.lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_interp<T, JB, MA>), dim3((unsigned)a.nwg), dim3(256), a.lds, st, a,
-                       (const T*)a.src, (T*)a.dst, a.band, a.iz, (const T*)a.wz, a.ly,
+    hipLaunchKernelGGL((k_interp<T, JB, MA, PIPE>), dim3((unsigned)a.nwg), dim3(256), a.lds, st,
+                       a, (const T*)a.src, (T*)a.dst, a.band, a.iz, (const T*)a.wz, a.ly,
                        (const T*)a.wy, a.ix, a.wx);
     return hipGetLastError();
+}
+
+template <typename T, int JB>
+static hipError_t launch_interp_jb(hipStream_t st, const InterpArgs& a)
+{
+    constexpr int MA = sizeof(T) == 4 ? 20 : 12;  // rows of loads in flight
+    // one batch of loads per item: coarse rows of at most 256 points, bands
+    // of at most MA rows
+    if (a.rmax <= MA && a.sx <= 256) return launch_interp_k<T, JB, MA, true>(st, a);
+    return launch_interp_k<T, JB, MA, false>(st, a);
 }
 
 template <typename T>
