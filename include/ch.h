@@ -377,10 +377,11 @@ ch_status ch_get_config(const ch_state* s, int cfg[8]);
  * tests (the arithmetic is the same in all): *kind = 0 the general program,
  * 1 the row program (one cell per thread, the y stencil in registers), 2 the
  * row program with several rows in some task, 3 the segmented program (x
- * lines longer than a work-group), 4 the row program in two launches (a
- * batch whose boxes take one row per task in one, several rows in the
- * other).  CH_EINVAL before the first plan (no step yet and no dt_hint) or
- * on a null output. */
+ * lines longer than a work-group), 4 the row program in two or three
+ * launches (a batch whose boxes take different row modes: one row per task,
+ * several rows with per-thread row offsets, several rows of whole waves; one
+ * launch per mode, each with its own work-group size).  CH_EINVAL before the
+ * first plan (no step yet and no dt_hint) or on a null output. */
 ch_status ch_get_x_program(const ch_state* s, int* kind);
 ch_status ch_batch_get_x_program(const ch_batch* b, int* kind);
 

@@ -128,7 +128,7 @@ SIGNATURES = {
 
 # x-pass program kinds reported by ch_get_x_program
 X_PROGRAMS = {0: "general", 1: "row", 2: "row, several rows per task", 3: "segmented",
-              4: "row, one-row and several-row boxes in two launches"}
+              4: "row, one launch per row mode (two or three)"}
 
 
 def lib():

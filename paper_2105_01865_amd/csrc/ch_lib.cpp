@@ -82,7 +82,7 @@ void unreg(const H* p)
 struct Engine {
     chp::Plan P;
     chd::BoxDesc* d_boxes = nullptr;
-    chd::BoxDesc* d_xbox[2] = {nullptr, nullptr};   // box tables of a two-launch x pass
+    chd::BoxDesc* d_xbox[3] = {nullptr, nullptr, nullptr};   // box tables of the x launches
     void* C = nullptr;
     void* E = nullptr;
     void* E2 = nullptr;   // the segmented x program's second E (allocated when used)
@@ -126,7 +126,8 @@ void free_engine(Engine& e)
     }
     for (auto ev : e.ev_pool) (void)hipEventDestroy(ev);
     void* bufs[] = {e.C, e.E, e.E2, e.qa, e.qb, e.d_partial, e.d_h3, e.d_mass, e.d_flags,
-                    e.d_boxes, e.d_xbox[0], e.d_xbox[1], e.fu, e.fv, e.fw, e.d_lab, e.d_cnt,
+                    e.d_boxes, e.d_xbox[0], e.d_xbox[1], e.d_xbox[2], e.fu, e.fv, e.fw,
+                    e.d_lab, e.d_cnt,
                     e.d_list};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
@@ -155,7 +156,7 @@ ch_status init_engine(Engine& e, int nbox, const ch_grid* g, const double* Cn, c
     HIP_TRY(hipMalloc(&e.d_flags, sizeof(int) * 2 * chk::CHECK_WGS));
     HIP_TRY(hipMalloc(&e.d_boxes, sizeof(chd::BoxDesc) * nbox));
     if (nbox > 1)
-        for (int g = 0; g < 2; ++g) HIP_TRY(hipMalloc(&e.d_xbox[g], sizeof(chd::BoxDesc) * nbox));
+        for (int g = 0; g < 3; ++g) HIP_TRY(hipMalloc(&e.d_xbox[g], sizeof(chd::BoxDesc) * nbox));
     std::vector<double> h3(nbox);
     for (int b = 0; b < nbox; ++b) h3[b] = P.g[b].h * P.g[b].h * P.g[b].h;
     HIP_TRY(hipMemcpy(e.d_h3, h3.data(), sizeof(double) * nbox, hipMemcpyHostToDevice));
@@ -186,8 +187,8 @@ ch_status set_dt(Engine& e, double dt, bool e25 = false)
     }
     HIP_TRY(hipMemcpy(e.d_boxes, e.P.boxes.data(), sizeof(chd::BoxDesc) * e.P.nbox,
                       hipMemcpyHostToDevice));
-    if (e.P.nxl == 2)
-        for (int g = 0; g < 2; ++g)
+    if (e.P.nxl > 1)
+        for (int g = 0; g < e.P.nxl; ++g)
             HIP_TRY(hipMemcpy(e.d_xbox[g], e.P.xbox[g].data(),
                               sizeof(chd::BoxDesc) * e.P.xbox[g].size(), hipMemcpyHostToDevice));
     if (e.gexec) {
@@ -227,11 +228,11 @@ hipError_t enqueue_substage(Engine& e, int k, const void* u, const void* v, cons
             err = chk::launch_pass_x_seg<T, A>(e.P.ntask[0], e.P.x_threads, e.P.lds[0],
                                                e.stream, e.d_boxes, e.P.nbox, pa, e.C, u, v, w,
                                                k == 2 ? e.E2 : e.E, k == 1 ? e.E2 : e.E, e.qa);
-        else if (p == 0 && e.P.nxl == 2) {
-            // boxes with one row per task, then those with several
+        else if (p == 0 && e.P.nxl > 1) {
+            // one launch per row mode, each with its own work-group size
             err = hipSuccess;
-            for (int g = 0; g < 2 && err == hipSuccess; ++g)
-                err = chk::launch_pass_x<T, A>(e.P.mi, e.P.x_ntask[g], e.P.x_threads,
+            for (int g = 0; g < e.P.nxl && err == hipSuccess; ++g)
+                err = chk::launch_pass_x<T, A>(e.P.mi, e.P.x_ntask[g], e.P.x_nth[g],
                                                e.P.x_lds[g], e.stream, e.d_xbox[g],
                                                (int)e.P.xbox[g].size(), pa, e.C, u, v, w, e.E,
                                                e.qa, false, true, e.P.x_rm[g]);
@@ -1138,7 +1139,7 @@ static ch_status x_program(const chp::Plan& P, int* kind)
 {
     if (!kind) return fail(CH_EINVAL, "null output");
     if (std::isnan(P.dt)) return fail(CH_EINVAL, "no plan yet: step once or pass dt_hint");
-    *kind = P.xseg ? 3 : P.nxl == 2 ? 4 : P.xrow ? (P.xrow_multi ? 2 : 1) : 0;
+    *kind = P.xseg ? 3 : P.nxl > 1 ? 4 : P.xrow ? (P.xrow_multi ? 2 : 1) : 0;
     return CH_OK;
 }
 

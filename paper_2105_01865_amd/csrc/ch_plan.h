@@ -108,16 +108,19 @@ struct Plan {
     bool xrow_multi = false;  // ... with several rows in some task
     int xrm = 0;              // its row mode (chd::XR_ONE, XR_THREAD or XR_WAVE)
     bool xseg = false;        // the x pass runs the segmented program (long lines)
-    // The x pass of a batch in which the row program gives some boxes one row
-    // per task and others several runs as two launches (nxl = 2): the
-    // one-row boxes in the one-cell-per-thread kernel, the others in the
-    // several-rows kernel, each over a box table of its own whose x tasks are
-    // numbered from 0 (the y and z passes keep the whole table).
+    // The x pass of a batch whose boxes take different row modes in the row
+    // program runs as one launch per mode (nxl of them, at most 3: one row
+    // per task, several with per-thread row offsets, several of whole
+    // waves), each over a box table of its own whose x tasks are numbered
+    // from 0 and with a work-group size of its own (the y and z passes keep
+    // the whole table).
     int nxl = 1;
-    std::vector<chd::BoxDesc> xbox[2];
-    int x_ntask[2] = {0, 0};
-    size_t x_lds[2] = {0, 0};
-    int x_rm[2] = {0, 0};   // row mode of each launch
+    std::vector<chd::BoxDesc> xbox[3];
+    int x_ntask[3] = {0, 0, 0};
+    size_t x_lds[3] = {0, 0, 0};
+    int x_rm[3] = {0, 0, 0};    // row mode of each launch
+    int x_nth[3] = {0, 0, 0};   // its threads per work-group
+    std::vector<int> box_th, box_rm;   // each box's work-group size and row mode
     int tw_max = 0;
     int x_rows = 0, x_threads = 256, zc = 1, mi = 1, lanes = 32, yz_threads = 256, seg_cap = 0;
     int ntask[3] = {0, 0, 0};
@@ -380,14 +383,14 @@ inline ch_status plan_dt(Plan& P, double dt)
     };
     const int xwaves = row_ok ? (sT == 4 ? XROW_WAVES_F32 : XROW_WAVES_F64)
                               : (sT == 4 ? X_WAVES_F32 : X_WAVES_F64);
-    auto xbudget_for = [&](int R) {
-        const int threads = threads_for(R);
+    auto xbudget_th = [&](int threads) {
         const int per_simd = (threads / 64 + 3) / 4;   // waves of one group per SIMD
         const int groups = std::max(1, xwaves / std::max(1, per_simd));
         // measured on gfx950: five groups of the single-precision kernel
         // share a CU only with about 2 KB of LDS headroom each
         return LDS_HARD / (size_t)groups - (groups >= 5 ? 2048 : 0);
     };
+    auto xbudget_for = [&](int R) { return xbudget_th(threads_for(R)); };
     int R = P.e25 ? 1 : P.opt.x_rows;   // the explicit mode reads rows y -+ 1 as halo
     if (R == 0) {
         // about 256 threads per work-group: one row of a long line, several
@@ -401,15 +404,67 @@ inline ch_status plan_dt(Plan& P, double dt)
     if (P.x_threads > X_MAX_THREADS) return P.fail(CH_EINVAL, "x_rows too large for the x extent");
     P.xrow = row_ok;
     P.xrow_multi = false;
-    auto rows_of = [&](int b) {
-        return row_ok ? rows_row(b, P.x_threads) : std::min(R, P.boxes[b].n[1]);
+    // Rows per task of each box and the threads of its work-group.  One size
+    // for all by default; for the automatic plan of a batch, each box takes
+    // 192 or 256 threads, whichever leaves fewer of them idle (more rows on
+    // a tie), and boxes of one row mode share a launch of the largest size
+    // among them (a 128-cell line: two rows of 256 instead of one of 192).
+    std::vector<int> brows(P.nbox), bth(P.nbox, P.x_threads), bmode(P.nbox, chd::XR_ONE);
+    auto mode_of = [&](int b, int r) {
+        return r == 1 ? chd::XR_ONE : P.boxes[b].n[0] % 64 == 0 ? chd::XR_WAVE : chd::XR_THREAD;
     };
+    for (int b = 0; b < P.nbox; ++b) {
+        brows[b] = row_ok ? rows_row(b, P.x_threads) : std::min(R, P.boxes[b].n[1]);
+        bmode[b] = row_ok ? mode_of(b, brows[b]) : chd::XR_ONE;
+    }
+    if (row_ok && P.opt.x_rows == 0 && P.nbox > 1) {
+        int gth[3] = {0, 0, 0};
+        for (int b = 0; b < P.nbox; ++b) {
+            const int nx = P.boxes[b].n[0];
+            int T = (nx + 63) / 64 * 64;
+            if (nx <= 256) {
+                double best = -1.0;
+                for (int c : {192, 256}) {
+                    if (nx > c) continue;
+                    const double use = (double)(rows_row(b, c) * nx) / c;
+                    if (use >= best - 1e-12) {
+                        best = use;
+                        T = c;
+                    }
+                }
+            }
+            bth[b] = T;
+            bmode[b] = mode_of(b, rows_row(b, T));
+            gth[bmode[b]] = std::max(gth[bmode[b]], bmode[b] == chd::XR_ONE ? (nx + 63) / 64 * 64 : T);
+        }
+        P.x_threads = 0;
+        for (int b = 0; b < P.nbox; ++b) {
+            bth[b] = gth[bmode[b]];
+            // a box of several rows keeps several with its launch's size
+            brows[b] = bmode[b] == chd::XR_ONE ? 1 : rows_row(b, bth[b]);
+            P.x_threads = std::max(P.x_threads, bth[b]);
+        }
+    }
+    auto rows_of = [&](int b) { return brows[b]; };
     for (int b = 0; b < P.nbox && row_ok; ++b) P.xrow_multi = P.xrow_multi || rows_of(b) > 1;
+    // LDS of box b's task at zc planes, and whether every box's fits the
+    // groups per CU that its work-group size allows
+    auto blds = [&](int b, int zc) {
+        return row_ok ? chd::x_row_layout(P.boxes[b].n[0], rows_of(b),
+                                          std::min(zc, P.boxes[b].n[2]), P.tw_max, (int)sT,
+                                          (int)sA).total
+                      : chd::x_layout(nxm, R, zc, P.tw_max, (int)sT, (int)sA, P.e25).total;
+    };
+    auto lds_fits = [&](int zc, bool hard) {
+        for (int b = 0; b < P.nbox; ++b)
+            if (blds(b, zc) > (hard ? LDS_HARD : xbudget_th(bth[b]))) return false;
+        return true;
+    };
     // planes per task: every line of a task needs its chunks' threads
     int zlim = 64;
     // (a box takes min(z_chunk, nz) planes, so one whose nz fits sets no limit)
     for (int b = 0; b < P.nbox && !P.e25; ++b) {
-        const int lim = P.x_threads / (rows_of(b) * nch_x(P.boxes[b].n[0]));
+        const int lim = bth[b] / (rows_of(b) * nch_x(P.boxes[b].n[0]));
         if (P.boxes[b].n[2] > lim) zlim = std::min(zlim, lim);
     }
     int zc = P.opt.z_chunk;
@@ -419,14 +474,18 @@ inline ch_status plan_dt(Plan& P, double dt)
         const int64_t rows_total = cells / std::max(1, nxm);
         zc = (int)std::max<int64_t>(1, std::min<int64_t>(16, rows_total / R / 2048));
         zc = std::min(zc, zlim);
-        const size_t xbudget = xbudget_for(R);
-        while (zc > 1 && xlds(R, zc) > xbudget) --zc;
+        while (zc > 1 && !lds_fits(zc, false)) --zc;
     }
     if (zc > zlim) return P.fail(CH_EINVAL, "z_chunk too large for this x extent");
-    if (xlds(R, zc) > LDS_HARD) return P.fail(CH_EUNSUPPORTED, "x tile too large for LDS");
+    if (!lds_fits(zc, true)) return P.fail(CH_EUNSUPPORTED, "x tile too large for LDS");
     P.zc = zc;
-    for (int b = 0; b < P.nbox; ++b) P.boxes[b].x_rows = rows_of(b);
-    P.lds[0] = xlds(R, zc);
+    P.lds[0] = 0;
+    for (int b = 0; b < P.nbox; ++b) {
+        P.boxes[b].x_rows = rows_of(b);
+        P.lds[0] = std::max(P.lds[0], blds(b, zc));
+    }
+    P.box_th = bth;
+    P.box_rm = bmode;
     }   // !P.xseg
     // ---- y/z passes: lanes of 128 bytes, whole lines when they fit
     P.lanes = (int)(128 / sA);
@@ -467,39 +526,46 @@ inline ch_status plan_dt(Plan& P, double dt)
         }
     }
     for (int p = 0; p < 3; ++p) P.ntask[p] = (int)t0[p];
-    // the row mode of an x launch of the row program over boxes bs: several
-    // rows of whole waves when every box with several rows per task has a
-    // multiple of 64 cells in x (then no wave holds cells of two rows)
-    auto row_mode = [&](const std::vector<chd::BoxDesc>& bs) {
-        bool multi = false, wave = true;
-        for (const chd::BoxDesc& d : bs)
-            if (d.x_rows > 1) {
-                multi = true;
-                wave = wave && d.n[0] % 64 == 0;
-            }
-        return !multi ? chd::XR_ONE : wave ? chd::XR_WAVE : chd::XR_THREAD;
-    };
-    P.xrm = P.xrow ? row_mode(P.boxes) : chd::XR_ONE;
+    // the row program's x launches: one per row mode among the boxes, each
+    // with the largest work-group size of its boxes
     P.nxl = 1;
-    if (P.xrow && P.xrow_multi) {
-        for (int g = 0; g < 2; ++g) {
-            P.xbox[g].clear();
-            P.x_ntask[g] = 0;
-            P.x_lds[g] = 0;
-        }
-        for (int b = 0; b < P.nbox; ++b)
-            P.xbox[P.boxes[b].x_rows == 1 ? 0 : 1].push_back(P.boxes[b]);
-        if (!P.xbox[0].empty() && !P.xbox[1].empty()) {
-            P.nxl = 2;
-            for (int g = 0; g < 2; ++g)
-                for (chd::BoxDesc& d : P.xbox[g]) {
-                    d.task0[0] = P.x_ntask[g];
-                    P.x_ntask[g] += d.ntask[0];
-                    P.x_lds[g] = std::max(P.x_lds[g],
-                                          chd::x_row_layout(d.n[0], d.x_rows, d.zc, P.tw_max,
-                                                            (int)sT, (int)sA).total);
-                }
-            for (int g = 0; g < 2; ++g) P.x_rm[g] = row_mode(P.xbox[g]);
+    P.xrm = chd::XR_ONE;
+    if (P.xrow) {
+        int present[3] = {0, 0, 0};
+        for (int b = 0; b < P.nbox; ++b) present[P.box_rm[b]] = 1;
+        P.xrm = present[chd::XR_THREAD] ? chd::XR_THREAD
+              : present[chd::XR_WAVE] ? chd::XR_WAVE : chd::XR_ONE;
+        const int modes = present[0] + present[1] + present[2];
+        if (modes > 1 || P.nbox > 1) {
+            int g = 0, gi[3] = {-1, -1, -1};
+            for (int m = 0; m < 3; ++m)
+                if (present[m]) gi[m] = g++;
+            for (int k = 0; k < 3; ++k) {
+                P.xbox[k].clear();
+                P.x_ntask[k] = 0;
+                P.x_lds[k] = 0;
+                P.x_nth[k] = 0;
+                P.x_rm[k] = chd::XR_ONE;
+            }
+            for (int m = 0; m < 3; ++m)
+                if (gi[m] >= 0) P.x_rm[gi[m]] = m;
+            for (int b = 0; b < P.nbox; ++b) {
+                const int k = gi[P.box_rm[b]];
+                chd::BoxDesc d = P.boxes[b];
+                d.task0[0] = P.x_ntask[k];
+                P.x_ntask[k] += d.ntask[0];
+                P.x_lds[k] = std::max(P.x_lds[k], chd::x_row_layout(d.n[0], d.x_rows, d.zc,
+                                                                    P.tw_max, (int)sT,
+                                                                    (int)sA).total);
+                P.x_nth[k] = std::max(P.x_nth[k], P.box_th[b]);
+                P.xbox[k].push_back(d);
+            }
+            // one launch: the whole table (its tasks already numbered from 0)
+            if (g > 1) P.nxl = g;
+            else {
+                P.xrm = P.x_rm[0];
+                P.x_threads = P.x_nth[0];
+            }
         }
     }
     if (P.xseg) {

@@ -14,13 +14,13 @@
 //   IN_DIR/{C,u,v,w}.bin: packed float64 arrays (the library's layout)
 //   OUT_DIR/C.bin: packed float64 result; OUT_DIR/mass.txt: per-box mass;
 //   OUT_DIR/plan.txt: x_rows seg_cap chains tw_max acc64 ntask0..2 lds0..2 z_chunk xrow
-//           xrm0 xrm1
+//           nxl xrm0 xrm1 xrm2
 //           (xrow: 0 general x program, 1 row program, 2 row program with
 //           several rows in some task, 3 segmented program, 4 row program in
-//           two launches: one-row boxes and several-row boxes; xrm0, xrm1: the
-//           row mode of the row program's launch, or of its two launches:
-//           0 one row, 1 several rows with per-thread offsets, 2 several rows
-//           of whole waves)
+//           one launch per row mode; nxl: the row program's launches; xrm0 ..
+//           xrm2: the row mode of each (of the single launch in xrm0): 0 one
+//           row, 1 several rows with per-thread offsets, 2 several rows of
+//           whole waves)
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -92,16 +92,19 @@ static void run_xrow(chp::Plan& P, int k, T* C, T* E, T* qa, const T* u, const T
     const chd::PassArgs pa = chp::pass_args(P, k, 0);
     chd::CpuExec ex{P.x_threads};
     std::vector<chd::XRowState<T, A>> st(ex.nth);
-    if (P.nxl == 2) {
-        // two launches: the one-row boxes, then those with several rows per task
-        for (int g = 0; g < 2; ++g) {
+    if (P.nxl > 1) {
+        // one launch per row mode, each with its own work-group size
+        for (int g = 0; g < P.nxl; ++g) {
             const chd::BoxDesc* gb = P.xbox[g].data();
             const int nb = (int)P.xbox[g].size();
+            chd::CpuExec exg{P.x_nth[g]};
+            std::vector<chd::XRowState<T, A>> stg(exg.nth);
             for (int task = 0; task < P.x_ntask[g]; ++task) {
                 unsigned char* lds = (unsigned char*)malloc(P.x_lds[g]);
                 memset(lds, 0xff, P.x_lds[g]);
                 const int b = chd::find_box(gb, nb, chd::PASS_X, task);
-                xrow_task<T, A>(P.x_rm[g], ex, st.data(), gb[b], pa, task, C, u, v, w, E, qa, lds);
+                xrow_task<T, A>(P.x_rm[g], exg, stg.data(), gb[b], pa, task, C, u, v, w, E, qa,
+                                lds);
                 free(lds);
             }
         }
@@ -236,11 +239,12 @@ static int go(chp::Plan& P, const std::string& in, const std::string& out, int n
     for (double x : m) fprintf(f, "%.17g\n", x);
     fclose(f);
     f = fopen((out + "/plan.txt").c_str(), "w");
-    fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu %d %d %d %d\n", P.x_rows, P.seg_cap,
+    fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu %d %d %d %d %d %d\n", P.x_rows, P.seg_cap,
             P.yz_threads, P.tw_max, P.acc64 ? 1 : 0, P.ntask[0], P.ntask[1], P.ntask[2], P.lds[0],
             P.lds[1], P.lds[2], P.zc,
-            P.xseg ? 3 : P.nxl == 2 ? 4 : P.xrow ? (P.xrow_multi ? 2 : 1) : 0,
-            P.nxl == 2 ? P.x_rm[0] : P.xrm, P.nxl == 2 ? P.x_rm[1] : P.xrm);
+            P.xseg ? 3 : P.nxl > 1 ? 4 : P.xrow ? (P.xrow_multi ? 2 : 1) : 0, P.nxl,
+            P.nxl > 1 ? P.x_rm[0] : P.xrm, P.nxl > 1 ? P.x_rm[1] : -1,
+            P.nxl > 2 ? P.x_rm[2] : -1);
     fclose(f);
     free(C); free(E); free(E2); free(qa); free(qb); free(u); free(v); free(w);
     return 0;

@@ -226,15 +226,16 @@ def test_row_program_in_a_batch(x_rows):
 @pytest.mark.parametrize("boxes,x_rows,xrm", [
     # rows of whole waves: 3 rows of 64 per task, the last task one row (two
     # idle waves); 2 rows of 128 with y and z walls, the last task one row
-    ([((12, 10, 64), (0, 0, 0))], 3, [2, 2]),
-    ([((9, 9, 128), (0, 1, 1))], 2, [2, 2]),
+    ([((12, 10, 64), (0, 0, 0))], 3, [2]),
+    ([((9, 9, 128), (0, 1, 1))], 2, [2]),
     # a batch: the 256-wide box one row per task, the 64- and 128-wide ones
-    # several rows of whole waves (two launches)
+    # several rows of whole waves in groups of 256 threads (two launches)
     ([((8, 8, 256), (0, 0, 0)), ((10, 9, 64), (0, 0, 1)), ((8, 11, 128), (0, 0, 0))], 0,
      [0, 2]),
-    # a 48-wide box among them: per-thread row offsets in the second launch
+    # a 48-wide box among them: four rows in groups of 192 threads with
+    # per-thread row offsets, a launch of its own (three launches)
     ([((8, 8, 256), (0, 0, 0)), ((10, 9, 48), (0, 0, 0)), ((8, 11, 128), (0, 0, 0))], 0,
-     [0, 1]),
+     [0, 1, 2]),
 ])
 def test_wave_rows(boxes, x_rows, xrm):
     """Several rows per task whose rows are whole waves (the row offsets
