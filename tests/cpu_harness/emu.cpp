@@ -14,13 +14,13 @@
 //   IN_DIR/{C,u,v,w}.bin: packed float64 arrays (the library's layout)
 //   OUT_DIR/C.bin: packed float64 result; OUT_DIR/mass.txt: per-box mass;
 //   OUT_DIR/plan.txt: x_rows seg_cap chains tw_max acc64 ntask0..2 lds0..2 z_chunk xrow
-//           nxl xrm0 xrm1 xrm2
+//           nxl xrm0 xrm1 xrm2 nth0 nth1 nth2
 //           (xrow: 0 general x program, 1 row program, 2 row program with
 //           several rows in some task, 3 segmented program, 4 row program in
 //           one launch per row mode; nxl: the row program's launches; xrm0 ..
 //           xrm2: the row mode of each (of the single launch in xrm0): 0 one
 //           row, 1 several rows with per-thread offsets, 2 several rows of
-//           whole waves)
+//           whole waves; nth0 .. nth2: the threads per work-group of each)
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -239,12 +239,14 @@ static int go(chp::Plan& P, const std::string& in, const std::string& out, int n
     for (double x : m) fprintf(f, "%.17g\n", x);
     fclose(f);
     f = fopen((out + "/plan.txt").c_str(), "w");
-    fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu %d %d %d %d %d %d\n", P.x_rows, P.seg_cap,
+    fprintf(f, "%d %d %d %d %d %d %d %d %zu %zu %zu %d %d %d %d %d %d %d %d %d\n", P.x_rows,
+            P.seg_cap,
             P.yz_threads, P.tw_max, P.acc64 ? 1 : 0, P.ntask[0], P.ntask[1], P.ntask[2], P.lds[0],
             P.lds[1], P.lds[2], P.zc,
             P.xseg ? 3 : P.nxl > 1 ? 4 : P.xrow ? (P.xrow_multi ? 2 : 1) : 0, P.nxl,
             P.nxl > 1 ? P.x_rm[0] : P.xrm, P.nxl > 1 ? P.x_rm[1] : -1,
-            P.nxl > 2 ? P.x_rm[2] : -1);
+            P.nxl > 2 ? P.x_rm[2] : -1, P.nxl > 1 ? P.x_nth[0] : P.x_threads,
+            P.nxl > 1 ? P.x_nth[1] : -1, P.nxl > 2 ? P.x_nth[2] : -1);
     fclose(f);
     free(C); free(E); free(E2); free(qa); free(qb); free(u); free(v); free(w);
     return 0;

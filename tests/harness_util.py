@@ -54,7 +54,8 @@ def run_emu(boxes, dt, nsteps, prec=0, kappa=4.0, eps=1e-6, solve=0, x_rows=0, s
         plan = dict(x_rows=int(p[0]), seg=int(p[1]), yz_threads=int(p[2]), tw_max=int(p[3]),
                     acc64=int(p[4]), ntask=[int(x) for x in p[5:8]],
                     lds=[int(x) for x in p[8:11]], z_chunk=int(p[11]), xrow=int(p[12]), nxl=int(p[13]),
-                    xrm=[int(x) for x in p[14:17] if int(x) >= 0])
+                    xrm=[int(x) for x in p[14:17] if int(x) >= 0],
+                    nth=[int(x) for x in p[17:20] if int(x) >= 0])
     out, o = [], 0
     for b in boxes:
         n = b["C"].size

@@ -252,6 +252,25 @@ def test_wave_rows(boxes, x_rows, xrm):
             assert _rel(a, _oracle(b, dt, 2)) < tol
 
 
+def test_launches_per_row_mode_with_their_own_group_size():
+    """An ensemble-like batch (x extents 48 .. 192) in the automatic plan:
+    one launch per row mode, each box in 192 or 256 threads, whichever
+    leaves fewer idle: 160- and 192-cell boxes one row in 192 threads, 48-
+    and 96-cell boxes 4 and 2 rows in 192 (per-thread row offsets), 64- and
+    128-cell boxes rows of whole waves in 256.  The bits are the general
+    program's."""
+    widths = (48, 64, 96, 128, 160, 192)
+    bs = [_box((8, 9, nx), seed=80 + i, amp=1.5, drops=False) for i, nx in enumerate(widths)]
+    dt = 2e-4
+    got, _, plan = run_emu(bs, dt, 1, prec=0)
+    assert plan["xrow"] == 4 and plan["nxl"] == 3
+    assert plan["xrm"] == [0, 1, 2] and plan["nth"] == [192, 192, 256]
+    gen, _, _ = run_emu(bs, dt, 1, prec=0, x_general=1)
+    for a, g, b in zip(got, gen, bs):
+        assert np.array_equal(a, g)
+        assert _rel(a, _oracle(b, dt, 1)) < 1e-12
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_launch_plan_does_not_change_the_bits(prec):
     """Every face flux is formed from the same differences whatever the tile:
