@@ -22,6 +22,10 @@ MUTATIONS = [
      "double s0 = 13.0 / 12.0 * (a - 2.0 * b + c)", "double s0 = 12.0 / 12.0 * (a - 2.0 * b + c)"),
     ("weno-linear-weight", "ch_oracle.c",
      "double w1 = 0.6 /", "double w1 = 0.5 /"),
+    ("weno-weight-power", "ch_oracle.c",
+     "double w2 = 0.3 / ((eps + s2) * (eps + s2));", "double w2 = 0.3 / (eps + s2);"),
+    ("weno-derivative-term", "ch_oracle.c",
+     "+ 0.25 * (b - d) * (b - d);", "+ 0.5 * (b - d) * (b - d);"),
     ("weno-candidate", "ch_oracle.c",
      "double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;", "double q1 = (-b + 5.0 * c + 2.0 * d) / 6.5;"),
     ("upwind-side", "ch_oracle.c",

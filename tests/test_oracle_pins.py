@@ -92,6 +92,28 @@ def test_weno5_essentially_non_oscillatory_at_a_jump():
     assert abs(oracle.weno5(1, 1, 1, 1, 0) - 1) < 1e-10
 
 
+def test_weno5_nonlinear_weights_worked_examples():
+    """Non-smooth data, worked by hand in exact fractions from the Jiang-Shu
+    definitions (smoothness indicators of each three-point stencil, weights
+    d_k / (eps + beta_k)^2 with d = 1/10, 6/10, 3/10), at an eps large
+    enough for the weights to matter.
+
+    (0, 0, 0, 0, 1): beta = 0, 0, 13/12 + 1/4 = 4/3; candidates 0, 0, -1/6.
+      eps = 1:   alpha = 1/10, 6/10, (3/10)/(7/3)^2 = 27/490; sum 37/49;
+                 value = -(27/490)/(37/49)/6 = -9/740.
+      eps = 1/2: alpha = 2/5, 12/5, (3/10)/(11/6)^2 = 54/605; sum 1748/605;
+                 value = -(54/1748)/6 = -9/1748.
+    (0, 1, 0, 0, 0): beta = 13/12 * 4 + 16/4 = 25/3, 13/12 + 1/4 = 4/3, 0;
+      candidates -7/6, -1/6, 0.
+      eps = 1:   alpha = (1/10)(3/28)^2 = 9/7840, (6/10)(3/7)^2 = 864/7840,
+                 3/10 = 2352/7840; value = -(63/6 + 864/6)/3225 = -927/19350.
+    """
+    for data, eps, num, den in (((0, 0, 0, 0, 1), 1.0, -9, 740),
+                                ((0, 0, 0, 0, 1), 0.5, -9, 1748),
+                                ((0, 1, 0, 0, 0), 1.0, -927, 19350)):
+        assert abs(oracle.weno5(*data, eps=eps) - num / den) < 1e-14, (data, eps)
+
+
 def test_weno5_constant_and_affine_covariance():
     for _ in range(10):
         d = RNG.normal(size=5)
