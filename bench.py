@@ -32,10 +32,16 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
 VALU_PEAK_TFLOPS = 78.6
 # MI355X's published FP32 vector peak (packed FP32 math)
 VALU_PEAK_PUBLISHED_FP32_TFLOPS = 157.3
+# Vector instruction issue: a SIMD takes one wave64 VALU instruction every 4
+# cycles (16 lanes per cycle): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# lane-instructions per second, whatever the instruction.
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 METRIC = ("CH grid-point updates/s (Gpts/s) FP32 & batched vs FP64 at stated error; "
           "%HBM peak")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_x_256cube_fp32_traffic.md")
 TRAFFIC_FILE_LARGE = os.path.join(ROOT, "profiles", "k_pass_x_1536cube_fp32_traffic.md")
+SQ_FILE = os.path.join(ROOT, "profiles", "k_passes_256cube_fp32_sq_counters.md")
+SQ_FILE_LARGE = os.path.join(ROOT, "profiles", "k_passes_1536cube_fp32_sq_counters.md")
 X_SOURCES = ("ch_device.h", "ch_kernels.hip", "ch_plan.h")
 DROPS_DEF = ("face-connected cells with C >= 1/2 (periodic axes wrap, walls do not connect), "
              "V = h^3 cells, (4 pi/3)(D/2)^3 = V, H = box height")
@@ -80,20 +86,39 @@ def x_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path=None):
-    """HBM bytes per x-pass launch from a committed counter summary (the
-    256^3 one unless `path` names another), if it was taken on the current
-    kernel sources; otherwise None."""
-    path = path or TRAFFIC_FILE
+def profile_value(path, key):
+    """The number on the `key:` line of a committed counter summary, if the
+    summary was taken on the current kernel sources; otherwise None."""
     try:
         text = open(path).read()
     except OSError:
         return None
     src = re.search(r"^source-hash:\s*(\w+)", text, re.M)
-    val = re.search(r"^traffic-bytes-per-launch:\s*([0-9.eE+]+)", text, re.M)
+    val = re.search(r"^" + re.escape(key) + r":\s*([0-9.eE+]+)", text, re.M)
     if not src or not val or src.group(1) != x_source_hash():
         return None
     return float(val.group(1))
+
+
+def measured_traffic(path=None):
+    """HBM bytes per x-pass launch from a committed counter summary (the
+    256^3 one unless `path` names another), or None."""
+    return profile_value(path or TRAFFIC_FILE, "traffic-bytes-per-launch")
+
+
+def issue_view(avg_us, path=None):
+    """The x pass against vector instruction issue: its VALU lane-instructions
+    per launch (counted, from a committed summary for the current sources)
+    over its average launch time, as a fraction of VALU_ISSUE_PEAK; None
+    without a matching summary."""
+    n = profile_value(path or SQ_FILE, "x-pass-valu-lane-instructions-per-launch")
+    if n is None:
+        return None
+    rate = n / (avg_us * 1e-6)
+    return {"valu_lane_instructions_per_launch": n,
+            "achieved_lane_instructions_per_s": round(rate / 1e12, 3),
+            "peak_lane_instructions_per_s": round(VALU_ISSUE_PEAK / 1e12, 3),
+            "unit": "10^12 lane-instructions/s", "frac": round(rate / VALU_ISSUE_PEAK, 4)}
 
 
 def x_roofline(avg_us, points, es, traffic=None, kernel="k_pass_x"):
@@ -486,7 +511,8 @@ def bench_large(args, stream):
                      "kernels_avg_us": {k: round(1e3 * v[0] / max(1, v[1]), 1)
                                         for k, v in kern.items()},
                      "hbm_frac_step_model": step_hbm_frac(pts, 4, ms / args.large_steps)},
-            "roofline": x_roofline(x_us, pts, 4, measured_traffic(TRAFFIC_FILE_LARGE)),
+            "roofline": dict(x_roofline(x_us, pts, 4, measured_traffic(TRAFFIC_FILE_LARGE)),
+                             issue_view=issue_view(x_us, SQ_FILE_LARGE)),
             "plan": cfg, "autotune": tune}
 
 
@@ -833,6 +859,8 @@ def main():
                      "frac_published": round(achieved / VALU_PEAK_PUBLISHED_FP32_TFLOPS, 4),
                      "peak_nonpacked_tflops": VALU_PEAK_TFLOPS,
                      "frac_nonpacked": round(achieved / VALU_PEAK_TFLOPS, 4)},
+        # and against vector instruction issue, the limit it runs at
+        "issue_view": issue_view(x_avg_s * 1e6),
         "window": f"{args.profile_steps} profiled steps, HIP events per launch"})
 
     line = {

@@ -1,6 +1,6 @@
 """Host logic of bench.py (no GPU): the one-GPU refusal, the per-point
-figures of the roofline, and the gating of the counter-measured traffic on
-the kernel sources it was taken on."""
+figures of the roofline, and the gating of the counter-measured traffic and
+instruction counts on the kernel sources they were taken on."""
 import os
 import re
 import subprocess
@@ -45,6 +45,28 @@ def test_traffic_is_reported_only_for_the_sources_it_was_taken_on(tmp_path, monk
     assert bench.measured_traffic() is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.md"))
     assert bench.measured_traffic() is None
+
+
+def test_issue_rate_from_the_counted_instructions(tmp_path):
+    # one wave64 VALU instruction per SIMD every 4 cycles: 16 lanes per cycle
+    assert bench.VALU_ISSUE_PEAK == pytest.approx(256 * 4 * 16 * 2.4e9)
+    text = open(bench.SQ_FILE).read()
+    recorded = re.search(r"^source-hash:\s*(\w+)", text, re.M).group(1)
+    n = float(re.search(r"^x-pass-valu-lane-instructions-per-launch:\s*(\S+)", text,
+                        re.M).group(1))
+    # the count is the table's SQ_INSTS_VALU of the x pass times 64 lanes
+    waves = float(re.search(r"^\| SQ_INSTS_VALU \| (\S+) \|", text, re.M).group(1))
+    assert n == pytest.approx(64 * waves, rel=1e-3)
+    v = bench.issue_view(100.0)
+    if recorded != bench.x_source_hash():
+        assert v is None
+    else:
+        assert v["valu_lane_instructions_per_launch"] == n
+        assert v["frac"] == pytest.approx(n / 1e-4 / bench.VALU_ISSUE_PEAK, rel=1e-3)
+    other = tmp_path / "s.md"
+    other.write_text(text.replace(recorded, "0" * 16))
+    assert bench.issue_view(100.0, str(other)) is None
+    assert bench.issue_view(100.0, str(tmp_path / "missing.md")) is None
 
 
 def test_roofline_and_step_fractions():
