@@ -7,10 +7,11 @@ resident in HBM before the timed region starts.
 
 A step is one full RK3 step (3 substages x {x pass, y solve, z solve}).
 `value` is the FP32 throughput in grid-point updates per second (Gpts/s);
-the FP64 throughput, the FP32-vs-FP64 error after warmup + timed steps, the
-roofline of the dominant kernel (the x pass) and the FP64 CPU oracle's
-throughput on a bounded sample of the same workload are reported on the
-same JSON line.
+the FP64 throughput, the FP32-vs-FP64 error after --acc-steps steps (1000
+by default, whatever --steps is), the roofline of the dominant kernel (the
+x pass, against HBM and against vector instruction issue) and the FP64 CPU
+oracle's throughput on a bounded sample of the same workload are reported
+on the same JSON line, with the other workloads' lines.
 
     python bench.py [--steps K] [--warmup W]
     python bench.py --counter-probe [fp64]    # 2 FP32 (FP64) steps + one 256 MiB device
@@ -36,6 +37,9 @@ VALU_PEAK_PUBLISHED_FP32_TFLOPS = 157.3
 # cycles (16 lanes per cycle): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # lane-instructions per second, whatever the instruction.
 VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
+# A device-to-device copy of 4 GiB or more on MI355X (torch copy, read +
+# write bytes over time): the HBM rate a streaming kernel can reach.
+COPY_GBS = 4900.0
 METRIC = ("CH grid-point updates/s (Gpts/s) FP32 & batched vs FP64 at stated error; "
           "%HBM peak")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_x_256cube_fp32_traffic.md")
@@ -119,6 +123,18 @@ def issue_view(avg_us, path=None):
             "achieved_lane_instructions_per_s": round(rate / 1e12, 3),
             "peak_lane_instructions_per_s": round(VALU_ISSUE_PEAK / 1e12, 3),
             "unit": "10^12 lane-instructions/s", "frac": round(rate / VALU_ISSUE_PEAK, 4)}
+
+
+def limiter(issue, traffic, avg_us):
+    """The limit the x pass runs nearer to: vector instruction issue (the
+    fraction of VALU_ISSUE_PEAK in `issue`) or HBM (its counted traffic per
+    launch at COPY_GBS); None without both counts."""
+    if not issue or not traffic:
+        return None
+    hbm = traffic / (avg_us * 1e-6) / 1e9 / COPY_GBS
+    return {"limiter": "valu_issue" if issue["frac"] >= hbm else "hbm",
+            "issue_frac": issue["frac"], "hbm_frac_of_copy_rate": round(hbm, 4),
+            "copy_gbs": COPY_GBS}
 
 
 def x_roofline(avg_us, points, es, traffic=None, kernel="k_pass_x"):
@@ -512,7 +528,9 @@ def bench_large(args, stream):
                                         for k, v in kern.items()},
                      "hbm_frac_step_model": step_hbm_frac(pts, 4, ms / args.large_steps)},
             "roofline": dict(x_roofline(x_us, pts, 4, measured_traffic(TRAFFIC_FILE_LARGE)),
-                             issue_view=issue_view(x_us, SQ_FILE_LARGE)),
+                             issue_view=issue_view(x_us, SQ_FILE_LARGE),
+                             limit=limiter(issue_view(x_us, SQ_FILE_LARGE),
+                                           measured_traffic(TRAFFIC_FILE_LARGE), x_us)),
             "plan": cfg, "autotune": tune}
 
 
@@ -861,6 +879,7 @@ def main():
                      "frac_nonpacked": round(achieved / VALU_PEAK_TFLOPS, 4)},
         # and against vector instruction issue, the limit it runs at
         "issue_view": issue_view(x_avg_s * 1e6),
+        "limit": limiter(issue_view(x_avg_s * 1e6), traffic, x_avg_s * 1e6),
         "window": f"{args.profile_steps} profiled steps, HIP events per launch"})
 
     line = {

@@ -69,6 +69,18 @@ def test_issue_rate_from_the_counted_instructions(tmp_path):
     assert bench.issue_view(100.0, str(tmp_path / "missing.md")) is None
 
 
+def test_limiter_compares_issue_with_hbm_at_copy_rate():
+    issue = {"frac": 0.9}
+    # 4.9e8 bytes in 100 us: 4.9 TB/s, the copy rate
+    assert bench.limiter(issue, 4.9e8, 100.0)["limiter"] == "hbm"
+    got = bench.limiter(issue, 4.0e8, 100.0)
+    assert got["limiter"] == "valu_issue"
+    assert got["hbm_frac_of_copy_rate"] == pytest.approx(4.0e8 / 1e-4 / 1e9 / bench.COPY_GBS,
+                                                         rel=1e-3)
+    assert bench.limiter(None, 4.0e8, 100.0) is None
+    assert bench.limiter(issue, None, 100.0) is None
+
+
 def test_roofline_and_step_fractions():
     # 16.78 M points at 25.33 B each in 100 us: 4.25 TB/s
     r = bench.x_roofline(100.0, 256 ** 3, 4, traffic=5e8)
